@@ -1,0 +1,188 @@
+"""OSQP's ADMM (Algorithm 1, Section 3) with the direct KKT solve (eq. kkt).
+
+Each iteration, on the Ruiz-scaled problem (Algorithm 2):
+  1. solve  [P̄+σI  Āᵀ; Ā  −R⁻¹] [x̃; ν] = [σx − q̄; z − R⁻¹y]          (eq. kkt)
+  2. z̃ = z + R⁻¹(ν − y)
+  3. x ← αx̃ + (1−α)x
+  4. z ← Π_[l̄,ū](αz̃ + (1−α)z + R⁻¹y)
+  5. y ← y + R(αz̃ + (1−α)z − z_new)
+and stops when the unscaled residuals meet the relative test of Section 3.1.
+
+R is ρ̄I (the choice Section 6.3 makes for the GPU solver) or OSQP's vector
+ρ_i = ρ̄ on inequalities and 10³ρ̄ on equalities (eq. rho_vec); the solution
+does not depend on R. The KKT matrix is factored once and again only when ρ̄
+changes (Section 3.2, 3.4). The sparse LU used for the factorisation is a
+library primitive; no ordering or factorisation is re-implemented here.
+
+Scaled variables (Section 3.3): x̄ = D⁻¹x, ȳ = cE⁻¹y, and z̄ = Ez. (The paper
+prints z̄ = E⁻¹z, which contradicts Ā = EAD and l̄ = El; z̄ = Āx̄ = EAx = Ez is
+the consistent reading.) Unscaled residuals are r_prim = E⁻¹r̄_prim and
+r_dual = c⁻¹D⁻¹r̄_dual.
+
+ρ̄ estimate (Section 3.4 names only "the ratio of primal and dual residual
+norms"): ρ̄·√[(‖r̄_p‖∞ / max(‖Āx̄‖∞, ‖z̄‖∞)) / (‖r̄_d‖∞ / max(‖P̄x̄‖∞, ‖Āᵀȳ‖∞, ‖q̄‖∞))]
+on scaled quantities, clipped to [1e-6, 1e6]. Because every change costs a
+refactorisation, the oracle applies it only when the estimate differs from
+ρ̄ by more than a factor 5, and at most every ``rho_interval`` iterations.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import ruiz as _ruiz
+
+RHO_MIN, RHO_MAX = 1e-6, 1e6
+INF = 1e20
+
+
+@dataclasses.dataclass
+class AdmmResult:
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    obj: float
+    iters: int
+    status: str
+    prim_res: float
+    dual_res: float
+    rho: float
+    rho_updates: int
+    trace: list
+    scaling: tuple
+    factor_time: float = 0.0
+    iter_time: float = 0.0
+
+
+def kkt_matrix(Pb, Ab, sigma, rvec):
+    n = Pb.shape[0]
+    return sp.bmat([[Pb + sigma * sp.identity(n), Ab.T],
+                    [Ab, -sp.diags(1.0 / rvec)]], format="csc")
+
+
+class KKTSolver:
+    """Factor the quasi-definite KKT matrix once; solve many right-hand sides."""
+
+    def __init__(self, Pb, Ab, sigma, rvec):
+        K = kkt_matrix(Pb, Ab, sigma, rvec)
+        self.K = K
+        try:
+            self.lu = spla.splu(K, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                                options=dict(SymmetricMode=True))
+            t = np.ones(K.shape[0])
+            if not np.all(np.isfinite(self.lu.solve(t))):
+                raise RuntimeError
+        except Exception:
+            self.lu = spla.splu(K)
+
+    def solve(self, rhs):
+        sol = self.lu.solve(rhs)
+        # one step of iterative refinement keeps the solve at round-off level
+        return sol - self.lu.solve(self.K @ sol - rhs)
+
+
+def admm_step(kkt, qb, lb, ub, rvec, sigma, alpha, x, z, y):
+    """One iteration of Algorithm 1 on the scaled problem."""
+    n = x.shape[0]
+    sol = kkt.solve(np.concatenate([sigma * x - qb, z - y / rvec]))
+    xt = sol[:n]
+    nu = sol[n:]
+    zt = z + (nu - y) / rvec
+    x_new = alpha * xt + (1.0 - alpha) * x
+    v = alpha * zt + (1.0 - alpha) * z
+    z_new = np.minimum(np.maximum(v + y / rvec, lb), ub)
+    y_new = y + rvec * (v - z_new)
+    return x_new, z_new, y_new
+
+
+def rho_vector(l, u, rho_bar, mode):
+    if mode == "scalar":
+        return np.full(l.shape[0], rho_bar)
+    eq = np.abs(u - l) < 1e-12 * np.maximum(1.0, np.abs(l))
+    return np.where(eq, 1e3 * rho_bar, rho_bar)
+
+
+def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, eps_rel=1e-9,
+          max_iter=20000, scaling_iters=10, r_mode="scalar", adaptive_rho=True, rho_interval=100,
+          check_every=1, record=0, x0=None, z0=None, y0=None) -> AdmmResult:
+    import time
+
+    P_full = sp.csr_matrix(P_full, dtype=np.float64)
+    A = sp.csr_matrix(A, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    l = np.maximum(np.asarray(l, dtype=np.float64), -INF)
+    u = np.minimum(np.asarray(u, dtype=np.float64), INF)
+    n, m = A.shape[1], A.shape[0]
+
+    if scaling_iters > 0:
+        D, E, c, Pb, qb, Ab, _ = _ruiz.ruiz(P_full, q, A, scaling_iters)
+    else:
+        D, E, c, Pb, qb, Ab, _ = _ruiz.no_scaling(P_full, q, A)
+    lb = E * l
+    ub = E * u
+    Abt = Ab.T.tocsr()
+
+    x = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64) / D
+    z = np.zeros(m) if z0 is None else E * np.asarray(z0, dtype=np.float64)
+    y = np.zeros(m) if y0 is None else c * np.asarray(y0, dtype=np.float64) / E
+
+    rho_bar = rho
+    rvec = rho_vector(lb, ub, rho_bar, r_mode)
+    t0 = time.perf_counter()
+    kkt = KKTSolver(Pb, Ab, sigma, rvec)
+    factor_time = time.perf_counter() - t0
+    rho_updates = 0
+    last_update = 0
+    trace = []
+    status = "max_iter_reached"
+    it = 0
+    pr = dr = np.inf
+    t1 = time.perf_counter()
+    for it in range(1, max_iter + 1):
+        x, z, y = admm_step(kkt, qb, lb, ub, rvec, sigma, alpha, x, z, y)
+        if it <= record:
+            trace.append((D * x, z / E, E * y / c))
+        if it % check_every:
+            continue
+        Ax = Ab @ x
+        Px = Pb @ x
+        Aty = Abt @ y
+        rp_s = Ax - z
+        rd_s = Px + qb + Aty
+        # unscaled residuals and normalisers
+        pr = float(np.max(np.abs(rp_s / E))) if m else 0.0
+        dr = float(np.max(np.abs(rd_s / D))) / c
+        nAx = float(np.max(np.abs(Ax / E))) if m else 0.0
+        nz = float(np.max(np.abs(z / E))) if m else 0.0
+        nPx = float(np.max(np.abs(Px / D))) / c
+        nAty = float(np.max(np.abs(Aty / D))) / c
+        nq = float(np.max(np.abs(qb / D))) / c
+        eps_p = eps_abs + eps_rel * max(nAx, nz)
+        eps_d = eps_abs + eps_rel * max(nPx, nAty, nq)
+        if pr <= eps_p and dr <= eps_d:
+            status = "solved"
+            break
+        if adaptive_rho and it - last_update >= rho_interval:
+            num = float(np.max(np.abs(rp_s))) / max(float(np.max(np.abs(Ax))) if m else 0.0,
+                                                     float(np.max(np.abs(z))) if m else 0.0, 1e-10)
+            den = float(np.max(np.abs(rd_s))) / max(float(np.max(np.abs(Px))), float(np.max(np.abs(Aty))),
+                                                     float(np.max(np.abs(qb))), 1e-10)
+            est = float(np.clip(rho_bar * np.sqrt(num / max(den, 1e-300)), RHO_MIN, RHO_MAX))
+            if est > 5.0 * rho_bar or est < rho_bar / 5.0:
+                rho_bar = est
+                rvec = rho_vector(lb, ub, rho_bar, r_mode)
+                t0 = time.perf_counter()
+                kkt = KKTSolver(Pb, Ab, sigma, rvec)
+                factor_time += time.perf_counter() - t0
+                rho_updates += 1
+                last_update = it
+    iter_time = time.perf_counter() - t1
+    xs = D * x
+    ys = E * y / c
+    zs = z / E
+    obj = 0.5 * float(xs @ (P_full @ xs)) + float(q @ xs)
+    return AdmmResult(xs, ys, zs, obj, it, status, pr, dr, rho_bar, rho_updates, trace,
+                      (D, E, c), factor_time, iter_time)

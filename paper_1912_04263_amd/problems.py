@@ -1,0 +1,202 @@
+"""Seeded synthetic QP instances in OSQP form  min ½xᵀPx + qᵀx  s.t.  l ≤ Ax ≤ u.
+
+This module only draws random data and writes the problem classes of the
+paper's benchmark section (Section 7.1: Random, Lasso, Portfolio, SVM) in the
+standard form of Section 2, eq. (qp). It holds none of the solver's arithmetic
+and imports neither the solver binding nor the oracle, so both sides (and the
+tests) can draw identical inputs from it.
+
+Output convention (the OSQP input convention, Section 6.2): P is returned as
+the upper triangle (diagonal included) in CSC, A in CSC, q/l/u as float64
+vectors, ±inf for absent bounds.
+
+Sparsity patterns are i.i.d. Bernoulli(d): the linearised positions of the
+nonzeros are drawn by geometric gap skipping, which realises exactly one
+independent Bernoulli(d) trial per entry at O(nnz) cost.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclasses.dataclass
+class QP:
+    name: str
+    P_triu: sp.csc_matrix      # upper triangle of P incl. diagonal, CSC
+    q: np.ndarray
+    A: sp.csc_matrix           # m×n, CSC
+    l: np.ndarray
+    u: np.ndarray
+    meta: dict
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+    @property
+    def m(self) -> int:
+        return self.A.shape[0]
+
+    def P_full(self) -> sp.csr_matrix:
+        T = self.P_triu.tocsr()
+        return (T + sp.triu(T, k=1).T).tocsr()
+
+
+def _bernoulli_positions(rng, rows: int, cols: int, d: float) -> tuple[np.ndarray, np.ndarray]:
+    """Row/column indices (row-major sorted) of an i.i.d. Bernoulli(d) pattern."""
+    total = rows * cols
+    if d <= 0.0 or total == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    if d >= 1.0:
+        pos = np.arange(total, dtype=np.int64)
+    else:
+        expect = total * d
+        chunks = []
+        last = -1
+        while True:
+            k = int(expect + 6.0 * math.sqrt(expect) + 64) if not chunks else int(0.05 * expect + 1024)
+            gaps = rng.geometric(d, size=k).astype(np.int64)
+            p = last + np.cumsum(gaps)
+            chunks.append(p)
+            last = int(p[-1])
+            if last >= total:
+                break
+        pos = np.concatenate(chunks)
+        pos = pos[pos < total]
+    return pos // cols, pos % cols
+
+
+def sprandn(rng, rows: int, cols: int, d: float, mean=0.0, var=1.0, row_mean=None) -> sp.csr_matrix:
+    """rows×cols CSR with Bernoulli(d) pattern and N(mean, var) values.
+
+    ``row_mean`` (length rows) overrides ``mean`` per row.
+    """
+    r, c = _bernoulli_positions(rng, rows, cols, d)
+    vals = rng.standard_normal(r.size) * math.sqrt(var)
+    if row_mean is not None:
+        vals += np.asarray(row_mean, dtype=np.float64)[r]
+    else:
+        vals += mean
+    indptr = np.zeros(rows + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=rows), out=indptr[1:])
+    return sp.csr_matrix((vals, c.astype(np.int32), indptr), shape=(rows, cols))
+
+
+def _finish(name, P_full, q, A, l, u, meta) -> QP:
+    P_triu = sp.triu(sp.csr_matrix(P_full), format="csc")
+    P_triu.sort_indices()
+    A = sp.csc_matrix(A)
+    A.sort_indices()
+    P_triu.indices = P_triu.indices.astype(np.int32)
+    P_triu.indptr = P_triu.indptr.astype(np.int32)
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int32)
+    meta = dict(meta)
+    meta.update(n=A.shape[1], m=A.shape[0], nnz_P_full=int(sp.csr_matrix(P_full).nnz),
+                nnz_P_triu=int(P_triu.nnz), nnz_A=int(A.nnz))
+    return QP(name, P_triu, np.ascontiguousarray(q, np.float64), A,
+              np.ascontiguousarray(l, np.float64), np.ascontiguousarray(u, np.float64), meta)
+
+
+def random_qp(n: int, m: int, dens_M: float, dens_A: float, seed: int) -> QP:
+    """Random class: P = MMᵀ + 1e-2·I, A Bernoulli, q ~ N(0,1), l = −U[0,1], u = U[0,1]."""
+    rng = np.random.default_rng(seed)
+    M = sprandn(rng, n, n, dens_M)
+    P = (M @ M.T + 1e-2 * sp.identity(n, format="csr")).tocsr()
+    A = sprandn(rng, m, n, dens_A)
+    q = rng.standard_normal(n)
+    l = -rng.random(m)
+    u = rng.random(m)
+    return _finish("random", P, q, A, l, u, dict(seed=seed, dens_M=dens_M, dens_A=dens_A))
+
+
+def lasso_qp(n_feat: int, m_data: int, dens: float, seed: int) -> QP:
+    """Lasso class: min ‖Ad·x − b‖² + λ‖x‖₁ in OSQP form over (x, y, t).
+
+    min yᵀy + λ1ᵀt  s.t.  y = Ad·x − b,  −t ≤ x ≤ t.
+    """
+    rng = np.random.default_rng(seed)
+    Ad = sprandn(rng, m_data, n_feat, dens)
+    v = rng.standard_normal(n_feat) * math.sqrt(1.0 / n_feat)
+    v[rng.choice(n_feat, n_feat // 2, replace=False)] = 0.0
+    b = Ad @ v + rng.standard_normal(m_data)
+    lam = float(np.max(np.abs(Ad.T @ b))) / 5.0
+    n, m = n_feat, m_data
+    In = sp.identity(n, format="csr")
+    Im = sp.identity(m, format="csr")
+    P = sp.block_diag((sp.csr_matrix((n, n)), 2.0 * Im, sp.csr_matrix((n, n))), format="csr")
+    q = np.concatenate([np.zeros(n), np.zeros(m), lam * np.ones(n)])
+    A = sp.bmat([[Ad, -Im, None], [In, None, -In], [In, None, In]], format="csc")
+    inf = np.inf
+    l = np.concatenate([b, -inf * np.ones(n), np.zeros(n)])
+    u = np.concatenate([b, np.zeros(n), inf * np.ones(n)])
+    return _finish("lasso", P, q, A, l, u, dict(seed=seed, n_feat=n_feat, m_data=m_data, dens=dens, lam=lam))
+
+
+def portfolio_qp(n_assets: int, k_factors: int, dens: float, seed: int, gamma: float = 1.0) -> QP:
+    """Portfolio class: min xᵀDx + yᵀy − μᵀx/γ  s.t.  y = Fᵀx, 1ᵀx = 1, x ≥ 0."""
+    rng = np.random.default_rng(seed)
+    F = sprandn(rng, n_assets, k_factors, dens)
+    Dd = rng.random(n_assets) * math.sqrt(k_factors)
+    mu = rng.standard_normal(n_assets)
+    n, k = n_assets, k_factors
+    P = sp.block_diag((sp.diags(2.0 * Dd), 2.0 * sp.identity(k)), format="csr")
+    q = np.concatenate([-mu / gamma, np.zeros(k)])
+    A = sp.bmat([[F.T, -sp.identity(k)],
+                 [sp.csr_matrix(np.ones((1, n))), None],
+                 [sp.identity(n), None]], format="csc")
+    l = np.concatenate([np.zeros(k), [1.0], np.zeros(n)])
+    u = np.concatenate([np.zeros(k), [1.0], np.inf * np.ones(n)])
+    return _finish("portfolio", P, q, A, l, u, dict(seed=seed, n_assets=n, k_factors=k, dens=dens, gamma=gamma))
+
+
+def svm_qp(n_points: int, n_feat: int, dens: float, seed: int, lam: float = 1.0) -> QP:
+    """SVM class: min xᵀx + λ Σ max(0, b_i a_iᵀx + 1) over (x, t).
+
+    min xᵀx + λ1ᵀt  s.t.  t ≥ diag(b)·Ad·x + 1,  t ≥ 0  (the hinge sign as the
+    paper prints it). The first half of the points has label +1 and entries
+    N(+1/n_feat, 1/n_feat), the second half label −1 and N(−1/n_feat, 1/n_feat).
+    """
+    rng = np.random.default_rng(seed)
+    half = n_points // 2
+    b = np.concatenate([np.ones(half), -np.ones(n_points - half)])
+    Ad = sprandn(rng, n_points, n_feat, dens, var=1.0 / n_feat, row_mean=b / n_feat)
+    n, N = n_feat, n_points
+    P = sp.block_diag((2.0 * sp.identity(n), sp.csr_matrix((N, N))), format="csr")
+    q = np.concatenate([np.zeros(n), lam * np.ones(N)])
+    A = sp.bmat([[sp.diags(b) @ Ad, -sp.identity(N)],
+                 [None, sp.identity(N)]], format="csc")
+    l = np.concatenate([-np.inf * np.ones(N), np.zeros(N)])
+    u = np.concatenate([-np.ones(N), np.inf * np.ones(N)])
+    return _finish("svm", P, q, A, l, u, dict(seed=seed, n_points=N, n_feat=n, dens=dens, lam=lam))
+
+
+# The five benchmark workloads and their scaled-down parity variants.
+# Instance j of workload i uses seed 1000·i + j.
+WORKLOADS = {
+    "random_c0": lambda j=0: random_qp(200, 400, 0.15, 0.15, 1000 * 0 + j),
+    "lasso_c1": lambda j=0: lasso_qp(10_000, 100_000, 0.01, 1000 * 1 + j),
+    "random_c2": lambda j=0: random_qp(100_000, 1_000_000, 4.47e-5, 2e-4, 1000 * 2 + j),
+    "portfolio_c3": lambda j=0: portfolio_qp(100_000, 1_000, 0.5, 1000 * 3 + j),
+    "svm_c4": lambda j=0: svm_qp(1_000_000, 10_000, 0.01, 1000 * 4 + j),
+}
+
+# Scaled-down variants with the same generators and per-row densities, sized so
+# that the oracle's direct solve finishes in seconds.
+SMALL = {
+    "random_small": lambda j=0: random_qp(300, 600, 0.10, 0.10, 1000 * 5 + j),
+    "lasso_small": lambda j=0: lasso_qp(200, 2_000, 0.05, 1000 * 6 + j),
+    "random2_small": lambda j=0: random_qp(1_000, 10_000, 4.4e-3, 2e-2, 1000 * 7 + j),
+    "portfolio_small": lambda j=0: portfolio_qp(2_000, 20, 0.5, 1000 * 8 + j),
+    "svm_small": lambda j=0: svm_qp(4_000, 100, 0.1, 1000 * 9 + j),
+}
+
+
+def make(name: str, j: int = 0) -> QP:
+    if name in WORKLOADS:
+        return WORKLOADS[name](j)
+    return SMALL[name](j)

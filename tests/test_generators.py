@@ -1,0 +1,58 @@
+"""Seeded input generators: shapes, densities, value distributions, reproducibility."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1912_04263_amd import problems as pr
+
+
+def test_bernoulli_pattern_density_and_moments():
+    rng = np.random.default_rng(0)
+    M = pr.sprandn(rng, 2000, 500, 0.02)
+    assert M.nnz == pytest.approx(2000 * 500 * 0.02, rel=0.03)
+    assert abs(M.data.mean()) < 0.03 and M.data.std() == pytest.approx(1.0, rel=0.03)
+    M.sum_duplicates()
+    assert M.has_sorted_indices
+    counts = np.diff(M.indptr)  # Binomial(500, 0.02) per row
+    assert counts.mean() == pytest.approx(10.0, rel=0.05)
+    assert counts.var() == pytest.approx(500 * 0.02 * 0.98, rel=0.15)
+
+
+def test_reproducible_and_seed_dependent():
+    a, b, c = pr.make("random_c0", 0), pr.make("random_c0", 0), pr.make("random_c0", 1)
+    assert (a.A != b.A).nnz == 0 and np.array_equal(a.q, b.q)
+    assert not np.array_equal(a.q, c.q)
+
+
+@pytest.mark.parametrize("name", list(pr.SMALL) + ["random_c0"])
+def test_problem_structure(name):
+    p = pr.make(name)
+    assert p.P_triu.shape == (p.n, p.n) and p.A.shape == (p.m, p.n)
+    T = p.P_triu.tocoo()
+    assert np.all(T.row <= T.col)
+    assert np.all(p.l <= p.u)
+    P = p.P_full().toarray() if p.n <= 5000 else None
+    if P is not None:
+        assert np.allclose(P, P.T)
+        assert np.linalg.eigvalsh(P).min() > -1e-9
+    assert p.P_triu.indices.dtype == np.int32 and p.A.indptr.dtype == np.int32
+
+
+def test_lasso_structure():
+    p = pr.lasso_qp(50, 400, 0.1, 9)
+    n, m = 50, 400
+    assert p.n == 2 * n + m and p.m == m + 2 * n
+    # P = blkdiag(0, 2I, 0); equality rows first, then −t ≤ x ≤ t
+    d = p.P_full().diagonal()
+    assert np.all(d[:n] == 0) and np.all(d[n:n + m] == 2) and np.all(d[n + m:] == 0)
+    assert np.array_equal(p.l[:m], p.u[:m])
+    assert np.all(np.isinf(p.l[m:m + n])) and np.all(np.isinf(p.u[m + n:]))
+
+
+def test_svm_labels_and_means():
+    p = pr.svm_qp(4000, 100, 0.2, 3)
+    N = 4000
+    Ad = sp.csr_matrix(p.A)[:N, :100]
+    # rows are diag(b)·Ad, whose entries then all have mean +1/n_feat
+    assert Ad.data.mean() == pytest.approx(1.0 / 100, rel=0.1)
+    assert np.all(p.u[:N] == -1.0) and np.all(p.l[N:] == 0.0)

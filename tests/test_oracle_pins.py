@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here calls the GPU library. Each pin is checked against something
+other than the oracle itself: a value the paper prints, a closed form, an
+invariant, a brute-force enumeration or a dense textbook computation. The
+``*_has_teeth`` tests plant a plausible mistake in a copy of an oracle
+routine and show that the corresponding pin then fails.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import activeset, admm, formats, kkt, pcg, ruiz, spmv
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- formats
+def test_paper_4x5_coo_csr_csc():
+    g = json.load(open(os.path.join(GOLD, "paper_4x5_formats.json")))
+    A = np.array(g["A"], dtype=float)
+    v, r, c = formats.dense_to_coo(A)
+    assert v.tolist() == g["coo"]["Value"]
+    assert r.tolist() == g["coo"]["RowIndex"]
+    assert c.tolist() == g["coo"]["ColumnIndex"]
+    cv, rp, ci = formats.coo_to_csr(v, r, c, 4)
+    assert cv.tolist() == g["csr"]["Value"]
+    assert rp.tolist() == g["csr"]["RowPointer"]
+    assert ci.tolist() == g["csr"]["ColumnIndex"]
+    assert rp[-1] == len(v)  # RowPointer[m] = nnz
+    sv, sr, sc = formats.coo_to_csc(v, r, c, 5)
+    assert sv.tolist() == g["csc"]["Value"]
+    assert sr.tolist() == g["csc"]["RowIndex"]
+    assert sc.tolist() == g["csc"]["ColumnPointer"]  # empty column 3: pointer repeats 6, 6
+    # CSC of A read as CSR of Aᵀ (Section 5.3.3)
+    tp, ti, tv = formats.csr_transpose(rp, ci, cv, 5)
+    assert tp.tolist() == g["csc"]["ColumnPointer"]
+    assert ti.tolist() == g["csc"]["RowIndex"]
+    assert tv.tolist() == g["csc"]["Value"]
+
+
+def test_triu_to_full_matches_dense_symmetrisation():
+    rng = np.random.default_rng(3)
+    for n in (1, 5, 17):
+        S = rng.standard_normal((n, n)) * (rng.random((n, n)) < 0.4)
+        S = S + S.T
+        T = sp.csc_matrix(np.triu(S))
+        ptr, col, val = formats.triu_to_full(T.indptr, T.indices, T.data, n)
+        F = sp.csr_matrix((val, col, ptr), shape=(n, n)).toarray()
+        np.testing.assert_array_equal(F, S)
+    bad = sp.csc_matrix(np.array([[1.0, 0.0], [2.0, 1.0]]))
+    with pytest.raises(ValueError):
+        formats.triu_to_full(bad.indptr, bad.indices, bad.data, 2)
+
+
+# ---------------------------------------------------------------- spmv
+def test_spmv_is_exact_on_integers_and_matches_fsum():
+    rng = np.random.default_rng(5)
+    D = sp.random(40, 30, density=0.3, random_state=1, format="csr").toarray()
+    D[7, :] = 0.0  # an empty row
+    M = sp.csr_matrix(D)
+    M.data = rng.integers(-50, 50, M.nnz).astype(float)
+    M.data[M.data == 0] = 1.0
+    x = rng.integers(-50, 50, 30).astype(float)
+    y = spmv.spmv(M.indptr, M.indices, M.data, x)
+    np.testing.assert_array_equal(y, M.toarray() @ x)  # integers: every order is exact
+    M.data = rng.standard_normal(M.nnz) * 10.0 ** rng.integers(-8, 8, M.nnz)
+    x = rng.standard_normal(30)
+    y = spmv.spmv(M.indptr, M.indices, M.data, x)
+    ya = spmv.spmv_abs(M.indptr, M.indices, M.data, x)
+    for i in range(40):
+        ex = spmv.row_exact(M.indptr, M.indices, M.data, x, i)
+        # extended accumulation: error ≤ rowlen·2⁻⁶³·(|M||x|)_i plus the final rounding
+        assert abs(y[i] - ex) <= 64 * 2.0 ** -63 * ya[i] + np.spacing(abs(ex))
+
+
+# ---------------------------------------------------------------- ruiz
+def _small_qp(seed, n=8, m=12, dens=0.5):
+    rng = np.random.default_rng(seed)
+    Mm = rng.standard_normal((n, n)) * (rng.random((n, n)) < dens)
+    P = Mm @ Mm.T + 1e-2 * np.eye(n)
+    A = rng.standard_normal((m, n)) * (rng.random((m, n)) < dens)
+    q = rng.standard_normal(n)
+    l = -rng.random(m)
+    u = rng.random(m)
+    return P, q, A, l, u
+
+
+def test_ruiz_invariants_every_pass():
+    P, q, A, l, u = _small_qp(11)
+    A[2, :] = 0.0  # an empty constraint row exercises the norm guard
+    P = sp.csr_matrix(P)
+    A = sp.csr_matrix(A)
+    for iters in range(1, 11):
+        D, E, c, Pb, qb, Ab, passes = ruiz.ruiz(P, q, A, iters)
+        Dm, Em = np.diag(D), np.diag(E)
+        np.testing.assert_allclose(Pb.toarray(), c * Dm @ P.toarray() @ Dm, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(qb, c * D * q, rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(Ab.toarray(), Em @ A.toarray() @ Dm, rtol=1e-14, atol=1e-15)
+        assert np.all(D > 0) and np.all(E > 0) and c > 0
+
+
+def test_ruiz_first_pass_against_dense_assembly():
+    P, q, A, l, u = _small_qp(12, n=5, m=4)
+    n, m = 5, 4
+    M = np.block([[P, A.T], [A, np.zeros((m, m))]])  # the matrix of Algorithm 2
+    colmax = np.abs(M).max(axis=0)
+    colmax = np.where(colmax < 1e-4, 1.0, np.minimum(colmax, 1e4))
+    delta = 1.0 / np.sqrt(colmax)
+    D, E = delta[:n], delta[n:]
+    Pb = np.diag(D) @ P @ np.diag(D)
+    qb = D * q
+    gam = 1.0 / max(np.abs(Pb).max(axis=0).mean(), np.abs(qb).max())
+    D_o, E_o, c_o, Pb_o, qb_o, Ab_o, _ = ruiz.ruiz(sp.csr_matrix(P), q, sp.csr_matrix(A), 1)
+    np.testing.assert_allclose(D_o, D, rtol=1e-15)
+    np.testing.assert_allclose(E_o, E, rtol=1e-15)
+    assert c_o == pytest.approx(gam, rel=1e-15)
+    np.testing.assert_allclose(Pb_o.toarray(), gam * Pb, rtol=1e-14)
+
+
+def test_ruiz_equilibrates_constraint_matrix():
+    rng = np.random.default_rng(13)
+    P, q, A, l, u = _small_qp(13, n=20, m=30)
+    A = A * np.exp(rng.uniform(-4, 4, (30, 1))) * np.exp(rng.uniform(-4, 4, (1, 20)))
+    D, E, c, Pb, qb, Ab, passes = ruiz.ruiz(sp.csr_matrix(P), q, sp.csr_matrix(A), 30)
+    rn = ruiz.row_inf_norms(Ab)
+    spread0 = np.abs(A).max(axis=1).max() / np.abs(A).max(axis=1).min()
+    assert rn.max() / rn.min() < 2.0 < spread0
+    assert rn.max() <= 1.0 + 1e-2
+
+
+# ---------------------------------------------------------------- KKT system
+def test_reduced_kkt_equals_full_kkt_and_z_recovery():
+    P, q, A, l, u = _small_qp(21, n=7, m=9)
+    rng = np.random.default_rng(22)
+    sigma, rho = 1e-6, 0.37
+    x, z, y = rng.standard_normal(7), rng.standard_normal(9), rng.standard_normal(9)
+    rvec = np.full(9, rho)
+    sol = admm.KKTSolver(sp.csr_matrix(P), sp.csr_matrix(A), sigma, rvec).solve(
+        np.concatenate([sigma * x - q, z - y / rvec]))
+    xt, nu = sol[:7], sol[7:]
+    zt = z + (nu - y) / rvec
+    # independent: eliminate ν by hand and solve the reduced system densely
+    Kr = P + sigma * np.eye(7) + rho * A.T @ A
+    xr = np.linalg.solve(Kr, sigma * x - q + A.T @ (rho * z - y))
+    np.testing.assert_allclose(xt, xr, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(zt, A @ xr, rtol=1e-10, atol=1e-12)
+
+
+def test_kkt_matrix_is_quasi_definite_inertia():
+    P, q, A, l, u = _small_qp(23, n=6, m=10)
+    K = admm.kkt_matrix(sp.csr_matrix(P), sp.csr_matrix(A), 1e-6, np.full(10, 0.1)).toarray()
+    ev = np.linalg.eigvalsh(K)
+    assert (ev > 0).sum() == 6 and (ev < 0).sum() == 10
+
+
+# ---------------------------------------------------------------- ADMM closed forms
+def _solve(P, q, A, l, u, **kw):
+    kw.setdefault("eps_abs", 1e-11)
+    kw.setdefault("eps_rel", 1e-11)
+    return admm.solve(sp.csr_matrix(P), q, sp.csr_matrix(A), l, u, **kw)
+
+
+@pytest.mark.parametrize("scaling", [0, 10])
+def test_closed_form_diagonal_box(scaling):
+    rng = np.random.default_rng(31)
+    n = 12
+    p = rng.uniform(0.1, 5, n)
+    q = rng.standard_normal(n) * 3
+    l = -rng.random(n)
+    u = rng.random(n)
+    r = _solve(np.diag(p), q, np.eye(n), l, u, scaling_iters=scaling)
+    x = np.clip(-q / p, l, u)
+    np.testing.assert_allclose(r.x, x, atol=1e-8)
+    np.testing.assert_allclose(r.y, -(p * x + q), atol=1e-8)
+
+
+def test_closed_form_unconstrained():
+    P, q, A, l, u = _small_qp(32, n=6, m=4)
+    l[:] = -np.inf
+    u[:] = np.inf
+    r = _solve(P, q, A, l, u)
+    np.testing.assert_allclose(r.x, -np.linalg.solve(P, q), rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(r.y, 0.0, atol=1e-8)
+
+
+def test_closed_form_equality_only():
+    P, q, A, l, u = _small_qp(33, n=8, m=3, dens=1.0)
+    b = np.random.default_rng(34).standard_normal(3)
+    r = _solve(P, q, A, b, b)
+    K = np.block([[P, A.T], [A, np.zeros((3, 3))]])
+    sol = np.linalg.solve(K, np.concatenate([-q, b]))
+    np.testing.assert_allclose(r.x, sol[:8], rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(r.y, sol[8:], rtol=1e-7, atol=1e-7)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bruteforce_active_set(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 7))
+    m = int(rng.integers(1, 9))
+    P, q, A, l, u = _small_qp(200 + seed, n=n, m=m, dens=0.8)
+    q *= 3
+    if seed % 3 == 0:
+        l[0] = u[0] = 0.1  # an equality
+    if seed % 2 == 1:
+        u[-1] = np.inf
+    xb, yb, fb = activeset.solve(P, q, A, l, u)
+    for r_mode in ("scalar", "vector"):
+        r = _solve(P, q, A, l, u, r_mode=r_mode)
+        np.testing.assert_allclose(r.x, xb, atol=1e-7 * (1 + np.abs(xb).max()))
+        assert r.obj == pytest.approx(fb, rel=1e-8, abs=1e-8)
+
+
+def test_kkt_report_zero_at_optimum_and_positive_elsewhere():
+    P, q, A, l, u = _small_qp(41, n=5, m=7)
+    q *= 3
+    xb, yb, fb = activeset.solve(P, q, A, l, u)
+    rep = kkt.kkt_report(sp.csr_matrix(P), q, sp.csr_matrix(A), l, u, xb, yb)
+    assert max(rep["prim"], rep["dual"], rep["box"], rep["comp"], rep["gap"]) < 1e-9
+    rep2 = kkt.kkt_report(sp.csr_matrix(P), q, sp.csr_matrix(A), l, u, xb + 1e-3, yb)
+    assert rep2["dual"] > 1e-5
+
+
+def test_admm_iterate_invariant():
+    P, q, A, l, u = _small_qp(51, n=10, m=20)
+    q *= 4
+    r = _solve(P, q, A, l, u, record=40, max_iter=40, scaling_iters=0)
+    for (x, z, y) in r.trace:
+        assert np.all(z >= l - 1e-15) and np.all(z <= u + 1e-15)
+        # y_new = y + ρ(v − Π(v + y/ρ)): an inactive row leaves y at round-off level
+        tol = 1e-12 * (1.0 + np.abs(y).max())
+        assert np.all((y <= tol) | (z == u))
+        assert np.all((y >= -tol) | (z == l))
+
+
+# ---------------------------------------------------------------- PCG pins
+def _spd(n, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.logspace(0, np.log10(cond), n)
+    return (Q * ev) @ Q.T
+
+
+def pcg_pin_holds(pcg_fn):
+    """Finite termination of CG (Section 4.1, Nocedal & Wright Thm 5.1 and its
+    corollary): with exact arithmetic PCG stops after at most as many steps as
+    M⁻¹K has distinct eigenvalues (≤ n). K = S K₀ S with K₀ having k distinct
+    eigenvalues and M = S² makes M⁻¹K similar to K₀, so k steps must solve it."""
+    for n, k, seed in ((8, 8, 1), (40, 5, 2), (64, 3, 3)):
+        rng = np.random.default_rng(seed)
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = np.resize(np.linspace(1.0, 20.0, k), n)
+        S = np.exp(rng.uniform(-2, 2, n))
+        K = S[:, None] * ((Q * lam) @ Q.T) * S[None, :]
+        b = rng.standard_normal(n)
+        x, steps, rn, _ = pcg_fn(lambda v: K @ v, b, np.zeros(n), 1.0 / S ** 2, 1e-13, k)
+        xs = np.linalg.solve(K, b)
+        if steps > k or np.max(np.abs(x - xs)) > 1e-8 * np.max(np.abs(xs)):
+            return False
+    return True
+
+
+def test_pcg_converges_within_n_steps():
+    assert pcg_pin_holds(pcg.pcg)
+
+
+def test_pcg_diagonal_system_with_jacobi_is_one_step():
+    d = np.random.default_rng(3).uniform(0.5, 9.0, 50)
+    b = np.random.default_rng(4).standard_normal(50)
+    x, k, rn, _ = pcg.pcg(lambda v: d * v, b, np.zeros(50), 1.0 / d, 1e-14, 10)
+    assert k == 1
+    np.testing.assert_allclose(x, b / d, rtol=1e-14)
+
+
+def test_pcg_warm_start_at_solution_takes_zero_steps():
+    K = _spd(20, 5)
+    b = np.random.default_rng(6).standard_normal(20)
+    xs = np.linalg.solve(K, b)
+    x, k, rn, _ = pcg.pcg(lambda v: K @ v, b, xs, np.ones(20), 1e-8, 50)
+    assert k == 0
+
+
+def test_pcg_iterates_invariant_to_preconditioner_scale():
+    K = _spd(30, 7)
+    b = np.random.default_rng(8).standard_normal(30)
+    d = 1.0 / np.diag(K)
+    x1, k1, _, h1 = pcg.pcg(lambda v: K @ v, b, np.zeros(30), d, 0.0, 12)
+    x2, k2, _, h2 = pcg.pcg(lambda v: K @ v, b, np.zeros(30), 7.5 * d, 0.0, 12)
+    np.testing.assert_allclose(x1, x2, rtol=1e-10, atol=1e-12)
+
+
+def test_jacobi_diag_and_reduced_operator_match_dense_product():
+    P, q, A, l, u = _small_qp(61, n=9, m=14)
+    Ps, As = sp.csr_matrix(P), sp.csr_matrix(A)
+    K = P + 1e-6 * np.eye(9) + 0.3 * A.T @ A
+    np.testing.assert_allclose(pcg.jacobi_diag(Ps, As, 1e-6, 0.3), np.diag(K), rtol=1e-14)
+    v = np.random.default_rng(62).standard_normal(9)
+    np.testing.assert_allclose(pcg.reduced_kkt_matvec(Ps, As, 1e-6, 0.3)(v), K @ v, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- planted mistakes
+def test_pcg_pin_has_teeth():
+    def pcg_wrong_sign(K, b, x0, minv, eps, max_iter):
+        # α taken with the sign as printed in Algorithm 3
+        x = np.array(x0, float)
+        r = K(x) - b
+        y = minv * r
+        p = -y
+        ry = r @ y
+        k = 0
+        while np.max(np.abs(r)) > eps * np.max(np.abs(b)) and k < max_iter:
+            Kp = K(p)
+            a = -ry / (p @ Kp)
+            x = x + a * p
+            r = r + a * Kp
+            y = minv * r
+            ry2 = r @ y
+            p = -y + ry2 / ry * p
+            ry = ry2
+            k += 1
+        return x, k, 0.0, []
+
+    def pcg_no_precond_update(K, b, x0, minv, eps, max_iter):
+        x = np.array(x0, float)
+        r = K(x) - b
+        y = minv * r
+        p = -y
+        ry = r @ y
+        k = 0
+        while np.max(np.abs(r)) > eps * np.max(np.abs(b)) and k < max_iter:
+            Kp = K(p)
+            a = ry / (p @ Kp)
+            x = x + a * p
+            r = r + a * Kp
+            ry2 = r @ y  # y not refreshed
+            p = -y + ry2 / ry * p
+            ry = ry2
+            k += 1
+        return x, k, 0.0, []
+
+    assert not pcg_pin_holds(pcg_wrong_sign)
+    assert not pcg_pin_holds(pcg_no_precond_update)
+
+
+def _admm_mutant(kind):
+    def step(kkt_, qb, lb, ub, rvec, sigma, alpha, x, z, y):
+        n = x.shape[0]
+        sol = kkt_.solve(np.concatenate([sigma * x - qb, z - y / rvec]))
+        xt, nu = sol[:n], sol[n:]
+        zt = z + (nu - y) / rvec
+        if kind == "relax_with_old_z":
+            zt = z.copy()
+        x_new = alpha * xt + (1.0 - alpha) * x
+        v = alpha * zt + (1.0 - alpha) * z
+        shift = 0.0 if kind == "drop_dual_in_projection" else y / rvec
+        z_new = np.minimum(np.maximum(v + shift, lb), ub)
+        y_new = y + rvec * (v - z_new)
+        return x_new, z_new, y_new
+    return step
+
+
+@pytest.mark.parametrize("kind", ["relax_with_old_z", "drop_dual_in_projection"])
+def test_bruteforce_pin_has_teeth(monkeypatch, kind):
+    P, q, A, l, u = _small_qp(205, n=4, m=6, dens=0.8)
+    q *= 3
+    xb, _, _ = activeset.solve(P, q, A, l, u)
+    monkeypatch.setattr(admm, "admm_step", _admm_mutant(kind))
+    with np.errstate(all="ignore"):
+        r = _solve(P, q, A, l, u, max_iter=3000)
+    assert not np.all(np.abs(r.x - xb) <= 1e-7 * (1 + np.abs(xb).max()))
