@@ -1,0 +1,187 @@
+/*
+ * qpg — ADMM with a reduced-KKT PCG linear solve for convex QPs, on MI355X (gfx950).
+ *
+ * Solves   minimize ½xᵀPx + qᵀx   subject to   l ≤ Ax ≤ u            (Section 2, eq. qp)
+ * with P ⪰ 0 (n×n), A (m×n), l_i ∈ ℝ∪{−∞}, u_i ∈ ℝ∪{+∞}, l ≤ u; l_i = u_i encodes an
+ * equality. The iteration is OSQP's ADMM (Algorithm 1) with R = ρ̄I, whose linear step is
+ * the reduced KKT system (P + σI + ρ̄AᵀA)x̃ = σx − q + Aᵀ(ρ̄z − y) (Section 6.3, eq.
+ * kkt_red_sc) solved inexactly by Jacobi-preconditioned CG (Algorithm 3, Section 6.3.1–6.3.3),
+ * warm-started from the previous x̃. The data are Ruiz-equilibrated (Algorithm 2) at setup.
+ *
+ * Conventions for every call:
+ *  - Return value: 0 on success, a negative QPG_ERR_* code otherwise. No call throws, aborts
+ *    or exits. The message of the last failure on a handle is kept for qpg_last_error().
+ *  - All dimensions and sparse indices are int32; values are IEEE double on the host side.
+ *  - Host pointers are read during the call only; setup copies every input, so the caller
+ *    may free its arrays on return. Output arrays are caller-allocated host memory.
+ *  - A handle is not thread-safe; use one handle per concurrent solve. All device work of a
+ *    handle runs on the stream given in the settings (NULL: the null stream).
+ *  - |bound| ≥ 1e20 (including ±INFINITY) is treated as infinite.
+ */
+#ifndef QPG_H
+#define QPG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes (return values). */
+#define QPG_OK 0
+#define QPG_ERR_ARG (-1)    /* null pointer, bad dimension, unsorted/duplicate/out-of-range index,
+                               entry below the diagonal of P_triu, bad setting value */
+#define QPG_ERR_DATA (-2)   /* NaN or ±inf in P, q or A; NaN in l or u; l_i > u_i */
+#define QPG_ERR_SIZE (-3)   /* a size that overflows the int32 indexing */
+#define QPG_ERR_DEVICE (-4) /* any HIP runtime error (message kept for qpg_last_error) */
+#define QPG_ERR_OOM (-5)    /* device or pinned host allocation failed */
+#define QPG_ERR_STATE (-6)  /* call not valid in the handle's current state */
+
+/* Solver status (qpg_info.status), separate from the error code. */
+#define QPG_UNSOLVED 0
+#define QPG_SOLVED 1
+#define QPG_MAX_ITER_REACHED 2
+#define QPG_NUMERICAL_ERROR 3 /* PCG breakdown (pᵀKp ≤ 0 or NaN) in every precision */
+
+/* Arithmetic of the iteration. */
+#define QPG_FP64 0  /* matrices, vectors and reductions in double */
+#define QPG_MIXED 1 /* matrices and vectors in float; PCG dots (α, β), residual norms and ρ̄
+                       ratios accumulated in double; falls back to QPG_FP64 on PCG stagnation */
+
+/* Preconditioner of the PCG step. */
+#define QPG_PRECOND_JACOBI 0 /* M = diag(P + σI + ρ̄AᵀA) (Section 6.3.1) */
+
+/* Compressed sparse column matrix (Section 5.3.3), zero-based. Row indices within each column
+ * must be strictly increasing. CSC of A is the CSR of Aᵀ (Section 5.3.3). */
+typedef struct {
+  int32_t nrows;
+  int32_t ncols;
+  int32_t nnz;
+  const int32_t* colptr; /* ncols+1 entries, colptr[0] = 0, colptr[ncols] = nnz */
+  const int32_t* rowidx; /* nnz entries */
+  const double* val;     /* nnz entries */
+} qpg_csc;
+
+typedef struct {
+  double rho;             /* initial ρ̄ > 0 (Section 3.4), default 0.1 */
+  double sigma;           /* σ > 0 (Section 3.4), default 1e-6 */
+  double alpha;           /* relaxation α ∈ (0, 2) (Section 3.4), default 1.6 */
+  double eps_abs;         /* absolute tolerance of the termination test, default 1e-3 */
+  double eps_rel;         /* relative tolerance of the termination test, default 1e-3 */
+  int32_t max_iter;       /* ADMM iteration cap, default 4000 */
+  int32_t check_every;    /* residual/termination check cadence (Section 6.3.3), default 5 */
+  int32_t rho_update_every; /* ρ̄ update cadence in iterations (Section 6.3.2), default 10; 0 = fixed ρ̄ */
+  double rho_update_gate; /* apply a ρ̄ estimate only if it differs by more than this factor; default 1 (always) */
+  double pcg_lambda;      /* λ of the PCG tolerance rule (Section 6.3.3), default 0.15 */
+  double pcg_eps_min;     /* ε_min of the PCG tolerance rule, default 1e-7 */
+  double pcg_eps_fixed;   /* > 0: use this fixed PCG tolerance instead of the rule; default 0 */
+  int32_t pcg_max_iter;   /* PCG iteration cap per ADMM iteration, default 100 */
+  int32_t pcg_rel_test;   /* 1: stop PCG when ‖r‖∞ ≤ ε‖b‖∞ (Algorithm 3); 0: when ‖r‖∞ ≤ ε */
+  int32_t scaling_iters;  /* Ruiz passes (Algorithm 2); 0 disables scaling; default 10 */
+  int32_t precision;      /* QPG_FP64 or QPG_MIXED */
+  int32_t precond;        /* QPG_PRECOND_JACOBI */
+  int32_t device;         /* HIP device ordinal, default 0 */
+  void* stream;           /* hipStream_t for all device work, NULL = null stream */
+  int32_t verbose;        /* 1: one line per residual check on stderr */
+} qpg_settings;
+
+typedef struct {
+  int32_t status;          /* QPG_SOLVED, QPG_MAX_ITER_REACHED, ... */
+  int32_t iter;            /* ADMM iterations of the last solve */
+  int64_t pcg_iter_total;  /* PCG iterations summed over the last solve */
+  int32_t pcg_iter_max;    /* largest PCG iteration count of one ADMM iteration */
+  int32_t rho_updates;     /* ρ̄ changes in the last solve */
+  double obj_val;          /* ½xᵀPx + qᵀx of the returned x (unscaled) */
+  double prim_res;         /* ‖Ax − z‖∞ (unscaled) at the last check */
+  double dual_res;         /* ‖Px + q + Aᵀy‖∞ (unscaled) at the last check */
+  double rho_final;        /* ρ̄ at the end of the last solve */
+  double setup_time;       /* seconds spent in qpg_setup */
+  double solve_time;       /* seconds of the last qpg_solve (device work included) */
+  int32_t precision_used;  /* precision the last solve finished in */
+  int32_t precond_used;    /* preconditioner the last solve finished with */
+  int32_t fallback_events; /* precision fallbacks taken during the last solve */
+  int32_t scaling_passes;  /* Ruiz passes performed at setup */
+} qpg_info;
+
+typedef struct qpg_solver qpg_solver;
+
+/* Fill *s with the defaults listed above. */
+int qpg_default_settings(qpg_settings* s);
+
+/* Validate and copy the problem (P given as its upper triangle incl. diagonal in CSC, the OSQP
+ * convention of Section 6.2; A in CSC), expand P to full CSR and store A and Aᵀ in CSR
+ * (Section 6.2), equilibrate (Algorithm 2), move everything to device memory and build the
+ * SpMV work schedules. On success *out owns all device memory of the problem. Validation
+ * failures return before any device call. */
+int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qpg_csc* A,
+              const double* l, const double* u, const qpg_settings* settings);
+
+/* Run Algorithm 1 from x = z = y = 0, x̃ = 0 and the initial ρ̄ until the unscaled residuals meet
+ * eps_prim = eps_abs + eps_rel·max(‖Ax‖∞, ‖z‖∞), eps_dual = eps_abs + eps_rel·max(‖Px‖∞, ‖Aᵀy‖∞,
+ * ‖q‖∞) (Section 3.1, checked every check_every iterations) or max_iter is reached. The status
+ * is in qpg_info; reaching max_iter is not an error. */
+int qpg_solve(qpg_solver* h);
+
+/* Copy the unscaled iterates of the last solve: x (n), y (m), z (m). */
+int qpg_get_x(const qpg_solver* h, double* x);
+int qpg_get_y(const qpg_solver* h, double* y);
+int qpg_get_z(const qpg_solver* h, double* z);
+int qpg_get_info(const qpg_solver* h, qpg_info* info);
+
+/* Ruiz factors D (n), E (m) and cost scale c with P̄ = cDPD, q̄ = cDq, Ā = EAD (Section 3.3). */
+int qpg_get_scaling(const qpg_solver* h, double* D, double* E, double* c);
+
+/* Operators of the scaled problem, run by the solver's own device kernels and schedules in the
+ * given precision (QPG_FP64, or QPG_MIXED for the float copies). in/out are host arrays.
+ *   QPG_OP_A   out(m) = Ā in(n)                         (Section 6.2: A stored in CSR)
+ *   QPG_OP_AT  out(n) = Āᵀ in(m)                        (Section 6.2: Aᵀ stored in CSR)
+ *   QPG_OP_P   out(n) = P̄ in(n)                         (Section 6.2: full P in CSR)
+ *   QPG_OP_K   out(n) = (P̄ + σI + ρ̄ĀᵀĀ) in(n), matrix-free as w = ρ̄Āx, Px + σx + Āᵀw
+ *                                                       (Section 6.3) with the current ρ̄ */
+#define QPG_OP_A 0
+#define QPG_OP_AT 1
+#define QPG_OP_P 2
+#define QPG_OP_K 3
+int qpg_apply(qpg_solver* h, int32_t op, int32_t precision, const double* in, double* out);
+
+/* Algorithm 3 on the scaled reduced system (P̄ + σI + ρ̄ĀᵀĀ)x = b with the Jacobi preconditioner
+ * of Section 6.3.1 and the current ρ̄: starts from x0 (n), stops when ‖r‖∞ ≤ eps·‖b‖∞ (rel = 1)
+ * or ‖r‖∞ ≤ eps (rel = 0) or after max_iter iterations. Writes x (n), the iteration count and
+ * the final ‖r‖∞. Same kernels as the PCG inside qpg_solve. */
+int qpg_pcg(qpg_solver* h, int32_t precision, const double* b, const double* x0, double eps,
+            int32_t rel, int32_t max_iter, double* x, int32_t* iters, double* rnorm);
+
+/* Set ρ̄ (> 0) for qpg_apply(QPG_OP_K) and qpg_pcg, rebuilding diag(M) = diag(P̄) + σ + ρ̄‖Ā_i‖²
+ * (Section 6.3.1–6.3.2). qpg_solve restarts from settings.rho. */
+int qpg_set_rho(qpg_solver* h, double rho);
+
+/* Average device duration, in microseconds, of `reps` back-to-back launches of one kernel of the
+ * PCG iteration (Algorithm 3 with the matrix-free K-matvec of Section 6.3), timed with HIP events
+ * on the solver's stream, in the launch configuration the solve uses, on the current device
+ * vectors (their contents are overwritten). Kernels:
+ *   QPG_KERNEL_SPMV_A      w = ρ̄Āp                               (m rows of Ā)
+ *   QPG_KERNEL_SPMV_B      Kp = P̄p + σp + Āᵀw, κ = pᵀKp, α         (n rows of [P̄ | Āᵀ])
+ *   QPG_KERNEL_PCG_UPDATE  x̃ += αp, r += αKp, rᵀM⁻¹r, ‖r‖∞, β     (n)
+ *   QPG_KERNEL_PCG_DIR     p = −M⁻¹r + βp                          (n)
+ * reps ≥ 1; precision as in qpg_apply. */
+#define QPG_KERNEL_SPMV_A 0
+#define QPG_KERNEL_SPMV_B 1
+#define QPG_KERNEL_PCG_UPDATE 2
+#define QPG_KERNEL_PCG_DIR 3
+int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t reps, double* avg_us);
+
+/* Release all device and host memory of h. NULL is accepted. */
+int qpg_cleanup(qpg_solver* h);
+
+/* Static description of an error code. */
+const char* qpg_error_string(int code);
+
+/* Message of the last failure on h (empty string if none; h may be NULL for setup failures:
+ * then the message of the last failed qpg_setup on this thread is returned). */
+const char* qpg_last_error(const qpg_solver* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPG_H */

@@ -8,6 +8,12 @@ Each iteration, on the Ruiz-scaled problem (Algorithm 2):
   5. y ← y + R(αz̃ + (1−α)z − z_new)
 and stops when the unscaled residuals meet the relative test of Section 3.1.
 
+``linsys="pcg"`` replaces the direct solve by the route of Section 6.3: R = ρ̄I, the reduced
+system (eq. kkt_red_sc) solved with Algorithm 3 (``oracle.pcg``) to a tight relative tolerance,
+warm-started from the previous x̃, and z̃ = Āx̃. With an exact solve both routes produce the
+same iterates; this mode only exists to time the method on the host at sizes the direct
+factorisation cannot reach.
+
 R is ρ̄I (the choice Section 6.3 makes for the GPU solver) or OSQP's vector
 ρ_i = ρ̄ on inequalities and 10³ρ̄ on equalities (eq. rho_vec); the solution
 does not depend on R. The KKT matrix is factored once and again only when ρ̄
@@ -84,6 +90,33 @@ class KKTSolver:
         return sol - self.lu.solve(self.K @ sol - rhs)
 
 
+class ReducedPCGSolver:
+    """Exact-to-tolerance solve of eq. kkt via the reduced system and Algorithm 3 (R = ρ̄I)."""
+
+    def __init__(self, Pb, Ab, sigma, rvec, tol):
+        from . import pcg as _pcg
+        self.n = Pb.shape[0]
+        self.rho = float(rvec[0]) if rvec.size else 1.0
+        self.A = sp.csr_matrix(Ab)
+        self.At = self.A.T.tocsr()
+        self.K = _pcg.reduced_kkt_matvec(Pb, Ab, sigma, self.rho)
+        self.minv = 1.0 / _pcg.jacobi_diag(Pb, Ab, sigma, self.rho)
+        self.sigma = sigma
+        self.tol = tol
+        self.xt = np.zeros(self.n)
+        self.pcg_iters = 0
+        self._pcg = _pcg.pcg
+
+    def solve(self, rhs):
+        # rhs = [σx − q̄; z − R⁻¹y]  ⇒  b = σx − q̄ + Āᵀ(ρ̄z − y) = rhs_x + ρ̄Āᵀ rhs_z
+        b = rhs[:self.n] + self.rho * (self.At @ rhs[self.n:])
+        self.xt, k, _, _ = self._pcg(self.K, b, self.xt, self.minv, self.tol, 10 * self.n + 100)
+        self.pcg_iters += k
+        zt = self.A @ self.xt
+        # return (x̃, ν) with ν chosen so that z + R⁻¹(ν − y) = z̃, i.e. ν = ρ̄(z̃ − rhs_z)
+        return np.concatenate([self.xt, self.rho * (zt - rhs[self.n:])])
+
+
 def admm_step(kkt, qb, lb, ub, rvec, sigma, alpha, x, z, y):
     """One iteration of Algorithm 1 on the scaled problem."""
     n = x.shape[0]
@@ -107,7 +140,8 @@ def rho_vector(l, u, rho_bar, mode):
 
 def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, eps_rel=1e-9,
           max_iter=20000, scaling_iters=10, r_mode="scalar", adaptive_rho=True, rho_interval=100,
-          check_every=1, record=0, x0=None, z0=None, y0=None) -> AdmmResult:
+          check_every=1, record=0, x0=None, z0=None, y0=None, linsys="direct",
+          pcg_tol=1e-12) -> AdmmResult:
     import time
 
     P_full = sp.csr_matrix(P_full, dtype=np.float64)
@@ -130,9 +164,17 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
     y = np.zeros(m) if y0 is None else c * np.asarray(y0, dtype=np.float64) / E
 
     rho_bar = rho
+    if linsys == "pcg":
+        r_mode = "scalar"
     rvec = rho_vector(lb, ub, rho_bar, r_mode)
+
+    def factor(rv):
+        if linsys == "pcg":
+            return ReducedPCGSolver(Pb, Ab, sigma, rv, pcg_tol)
+        return KKTSolver(Pb, Ab, sigma, rv)
+
     t0 = time.perf_counter()
-    kkt = KKTSolver(Pb, Ab, sigma, rvec)
+    kkt = factor(rvec)
     factor_time = time.perf_counter() - t0
     rho_updates = 0
     last_update = 0
@@ -175,7 +217,10 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
                 rho_bar = est
                 rvec = rho_vector(lb, ub, rho_bar, r_mode)
                 t0 = time.perf_counter()
-                kkt = KKTSolver(Pb, Ab, sigma, rvec)
+                prev = getattr(kkt, "xt", None)
+                kkt = factor(rvec)
+                if prev is not None:
+                    kkt.xt = prev
                 factor_time += time.perf_counter() - t0
                 rho_updates += 1
                 last_update = it

@@ -1,0 +1,635 @@
+// Device kernels of the ADMM / reduced-KKT PCG path for gfx950 (wavefront 64, 256-thread
+// workgroups). Included by solver.hip only.
+//
+// All SpMVs run through one kernel template, k_spmv, driven by the host-built work list (Item):
+// each workgroup either streams a run of short rows through LDS (coalesced value/index loads,
+// products staged in LDS, then one power-of-two lane group per row reduces its segment), or
+// reduces one long row with all 256 threads, or one chunk of a very long row whose partial
+// sums are combined, in chunk order, by the last chunk to finish. The row sum then goes to an
+// operation-specific epilogue (the fused vector work of the ADMM / PCG step), whose reduction
+// contributions (FP64 sums and ∞-norms) are combined deterministically: per-workgroup partials,
+// reduced in a fixed order by the last workgroup to arrive, which also runs the scalar
+// finalisation (α, β, stopping flags) on the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qpg_internal.hpp"
+
+namespace qpg {
+
+constexpr int kMaxSlots = 8;
+
+// Scalars of the iteration that live on the device.
+struct DevState {
+  double rz;      // rᵀM⁻¹r of the current PCG iterate
+  double alpha;   // PCG step length
+  double beta;    // PCG direction update
+  double kappa;   // pᵀKp
+  double bnorm;   // ‖b‖∞
+  double rnorm;   // ‖r‖∞
+  double thresh;  // PCG stopping threshold on ‖r‖∞
+  double pad0;
+  int32_t iter;       // PCG iterations of the current solve
+  int32_t done;       // PCG finished (converged, capped or broken down)
+  int32_t breakdown;  // pᵀKp ≤ 0 / NaN or rᵀM⁻¹r NaN seen
+  int32_t maxit;      // PCG iteration cap
+  uint32_t pad1;
+  uint32_t pad2;
+  double norms[16];   // residual-check outputs (see OpRPrim / OpRDual)
+};
+
+struct RedBuf {
+  double* partials;        // [gridDim.x][kMaxSlots], read by the following k_finalize
+  double* chunk_part;      // [chunk slots][3]
+  uint32_t* chunk_ticket;  // [split rows] (kept at 0 between launches)
+};
+
+// NaN-propagating max (a NaN residual must not disappear inside a norm).
+__device__ __forceinline__ double nmax(double a, double b) {
+  if (a != a) return a;
+  if (b != b) return b;
+  return a > b ? a : b;
+}
+
+template <unsigned MAXMASK>
+__device__ __forceinline__ double comb(int s, double a, double b) {
+  return ((MAXMASK >> s) & 1u) ? nmax(a, b) : a + b;
+}
+
+template <typename T>
+__device__ __forceinline__ T ldnt(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// 256-thread reduction of NS slots; result valid in thread 0. Fixed order: deterministic.
+template <int NS, unsigned MAXMASK>
+__device__ __forceinline__ void block_reduce(double (&v)[NS], double* lds) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double x = v[s];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = comb<MAXMASK>(s, x, __shfl_xor(x, off, 64));
+    v[s] = x;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) lds[s * 4 + wid] = v[s];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      v[s] = comb<MAXMASK>(s, comb<MAXMASK>(s, lds[s * 4 + 0], lds[s * 4 + 1]),
+                           comb<MAXMASK>(s, lds[s * 4 + 2], lds[s * 4 + 3]));
+  }
+}
+
+// Publish this workgroup's partials (thread 0 after block_reduce). They are combined by
+// k_finalize, launched next on the same stream: no cross-workgroup synchronisation inside a
+// kernel, and the combination order is fixed (workgroup order), so results are reproducible.
+template <int NS, unsigned MAXMASK>
+__device__ __forceinline__ void publish(double (&v)[NS], double* partials) {
+  __shared__ double lds[kMaxSlots * 4];
+  block_reduce<NS, MAXMASK>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) partials[(size_t)blockIdx.x * kMaxSlots + s] = v[s];
+  }
+}
+
+// One workgroup: combine `count` partials in workgroup order, then run the scalar finalisation.
+template <int NS, unsigned MAXMASK, class Fin>
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int count,
+                                                     Fin fin, const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;
+  __shared__ double lds[kMaxSlots * 4];
+  double acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+  for (int b = threadIdx.x; b < count; b += kBlock) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = comb<MAXMASK>(s, acc[s], partials[(size_t)b * kMaxSlots + s]);
+  }
+  block_reduce<NS, MAXMASK>(acc, lds);
+  if (threadIdx.x == 0) fin(acc);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, width);
+  return x;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Generic CSR SpMV with fused epilogue. Op supplies:
+//   static constexpr int NS;            reduction slots (0: none)
+//   static constexpr unsigned MAXMASK;  bit s set: slot s is an ∞-norm (max), else a sum
+//   static constexpr int NV;            products per entry: 1, or 2 (second vector, Op::gather2)
+//   T gather(int col) const;            multiplied vector, first product
+//   T gather2(int col) const;           second product's vector (NV == 2)
+//   void epilogue(int row, T s1, T s2, T s3, double* red) const;
+//        s1 / s2: first product summed over the entries before / from split[row];
+//        s3: second product summed over the entries from split[row]
+//   void side() const;                  extra elementwise work (grid-stride)
+//   void operator()(const double* totals) const;  scalar finalisation (run by k_finalize)
+// ----------------------------------------------------------------------------------------------
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_spmv(const Item* __restrict__ items,
+                                                 const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ split,
+                                                 const int32_t* __restrict__ col,
+                                                 const T* __restrict__ val, Op op, RedBuf rb,
+                                                 const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;  // uniform across the grid: set before the launch
+  constexpr int NS = Op::NS > 0 ? Op::NS : 1;
+  constexpr int NV = Op::NV;
+  double red[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) red[s] = 0.0;
+
+  __shared__ T prod[NV][kStreamCap];
+  __shared__ T wsum[3][kBlock / 64];
+  const Item it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+
+  if (it.nchunk == 0 && it.k1 - it.k0 <= kStreamCap) {
+    // ---- a run of whole rows: stage the products in LDS, then one lane group per row
+    const int cnt = it.k1 - it.k0;
+#pragma unroll 8
+    for (int t = tid; t < cnt; t += kBlock) {
+      const int k = it.k0 + t;
+      const T v = ldnt(&val[k]);
+      const int c = ldnt(&col[k]);
+      prod[0][t] = v * op.gather(c);
+      if constexpr (NV == 2) prod[NV - 1][t] = v * op.gather2(c);
+    }
+    __syncthreads();
+    const int nrows = it.r1 - it.r0;
+    int L = 64;
+    while (L > 1 && L * nrows > kBlock) L >>= 1;
+    const int groups = kBlock / L;
+    const int g = tid / L, lane = tid % L;
+    for (int rr = g; rr < nrows; rr += groups) {
+      const int r = it.r0 + rr;
+      const int a = rowptr[r] - it.k0, b = rowptr[r + 1] - it.k0;
+      const int sp = split ? split[r] - it.k0 : b;
+      T s1 = T(0), s2 = T(0), s3 = T(0);
+      for (int t = a + lane; t < sp; t += L) s1 += prod[0][t];
+      for (int t = sp + lane; t < b; t += L) {
+        s2 += prod[0][t];
+        if constexpr (NV == 2) s3 += prod[NV - 1][t];
+      }
+      if (L > 1) {
+        s1 = wave_sum(s1, L);
+        s2 = wave_sum(s2, L);
+        if constexpr (NV == 2) s3 = wave_sum(s3, L);
+      }
+      if (lane == 0) op.epilogue(r, s1, s2, s3, red);
+    }
+  } else {
+    // ---- one long row (or one chunk of a very long row): all 256 threads stride its entries
+    const int r = it.r0;
+    const int sp = split ? split[r] : it.k1;
+    T s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll 4
+    for (int k = it.k0 + tid; k < it.k1; k += kBlock) {
+      const T v = ldnt(&val[k]);
+      const int c = ldnt(&col[k]);
+      const T pr = v * op.gather(c);
+      if (k < sp) {
+        s1 += pr;
+      } else {
+        s2 += pr;
+        if constexpr (NV == 2) s3 += v * op.gather2(c);
+      }
+    }
+    s1 = wave_sum(s1, 64);
+    s2 = wave_sum(s2, 64);
+    s3 = wave_sum(s3, 64);
+    if ((tid & 63) == 0) {
+      wsum[0][tid >> 6] = s1;
+      wsum[1][tid >> 6] = s2;
+      wsum[2][tid >> 6] = s3;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s1 = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+      s2 = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
+      s3 = (wsum[2][0] + wsum[2][1]) + (wsum[2][2] + wsum[2][3]);
+      if (it.nchunk == 0) {
+        op.epilogue(r, s1, s2, s3, red);
+      } else {
+        // rows longer than kLongCap: chunk partials, combined in chunk order by the last chunk
+        double* cp = rb.chunk_part + 3 * (size_t)(it.slot + it.chunk);
+        __hip_atomic_store(&cp[0], (double)s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cp[1], (double)s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cp[2], (double)s3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        uint32_t t = __hip_atomic_fetch_add(&rb.chunk_ticket[it.ticket], 1u, __ATOMIC_ACQ_REL,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        if (t == (uint32_t)(it.nchunk - 1)) {
+          __threadfence();
+          T S1 = T(0), S2 = T(0), S3 = T(0);
+          for (int c = 0; c < it.nchunk; ++c) {
+            const double* q = rb.chunk_part + 3 * (size_t)(it.slot + c);
+            S1 += (T)__hip_atomic_load(&q[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            S2 += (T)__hip_atomic_load(&q[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            S3 += (T)__hip_atomic_load(&q[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          __hip_atomic_store(&rb.chunk_ticket[it.ticket], 0u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          op.epilogue(r, S1, S2, S3, red);
+        }
+      }
+    }
+  }
+  op.side();
+  if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, rb.partials);
+}
+
+// ------------------------------------------------------------------------------- SpMV epilogues
+
+#define QPG_NO_SIDE \
+  __device__ void side() const {}
+#define QPG_NO_FIN \
+  __device__ void operator()(const double*) const {}
+#define QPG_ONE_PRODUCT                      \
+  static constexpr int NV = 1;               \
+  __device__ T gather2(int) const { return T(0); }
+
+// out = scale · (M v)   (M = Ā, or the whole of B with v = [vp; vat])
+template <typename T>
+struct OpScaled {
+  QPG_NO_SIDE
+  QPG_NO_FIN
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 0;
+  static constexpr unsigned MAXMASK = 0;
+  const T* v;
+  T* out;
+  T scale;
+  __device__ T gather(int c) const { return v[c]; }
+  __device__ void epilogue(int r, T s1, T s2, T, double*) const { out[r] = scale * (s1 + s2); }
+};
+
+// B-part products: P̄ vp + Āᵀ vat (either pointer may be null: that part contributes 0)
+template <typename T>
+struct OpB {
+  QPG_NO_SIDE
+  QPG_NO_FIN
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 0;
+  static constexpr unsigned MAXMASK = 0;
+  const T* vp;
+  const T* vat;
+  T* out;
+  int n;
+  __device__ T gather(int c) const {
+    if (c < n) return vp ? vp[c] : T(0);
+    return vat ? vat[c - n] : T(0);
+  }
+  __device__ void epilogue(int r, T s1, T s2, T, double*) const { out[r] = s1 + s2; }
+};
+
+// Right-hand side of the reduced KKT system (eq. kkt_red_sc) and the warm-started PCG residual
+// (Algorithm 3 initialisation) in one pass over B = [P̄ | Āᵀ], with z̃ = Āx̃ kept from the
+// previous ADMM iteration's update pass:
+//   b  = σx − q̄ + Āᵀ(ρ̄z − y)                                   (only ‖b‖∞ is needed)
+//   r⁰ = Kx̃ − b = P̄x̃ + σ(x̃ − x) + q̄ + Āᵀ(ρ̄(z̃ − z) + y)
+//   p⁰ = −M⁻¹r⁰;  rᵀM⁻¹r;  ‖r‖∞.
+template <typename T>
+struct OpRhsR0 {
+  QPG_NO_SIDE
+  static constexpr int NV = 2;
+  static constexpr int NS = 3;
+  static constexpr unsigned MAXMASK = 0x5u;  // ‖b‖∞, rᵀM⁻¹r, ‖r‖∞
+  const T* x;
+  const T* xt;
+  const T* qb;
+  const T* z;
+  const T* y;
+  const T* zt;
+  const T* dinv;
+  T* r;
+  T* p;
+  T sigma, rho;
+  int n, maxit, rel;
+  double eps;
+  DevState* st;
+  __device__ T gather(int c) const {
+    if (c < n) return xt[c];
+    const int j = c - n;
+    return rho * (zt[j] - z[j]) + y[j];
+  }
+  __device__ T gather2(int c) const {
+    if (c < n) return T(0);
+    const int j = c - n;
+    return rho * z[j] - y[j];
+  }
+  __device__ void epilogue(int i, T s1, T s2, T s3, double* red) const {
+    const T xi = x[i];
+    const T bi = sigma * xi - qb[i] + s3;
+    const T ri = ((s1 + sigma * (xt[i] - xi)) + qb[i]) + s2;
+    const T yi = ri * dinv[i];
+    r[i] = ri;
+    p[i] = -yi;
+    red[0] = nmax(red[0], fabs((double)bi));
+    red[1] += (double)ri * (double)yi;
+    red[2] = nmax(red[2], fabs((double)ri));
+  }
+  __device__ void operator()(const double* t) const {
+    st->bnorm = t[0];
+    st->thresh = rel ? eps * t[0] : eps;
+    st->rz = t[1];
+    st->rnorm = t[2];
+    st->iter = 0;
+    st->maxit = maxit;
+    st->breakdown = (t[1] != t[1]) ? 1 : 0;
+    st->done = (t[2] <= st->thresh || st->breakdown || maxit <= 0) ? 1 : 0;
+  }
+};
+
+// PCG initialisation for a given right-hand side b (Algorithm 3): r = Kx̃ − b with
+// Kx̃ = P̄x̃ + σx̃ + Āᵀw, w = ρ̄Āx̃ computed before; p = −M⁻¹r; rᵀM⁻¹r; ‖r‖∞.
+template <typename T>
+struct OpR0 {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 2;
+  static constexpr unsigned MAXMASK = 2u;
+  const T* xt;
+  const T* w;
+  const T* b;
+  const T* dinv;
+  T* r;
+  T* p;
+  T sigma;
+  int n;
+  int maxit;
+  DevState* st;
+  __device__ T gather(int c) const { return c < n ? xt[c] : w[c - n]; }
+  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+    const T ri = (s1 + s2 + sigma * xt[i]) - b[i];
+    const T yi = ri * dinv[i];
+    r[i] = ri;
+    p[i] = -yi;
+    red[0] += (double)ri * (double)yi;
+    red[1] = nmax(red[1], fabs((double)ri));
+  }
+  __device__ void operator()(const double* t) const {
+    st->rz = t[0];
+    st->rnorm = t[1];
+    st->iter = 0;
+    st->maxit = maxit;
+    st->breakdown = (t[0] != t[0]) ? 1 : 0;
+    st->done = (t[1] <= st->thresh || st->breakdown || maxit <= 0) ? 1 : 0;
+  }
+};
+
+// PCG K-matvec, second half: Kp = P̄p + σp + Āᵀw (w = ρ̄Āp); κ = pᵀKp; α = rᵀM⁻¹r / κ.
+template <typename T>
+struct OpKp {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 1;
+  static constexpr unsigned MAXMASK = 0u;
+  const T* p;
+  const T* w;
+  T* kp;
+  T sigma;
+  int n;
+  DevState* st;
+  __device__ T gather(int c) const { return c < n ? p[c] : w[c - n]; }
+  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+    const T pi = p[i];
+    const T k = s1 + s2 + sigma * pi;
+    kp[i] = k;
+    red[0] += (double)pi * (double)k;
+  }
+  __device__ void operator()(const double* t) const {
+    st->kappa = t[0];
+    if (t[0] > 0.0) {
+      st->alpha = st->rz / t[0];
+    } else {
+      // p = 0 only when r = 0 (an exact solve); any other pᵀKp ≤ 0 or NaN is a breakdown
+      st->alpha = 0.0;
+      st->done = 1;
+      if (!(t[0] == 0.0 && st->rz == 0.0)) st->breakdown = 1;
+    }
+  }
+};
+
+// ADMM update (Algorithm 1, relaxation, projection and dual steps) fused with z̃ = Āx̃
+// (Section 4) over the rows of Ā:
+//   v = αz̃ + (1−α)z;  z⁺ = Π_[l̄,ū](v + y/ρ̄);  y ← y + ρ̄(v − z⁺);  z̃ kept for the next r⁰;
+//   Āx ← αz̃ + (1−α)Āx when `ax` is tracked (x ← αx̃ + (1−α)x makes this exact);
+//   side task: x ← αx̃ + (1−α)x.
+// With CHECK, the primal residual r̄_p = Āx − z⁺ and its norms are reduced as well:
+// slots ‖r̄_p‖, ‖E⁻¹r̄_p‖, ‖Āx‖, ‖E⁻¹Āx‖, ‖z‖, ‖E⁻¹z‖ → norms[0..5].
+template <typename T, bool CHECK>
+struct OpUpdate {
+  QPG_ONE_PRODUCT
+  static constexpr int NS = CHECK ? 6 : 0;
+  static constexpr unsigned MAXMASK = 0x3Fu;
+  const T* xt;
+  T* x;
+  T* z;
+  T* y;
+  T* zt;
+  T* ax;
+  const T* lb;
+  const T* ub;
+  const double* einv;
+  T alpha, rho, rho_inv;
+  int n;
+  DevState* st;
+  __device__ T gather(int c) const { return xt[c]; }
+  __device__ void epilogue(int i, T s1, T, T, double* red) const {
+    const T zi = z[i], yi = y[i];
+    const T v = alpha * s1 + (T(1) - alpha) * zi;
+    T zn = v + yi * rho_inv;
+    zn = zn < lb[i] ? lb[i] : zn;
+    zn = zn > ub[i] ? ub[i] : zn;
+    y[i] = yi + rho * (v - zn);
+    z[i] = zn;
+    zt[i] = s1;
+    if (ax) {
+      const T a = alpha * s1 + (T(1) - alpha) * ax[i];
+      ax[i] = a;
+      if constexpr (CHECK) {
+        const double e = einv[i], ad = (double)a, zd = (double)zn;
+        const double rp = ad - zd;
+        red[0] = nmax(red[0], fabs(rp));
+        red[1] = nmax(red[1], fabs(rp * e));
+        red[2] = nmax(red[2], fabs(ad));
+        red[3] = nmax(red[3], fabs(ad * e));
+        red[4] = nmax(red[4], fabs(zd));
+        red[5] = nmax(red[5], fabs(zd * e));
+      }
+    }
+  }
+  __device__ void side() const {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+      x[i] = alpha * xt[i] + (T(1) - alpha) * x[i];
+  }
+  __device__ void operator()(const double* t) const {
+    for (int s = 0; s < 6; ++s) st->norms[s] = t[s];
+  }
+};
+
+// Primal residual check with Āx recomputed (Section 3.1): r̄_p = Āx̄ − z̄; norms[0..5] as above.
+template <typename T>
+struct OpRPrim {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 6;
+  static constexpr unsigned MAXMASK = 0x3Fu;
+  const T* x;
+  const T* z;
+  const double* einv;
+  DevState* st;
+  __device__ T gather(int c) const { return x[c]; }
+  __device__ void epilogue(int i, T s1, T, T, double* red) const {
+    const double ax = (double)s1, zi = (double)z[i], e = einv[i];
+    const double rp = ax - zi;
+    red[0] = nmax(red[0], fabs(rp));
+    red[1] = nmax(red[1], fabs(rp * e));
+    red[2] = nmax(red[2], fabs(ax));
+    red[3] = nmax(red[3], fabs(ax * e));
+    red[4] = nmax(red[4], fabs(zi));
+    red[5] = nmax(red[5], fabs(zi * e));
+  }
+  __device__ void operator()(const double* t) const {
+    for (int s = 0; s < 6; ++s) st->norms[s] = t[s];
+  }
+};
+
+// Dual residual check: r̄_d = P̄x̄ + q̄ + Āᵀȳ with both parts of B in one pass;
+// norms[6..11] = ‖r̄_d‖, ‖D⁻¹r̄_d‖, ‖P̄x̄‖, ‖D⁻¹P̄x̄‖, ‖Āᵀȳ‖, ‖D⁻¹Āᵀȳ‖ (c⁻¹ applied on the host),
+// norms[12] = x̄ᵀP̄x̄, norms[13] = q̄ᵀx̄ (objective = (½·[12] + [13]) / c).
+template <typename T>
+struct OpRDual {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 8;
+  static constexpr unsigned MAXMASK = 0x3Fu;
+  const T* x;
+  const T* y;
+  const T* qb;
+  const double* dinv_scale;
+  int n;
+  DevState* st;
+  __device__ T gather(int c) const { return c < n ? x[c] : y[c - n]; }
+  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+    const double px = (double)s1, aty = (double)s2, d = dinv_scale[i];
+    const double rd = px + (double)qb[i] + aty;
+    red[0] = nmax(red[0], fabs(rd));
+    red[1] = nmax(red[1], fabs(rd * d));
+    red[2] = nmax(red[2], fabs(px));
+    red[3] = nmax(red[3], fabs(px * d));
+    red[4] = nmax(red[4], fabs(aty));
+    red[5] = nmax(red[5], fabs(aty * d));
+    red[6] += (double)x[i] * px;
+    red[7] += (double)qb[i] * (double)x[i];
+  }
+  __device__ void operator()(const double* t) const {
+    for (int s = 0; s < 8; ++s) st->norms[6 + s] = t[s];
+  }
+};
+
+// -------------------------------------------------------------------------------- vector kernels
+
+// PCG update (Algorithm 3): x̃ += αp; r += αKp; y = M⁻¹r (not stored); rᵀy; ‖r‖∞.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt,
+                                                       T* __restrict__ r,
+                                                       const T* __restrict__ p,
+                                                       const T* __restrict__ kp,
+                                                       const T* __restrict__ dinv,
+                                                       const DevState* st, double* partials,
+                                                       const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;
+  const T a = (T)st->alpha;
+  double red[2] = {0.0, 0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    xt[i] += a * p[i];
+    const T ri = r[i] + a * kp[i];
+    r[i] = ri;
+    red[0] += (double)ri * (double)(ri * dinv[i]);
+    red[1] = nmax(red[1], fabs((double)ri));
+  }
+  publish<2, 2u>(red, partials);
+}
+
+// β = r⁺ᵀy⁺ / rᵀy, iteration count and the stopping flag (run by k_finalize).
+struct FinPcgUpdate {
+  DevState* st;
+  __device__ void operator()(const double* t) const {
+    const double rz_new = t[0];
+    st->beta = rz_new / st->rz;
+    st->rz = rz_new;
+    st->rnorm = t[1];
+    st->iter += 1;
+    if (rz_new != rz_new) st->breakdown = 1;
+    st->done = (t[1] <= st->thresh || st->iter >= st->maxit || st->breakdown) ? 1 : 0;
+  }
+};
+
+// PCG direction: p = −M⁻¹r + βp.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
+                                                    const T* __restrict__ r,
+                                                    const T* __restrict__ dinv,
+                                                    const DevState* st,
+                                                    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;
+  const T b = (T)st->beta;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    p[i] = -(r[i] * dinv[i]) + b * p[i];
+}
+
+// Jacobi preconditioner (Section 6.3.1): M⁻¹_ii = 1 / (diag(P̄)_i + σ + ρ̄‖Ā_i‖²).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
+                                                   const double* __restrict__ diagP,
+                                                   const double* __restrict__ colsq, double sigma,
+                                                   double rho) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    dinv[i] = (T)(1.0 / (diagP[i] + sigma + rho * colsq[i]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(int n, T* __restrict__ v, T val) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) v[i] = val;
+}
+
+template <typename D, typename S>
+__global__ __launch_bounds__(kBlock) void k_cast(int n, D* __restrict__ d, const S* __restrict__ s) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) d[i] = (D)s[i];
+}
+
+// ‖b‖∞ for a caller-supplied right-hand side.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_absmax(int n, const T* __restrict__ b, double* partials) {
+  double red[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+    red[0] = nmax(red[0], fabs((double)b[i]));
+  publish<1, 1u>(red, partials);
+}
+
+struct FinThresh {
+  DevState* st;
+  double eps;
+  int rel;
+  __device__ void operator()(const double* t) const {
+    st->bnorm = t[0];
+    st->thresh = rel ? eps * t[0] : eps;
+  }
+};
+
+}  // namespace qpg

@@ -1,0 +1,850 @@
+// Solver object and C ABI: device memory, SpMV schedules, the ADMM loop of Algorithm 1 with the
+// inexact reduced-KKT PCG step of Section 6.3, termination (Section 3.1), the PCG tolerance
+// rule (Section 6.3.3) and the ρ̄ update (Section 3.4, 6.3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "kernels.hpp"
+#include "qpg_internal.hpp"
+
+using namespace qpg;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+struct HipError {
+  hipError_t code;
+  const char* what;
+};
+
+#define HIPCHK(expr)                                         \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) throw HipError{e_, #expr};         \
+  } while (0)
+
+int grid_for(int n) {
+  int g = (n + kBlock - 1) / kBlock;
+  return std::max(1, std::min(g, 1024));
+}
+
+// Device arrays of one precision.
+template <typename T>
+struct Prec {
+  T* a_val = nullptr;  // Ā values (CSR)
+  T* b_val = nullptr;  // [P̄ | Āᵀ] values (CSR)
+  T *qb = nullptr, *lb = nullptr, *ub = nullptr;
+  T *x = nullptr, *z = nullptr, *y = nullptr, *xt = nullptr;  // ADMM iterates, PCG solution
+  T *r = nullptr, *p = nullptr, *kp = nullptr, *b = nullptr, *dinv = nullptr;  // PCG (n)
+  T* w = nullptr;   // ρ̄Āp (m)
+  T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
+  T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
+  bool ready = false;
+};
+
+}  // namespace
+
+struct qpg_solver {
+  qpg_settings s{};
+  int32_t n = 0, m = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<void*> allocs;
+
+  // structure shared by both precisions
+  int32_t *a_ptr = nullptr, *a_col = nullptr, *b_ptr = nullptr, *b_split = nullptr,
+          *b_col = nullptr;
+  Item *a_items = nullptr, *b_items = nullptr;
+  int32_t na_items = 0, nb_items = 0;
+  double *diagP = nullptr, *colsq = nullptr, *dscale = nullptr, *escale = nullptr;  // D⁻¹, E⁻¹
+  DevState* st = nullptr;
+  DevState* st_host = nullptr;  // pinned
+  RedBuf rb{};
+  int32_t vgrid = 1;
+
+  Prec<double> p64;
+  Prec<float> p32;
+
+  // host copies
+  std::vector<double> D, E, diagP_h, colsq_h, x_out, y_out, z_out;
+  double c = 1.0, q_norm = 0.0, qb_norm = 0.0;
+  double rho_cur = 0.1;
+  int32_t scaling_passes = 0;
+  int32_t last_pcg = 1;
+  qpg_info info{};
+  std::string err;
+
+  template <typename T>
+  Prec<T>& P();
+
+  template <typename T>
+  T* alloc(size_t count) {
+    void* ptr = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+    allocs.push_back(ptr);
+    return static_cast<T*>(ptr);
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& h) {
+    T* d = alloc<T>(h.size());
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+    return d;
+  }
+  template <typename T, typename S>
+  T* upload_as(const std::vector<S>& h) {
+    std::vector<T> t(h.begin(), h.end());
+    T* d = upload(t);
+    HIPCHK(hipStreamSynchronize(stream));  // t goes out of scope
+    return d;
+  }
+
+  ~qpg_solver() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+  }
+
+  // ----------------------------------------------------------------- launches
+  // SpMV launches; the returned grid size is the number of partials a finalize must combine.
+  template <typename T, class Op>
+  int spmv_A(const Op& op, const int32_t* gate = nullptr) {
+    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(na_items), dim3(kBlock), 0, stream, a_items, a_ptr,
+                       (const int32_t*)nullptr, a_col, P<T>().a_val, op, rb, gate);
+    return na_items;
+  }
+  template <typename T, class Op>
+  int spmv_B(const Op& op, const int32_t* gate = nullptr) {
+    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(nb_items), dim3(kBlock), 0, stream, b_items, b_ptr,
+                       b_split, b_col, P<T>().b_val, op, rb, gate);
+    return nb_items;
+  }
+  // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
+  template <class Op>
+  void finalize(const Op& op, int count, const int32_t* gate = nullptr) {
+    hipLaunchKernelGGL((k_finalize<Op::NS, Op::MAXMASK, Op>), dim3(1), dim3(kBlock), 0, stream,
+                       (const double*)rb.partials, count, op, gate);
+  }
+  template <int NS, unsigned MASK, class Fin>
+  void finalize_fn(const Fin& fin, int count, const int32_t* gate = nullptr) {
+    hipLaunchKernelGGL((k_finalize<NS, MASK, Fin>), dim3(1), dim3(kBlock), 0, stream,
+                       (const double*)rb.partials, count, fin, gate);
+  }
+
+  void sync_state() {
+    HIPCHK(hipMemcpyAsync(st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+
+  template <typename T>
+  void jacobi(double rho) {
+    hipLaunchKernelGGL((k_jacobi<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, P<T>().dinv, diagP,
+                       colsq, s.sigma, rho);
+  }
+
+  // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set.
+  template <typename T>
+  void pcg_iteration(double rho) {
+    Prec<T>& V = P<T>();
+    const int32_t* gate = &st->done;
+    spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho}, gate);
+    OpKp<T> kp{V.p, V.w, V.kp, (T)s.sigma, n, st};
+    finalize(kp, spmv_B<T>(kp, gate), gate);
+    hipLaunchKernelGGL((k_pcg_update<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.xt, V.r, V.p,
+                       V.kp, V.dinv, (const DevState*)st, rb.partials, gate);
+    finalize_fn<2, 2u>(FinPcgUpdate{st}, vgrid, gate);
+    hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, V.r, V.dinv,
+                       (const DevState*)st, gate);
+  }
+
+  // Run PCG iterations after the initialisation kernel until st->done. The first batch is one
+  // shorter than the previous PCG solve took, so that iterations launched after convergence
+  // (which exit at once) stay rare; then one iteration per host check. Returns the count.
+  template <typename T>
+  int pcg_loop(double rho, int maxit) {
+    int issued = 0;
+    int batch = std::max(1, std::min(last_pcg - 1, maxit));
+    for (;;) {
+      int k = std::min(batch, maxit - issued);
+      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho);
+      issued += k;
+      sync_state();
+      if (st_host->done || issued >= maxit) break;
+      batch = 1;
+    }
+    last_pcg = std::max(1, st_host->iter);
+    return st_host->iter;
+  }
+
+  // PCG on K x̃ = b with b already in P<T>().b and the threshold in st; starts from P<T>().xt.
+  template <typename T>
+  int pcg_solve(double rho, int maxit) {
+    Prec<T>& V = P<T>();
+    spmv_A<T>(OpScaled<T>{V.xt, V.w, (T)rho});
+    OpR0<T> r0{V.xt, V.w, V.b, V.dinv, V.r, V.p, (T)s.sigma, n, maxit, st};
+    finalize(r0, spmv_B<T>(r0));
+    return pcg_loop<T>(rho, maxit);
+  }
+
+  template <typename T>
+  void fill(T* v, int count, T val) {
+    if (count > 0)
+      hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(count)), dim3(kBlock), 0, stream, count, v, val);
+  }
+
+  template <typename T>
+  int admm(int k_start, double& rho, double& eps_pcg, int& status, int& fallback_request);
+
+  int solve();
+  void alloc_prec64(const HostProblem& H);
+  void alloc_prec32(const HostProblem& H);
+};
+
+template <>
+Prec<double>& qpg_solver::P<double>() {
+  return p64;
+}
+template <>
+Prec<float>& qpg_solver::P<float>() {
+  return p32;
+}
+
+void qpg_solver::alloc_prec64(const HostProblem& H) {
+  Prec<double>& V = p64;
+  V.a_val = upload(H.a_val);
+  V.b_val = upload(H.b_val);
+  V.qb = upload(H.qb);
+  V.lb = upload(H.lb);
+  V.ub = upload(H.ub);
+  V.x = alloc<double>(n);
+  V.xt = alloc<double>(n);
+  V.r = alloc<double>(n);
+  V.p = alloc<double>(n);
+  V.kp = alloc<double>(n);
+  V.b = alloc<double>(n);
+  V.dinv = alloc<double>(n);
+  V.z = alloc<double>(m);
+  V.y = alloc<double>(m);
+  V.w = alloc<double>(m);
+  V.zt = alloc<double>(m);
+  V.ax = alloc<double>(m);
+  V.ready = true;
+}
+
+void qpg_solver::alloc_prec32(const HostProblem& H) {
+  Prec<float>& V = p32;
+  V.a_val = upload_as<float>(H.a_val);
+  V.b_val = upload_as<float>(H.b_val);
+  V.qb = upload_as<float>(H.qb);
+  V.lb = upload_as<float>(H.lb);
+  V.ub = upload_as<float>(H.ub);
+  V.x = alloc<float>(n);
+  V.xt = alloc<float>(n);
+  V.r = alloc<float>(n);
+  V.p = alloc<float>(n);
+  V.kp = alloc<float>(n);
+  V.b = alloc<float>(n);
+  V.dinv = alloc<float>(n);
+  V.z = alloc<float>(m);
+  V.y = alloc<float>(m);
+  V.w = alloc<float>(m);
+  V.zt = alloc<float>(m);
+  V.ready = true;
+}
+
+// ADMM iterations k_start.. in precision T. Returns the last iteration index. status is set
+// when the loop ends for a reason other than a precision fallback (fallback_request = 1).
+template <typename T>
+int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
+                     int& fallback_request) {
+  Prec<T>& V = P<T>();
+  const double sigma = s.sigma, alpha = s.alpha;
+  const bool fixed_eps = s.pcg_eps_fixed > 0;
+  int cap_streak = 0;
+  double best_ratio = INFINITY;
+  int since_best = 0;
+  int k = k_start;
+  for (; k <= s.max_iter; ++k) {
+    // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
+    OpRhsR0<T> rr{V.x, V.xt, V.qb, V.z, V.y, V.zt, V.dinv, V.r, V.p, (T)sigma, (T)rho,
+                  n, s.pcg_max_iter, s.pcg_rel_test, eps_pcg, st};
+    finalize(rr, spmv_B<T>(rr));
+    // (a3)–(a6) PCG iterations
+    int it = pcg_loop<T>(rho, s.pcg_max_iter);
+    info.pcg_iter_total += it;
+    info.pcg_iter_max = std::max(info.pcg_iter_max, it);
+    if (st_host->breakdown) {
+      if (std::is_same<T, float>::value) {
+        fallback_request = 1;
+        return k;
+      }
+      status = QPG_NUMERICAL_ERROR;
+      return k;
+    }
+    cap_streak = (it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh) ? cap_streak + 1 : 0;
+    if (std::is_same<T, float>::value && cap_streak >= 3) {
+      fallback_request = 1;
+      return k;
+    }
+    // (a7)–(a8) z̃ = Āx̃ fused with relaxation, projection and dual update; x update; with
+    // Āx tracked (FP64) the primal residual of a check iteration comes out of the same pass
+    const bool check = (k % s.check_every == 0 || k == s.max_iter);
+    T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
+    if (check && ax) {
+      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.lb, V.ub, escale, (T)alpha, (T)rho,
+                           (T)(1.0 / rho), n, st};
+      finalize(up, spmv_A<T>(up));
+    } else {
+      spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.lb, V.ub, escale, (T)alpha,
+                                   (T)rho, (T)(1.0 / rho), n, st});
+    }
+    // (a9) residuals and termination every check_every iterations
+    if (check) {
+      if (!ax) {
+        OpRPrim<T> rp{V.x, V.z, escale, st};
+        finalize(rp, spmv_A<T>(rp));
+      }
+      OpRDual<T> rd{V.x, V.y, V.qb, dscale, n, st};
+      finalize(rd, spmv_B<T>(rd));
+      sync_state();
+      const double* nm = st_host->norms;
+      const double prim = nm[1], nAx = nm[3], nz = nm[5];
+      const double dual = nm[7] / c, nPx = nm[9] / c, nAty = nm[11] / c;
+      const double eps_p = s.eps_abs + s.eps_rel * std::max(nAx, nz);
+      const double eps_d = s.eps_abs + s.eps_rel * std::max(std::max(nPx, nAty), q_norm);
+      info.prim_res = prim;
+      info.dual_res = dual;
+      info.obj_val = (0.5 * nm[12] + nm[13]) / c;
+      info.iter = k;
+      if (s.verbose)
+        std::fprintf(stderr, "qpg %5d  prim %.3e (%.1e)  dual %.3e (%.1e)  rho %.3e  pcg %d  %s\n", k,
+                     prim, eps_p, dual, eps_d, rho, it, std::is_same<T, float>::value ? "fp32" : "fp64");
+      if (!(prim == prim) || !(dual == dual)) {
+        if (std::is_same<T, float>::value) {
+          fallback_request = 1;
+          return k;
+        }
+        status = QPG_NUMERICAL_ERROR;
+        return k;
+      }
+      if (prim <= eps_p && dual <= eps_d) {
+        status = QPG_SOLVED;
+        return k;
+      }
+      // FP32 stagnation: no 1% improvement of the worse normalised residual in 20 checks
+      const double ratio = std::max(prim / std::max(eps_p, 1e-300), dual / std::max(eps_d, 1e-300));
+      if (ratio < 0.99 * best_ratio) {
+        best_ratio = ratio;
+        since_best = 0;
+      } else if (++since_best >= 20 && std::is_same<T, float>::value) {
+        fallback_request = 1;
+        return k;
+      }
+      // PCG tolerance from the scaled residuals (Section 6.3.3)
+      if (!fixed_eps)
+        eps_pcg = std::max(s.pcg_lambda * std::sqrt(nm[0] * nm[6]), s.pcg_eps_min);
+      // ρ̄ update (Section 3.4, every rho_update_every iterations, Section 6.3.2)
+      if (s.rho_update_every > 0 && k % s.rho_update_every == 0) {
+        const double num = nm[0] / std::max(std::max(nm[2], nm[4]), 1e-10);
+        const double den = nm[6] / std::max(std::max(std::max(nm[8], nm[10]), qb_norm), 1e-10);
+        if (den > 0 && num > 0) {
+          double est = std::min(std::max(rho * std::sqrt(num / den), 1e-6), 1e6);
+          if (est >= s.rho_update_gate * rho || est <= rho / s.rho_update_gate) {
+            if (est != rho) {
+              rho = est;
+              info.rho_updates++;
+              jacobi<T>(rho);
+            }
+          }
+        }
+      }
+    }
+  }
+  status = QPG_MAX_ITER_REACHED;
+  return std::min(k, s.max_iter);
+}
+
+int qpg_solver::solve() {
+  auto t0 = std::chrono::steady_clock::now();
+  info.status = QPG_UNSOLVED;
+  info.iter = 0;
+  info.pcg_iter_total = 0;
+  info.pcg_iter_max = 0;
+  info.rho_updates = 0;
+  info.fallback_events = 0;
+  info.prim_res = info.dual_res = INFINITY;
+  info.obj_val = NAN;
+  double rho = s.rho;
+  double eps_pcg = s.pcg_eps_fixed > 0 ? s.pcg_eps_fixed : s.pcg_lambda;
+  int status = QPG_UNSOLVED;
+  last_pcg = 1;
+  bool use32 = (s.precision == QPG_MIXED);
+  int k_end = 0;
+  if (use32) {
+    Prec<float>& V = p32;
+    fill(V.x, n, 0.f);
+    fill(V.xt, n, 0.f);
+    fill(V.z, m, 0.f);
+    fill(V.y, m, 0.f);
+    fill(V.zt, m, 0.f);
+    jacobi<float>(rho);
+    int fb = 0;
+    k_end = admm<float>(1, rho, eps_pcg, status, fb);
+    if (fb) {
+      // continue in FP64 from the FP32 iterates
+      info.fallback_events++;
+      use32 = false;
+      Prec<double>& W = p64;
+      hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kBlock), 0, stream, n, W.x, V.x);
+      hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(n)), dim3(kBlock), 0, stream, n, W.xt, V.xt);
+      if (m > 0) {
+        hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(m)), dim3(kBlock), 0, stream, m, W.z, V.z);
+        hipLaunchKernelGGL((k_cast<double, float>), dim3(grid_for(m)), dim3(kBlock), 0, stream, m, W.y, V.y);
+      }
+      // z̃ = Āx̃ and the tracked Āx are recomputed in FP64 from the converted iterates
+      spmv_A<double>(OpScaled<double>{W.xt, W.zt, 1.0});
+      spmv_A<double>(OpScaled<double>{W.x, W.ax, 1.0});
+      jacobi<double>(rho);
+      int fb2 = 0;
+      last_pcg = 1;
+      k_end = admm<double>(k_end, rho, eps_pcg, status, fb2);
+    }
+  } else {
+    Prec<double>& V = p64;
+    fill(V.x, n, 0.0);
+    fill(V.xt, n, 0.0);
+    fill(V.z, m, 0.0);
+    fill(V.y, m, 0.0);
+    fill(V.zt, m, 0.0);
+    fill(V.ax, m, 0.0);
+    jacobi<double>(rho);
+    int fb = 0;
+    k_end = admm<double>(1, rho, eps_pcg, status, fb);
+  }
+  info.status = status;
+  info.rho_final = rho;
+  info.precision_used = use32 ? QPG_MIXED : QPG_FP64;
+  info.precond_used = QPG_PRECOND_JACOBI;
+  // unscaled iterates: x = D x̄, z = E⁻¹ z̄, y = E ȳ / c
+  x_out.assign(n, 0.0);
+  y_out.assign(m, 0.0);
+  z_out.assign(m, 0.0);
+  if (use32) {
+    std::vector<float> xf(n), yf(m), zf(m);
+    HIPCHK(hipMemcpyAsync(xf.data(), p32.x, n * sizeof(float), hipMemcpyDeviceToHost, stream));
+    if (m) {
+      HIPCHK(hipMemcpyAsync(yf.data(), p32.y, m * sizeof(float), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipMemcpyAsync(zf.data(), p32.z, m * sizeof(float), hipMemcpyDeviceToHost, stream));
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int i = 0; i < n; ++i) x_out[i] = xf[i];
+    for (int i = 0; i < m; ++i) {
+      y_out[i] = yf[i];
+      z_out[i] = zf[i];
+    }
+  } else {
+    HIPCHK(hipMemcpyAsync(x_out.data(), p64.x, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    if (m) {
+      HIPCHK(hipMemcpyAsync(y_out.data(), p64.y, m * sizeof(double), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipMemcpyAsync(z_out.data(), p64.z, m * sizeof(double), hipMemcpyDeviceToHost, stream));
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+  HIPCHK(hipGetLastError());
+  for (int i = 0; i < n; ++i) x_out[i] *= D[i];
+  for (int i = 0; i < m; ++i) {
+    y_out[i] = E[i] * y_out[i] / c;
+    z_out[i] = z_out[i] / E[i];
+  }
+  info.iter = k_end;
+  info.solve_time = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return QPG_OK;
+}
+
+// =============================================================================== C ABI
+
+namespace {
+
+int device_error(qpg_solver* h, const HipError& e) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s failed: %s", e.what, hipGetErrorString(e.code));
+  if (h) h->err = buf;
+  else g_setup_error = buf;
+  (void)hipGetLastError();
+  return (e.code == hipErrorOutOfMemory) ? QPG_ERR_OOM : QPG_ERR_DEVICE;
+}
+
+template <typename T>
+void to_device(qpg_solver* h, T* d, const double* src, int count) {
+  std::vector<T> t(src, src + count);
+  if (count) HIPCHK(hipMemcpyAsync(d, t.data(), count * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+}
+
+template <typename T>
+void from_device(qpg_solver* h, double* dst, const T* d, int count) {
+  std::vector<T> t(count);
+  if (count) HIPCHK(hipMemcpyAsync(t.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < count; ++i) dst[i] = (double)t[i];
+}
+
+template <typename T>
+int apply_impl(qpg_solver* h, int op, const double* in, double* out) {
+  Prec<T>& V = h->P<T>();
+  const int n = h->n, m = h->m;
+  switch (op) {
+    case QPG_OP_A:
+      to_device<T>(h, V.p, in, n);
+      h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)1});
+      from_device<T>(h, out, V.w, m);
+      break;
+    case QPG_OP_AT:
+      to_device<T>(h, V.w, in, m);
+      h->spmv_B<T>(OpB<T>{nullptr, V.w, V.kp, n});
+      from_device<T>(h, out, V.kp, n);
+      break;
+    case QPG_OP_P:
+      to_device<T>(h, V.p, in, n);
+      h->spmv_B<T>(OpB<T>{V.p, nullptr, V.kp, n});
+      from_device<T>(h, out, V.kp, n);
+      break;
+    case QPG_OP_K:
+      to_device<T>(h, V.p, in, n);
+      h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)h->rho_cur});
+      h->spmv_B<T>(OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, n, h->st});
+      from_device<T>(h, out, V.kp, n);
+      break;
+    default:
+      h->err = "qpg_apply: unknown operator";
+      return QPG_ERR_ARG;
+  }
+  HIPCHK(hipGetLastError());
+  return QPG_OK;
+}
+
+template <typename T>
+int pcg_impl(qpg_solver* h, const double* b, const double* x0, double eps, int rel, int maxit,
+             double* x, int32_t* iters, double* rnorm) {
+  Prec<T>& V = h->P<T>();
+  to_device<T>(h, V.b, b, h->n);
+  to_device<T>(h, V.xt, x0, h->n);
+  h->jacobi<T>(h->rho_cur);
+  hipLaunchKernelGGL((k_absmax<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, (const T*)V.b,
+                     h->rb.partials);
+  h->finalize_fn<1, 1u>(FinThresh{h->st, eps, rel}, h->vgrid);
+  h->last_pcg = 1;
+  int it = h->pcg_solve<T>(h->rho_cur, maxit);
+  from_device<T>(h, x, V.xt, h->n);
+  if (iters) *iters = it;
+  if (rnorm) *rnorm = h->st_host->rnorm;
+  HIPCHK(hipGetLastError());
+  return h->st_host->breakdown ? QPG_ERR_STATE : QPG_OK;
+}
+
+template <typename T>
+int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
+  Prec<T>& V = h->P<T>();
+  auto launch = [&]() {
+    switch (kernel) {
+      case QPG_KERNEL_SPMV_A:
+        h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)h->rho_cur});
+        break;
+      case QPG_KERNEL_SPMV_B:
+        h->spmv_B<T>(OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, h->n, h->st});
+        break;
+      case QPG_KERNEL_PCG_UPDATE:
+        hipLaunchKernelGGL((k_pcg_update<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.xt,
+                           V.r, V.p, V.kp, V.dinv, (const DevState*)h->st, h->rb.partials,
+                           (const int32_t*)nullptr);
+        break;
+      default:
+        hipLaunchKernelGGL((k_pcg_dir<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.p, V.r,
+                           V.dinv, (const DevState*)h->st, (const int32_t*)nullptr);
+    }
+  };
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  launch();
+  HIPCHK(hipEventRecord(e0, h->stream));
+  for (int i = 0; i < reps; ++i) launch();
+  HIPCHK(hipEventRecord(e1, h->stream));
+  HIPCHK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipGetLastError());
+  *avg_us = 1e3 * (double)ms / reps;
+  return QPG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t reps, double* avg_us) {
+  if (!h || !avg_us || reps < 1 || kernel < 0 || kernel > QPG_KERNEL_PCG_DIR) return QPG_ERR_ARG;
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    if (precision == QPG_FP64) return time_kernel_impl<double>(h, kernel, reps, avg_us);
+    if (precision == QPG_MIXED && h->p32.ready) return time_kernel_impl<float>(h, kernel, reps, avg_us);
+    h->err = "qpg_time_kernel: precision not available";
+    return QPG_ERR_STATE;
+  } catch (const HipError& e) {
+    return device_error(h, e);
+  }
+}
+
+int qpg_default_settings(qpg_settings* s) {
+  if (!s) return QPG_ERR_ARG;
+  std::memset(s, 0, sizeof(*s));
+  s->rho = 0.1;
+  s->sigma = 1e-6;
+  s->alpha = 1.6;
+  s->eps_abs = 1e-3;
+  s->eps_rel = 1e-3;
+  s->max_iter = 4000;
+  s->check_every = 5;
+  s->rho_update_every = 10;
+  s->rho_update_gate = 1.0;
+  s->pcg_lambda = 0.15;
+  s->pcg_eps_min = 1e-7;
+  s->pcg_eps_fixed = 0.0;
+  s->pcg_max_iter = 100;
+  s->pcg_rel_test = 1;
+  s->scaling_iters = 10;
+  s->precision = QPG_FP64;
+  s->precond = QPG_PRECOND_JACOBI;
+  s->device = 0;
+  s->stream = nullptr;
+  s->verbose = 0;
+  return QPG_OK;
+}
+
+int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qpg_csc* A,
+              const double* l, const double* u, const qpg_settings* settings) {
+  g_setup_error.clear();
+  if (!out) {
+    g_setup_error = "out: null";
+    return QPG_ERR_ARG;
+  }
+  *out = nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  HostProblem H;
+  std::string msg;
+  int rc = prepare(P_triu, q, A, l, u, settings, &H, &msg);
+  if (rc) {
+    g_setup_error = msg;
+    return rc;
+  }
+  qpg_solver* h = new (std::nothrow) qpg_solver();
+  if (!h) {
+    g_setup_error = "host allocation failed";
+    return QPG_ERR_OOM;
+  }
+  h->s = *settings;
+  h->n = H.n;
+  h->m = H.m;
+  h->device = settings->device;
+  h->stream = static_cast<hipStream_t>(settings->stream);
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    Plan pa = make_plan(H.a_ptr, H.m);
+    Plan pb = make_plan(H.b_ptr, H.n);
+    if (pa.items.empty()) pa.items.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+    if (pb.items.empty()) pb.items.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+    h->na_items = (int32_t)pa.items.size();
+    h->nb_items = (int32_t)pb.items.size();
+    h->vgrid = grid_for(h->n);
+    h->a_ptr = h->upload(H.a_ptr);
+    h->a_col = h->upload(H.a_col);
+    h->b_ptr = h->upload(H.b_ptr);
+    h->b_split = h->upload(H.b_split);
+    h->b_col = h->upload(H.b_col);
+    h->a_items = h->upload(pa.items);
+    h->b_items = h->upload(pb.items);
+    h->diagP = h->upload(H.diagP);
+    h->colsq = h->upload(H.colsq);
+    std::vector<double> dinv(H.n), einv(H.m);
+    for (int i = 0; i < H.n; ++i) dinv[i] = 1.0 / H.D[i];
+    for (int i = 0; i < H.m; ++i) einv[i] = 1.0 / H.E[i];
+    h->dscale = h->upload(dinv);
+    h->escale = h->upload(einv);
+    int maxgrid = std::max(std::max(h->na_items, h->nb_items), 1024);
+    h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
+    int slots = std::max(std::max(pa.n_chunk_slots, pb.n_chunk_slots), 1);
+    int tickets = std::max(std::max(pa.n_split_rows, pb.n_split_rows), 1);
+    h->rb.chunk_part = h->alloc<double>(3 * (size_t)slots);
+    h->rb.chunk_ticket = h->alloc<uint32_t>(tickets);
+    HIPCHK(hipMemsetAsync(h->rb.chunk_ticket, 0, tickets * sizeof(uint32_t), h->stream));
+    h->st = h->alloc<DevState>(1);
+    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream));
+    HIPCHK(hipHostMalloc((void**)&h->st_host, sizeof(DevState), hipHostMallocDefault));
+    std::memset(h->st_host, 0, sizeof(DevState));
+    h->alloc_prec64(H);
+    if (settings->precision == QPG_MIXED) h->alloc_prec32(H);
+    for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);
+    for (double* v : {h->p64.z, h->p64.y, h->p64.w, h->p64.zt, h->p64.ax}) h->fill(v, h->m, 0.0);
+    if (h->p32.ready) {
+      for (float* v : {h->p32.x, h->p32.xt, h->p32.r, h->p32.p, h->p32.kp, h->p32.b}) h->fill(v, h->n, 0.f);
+      for (float* v : {h->p32.z, h->p32.y, h->p32.w, h->p32.zt}) h->fill(v, h->m, 0.f);
+    }
+    h->D = H.D;
+    h->E = H.E;
+    h->c = H.c;
+    h->q_norm = H.q_norm_unscaled;
+    double qbn = 0.0;
+    for (double v : H.qb) qbn = std::max(qbn, std::fabs(v));
+    h->qb_norm = qbn;
+    h->scaling_passes = H.scaling_passes;
+    h->rho_cur = settings->rho;
+    h->jacobi<double>(h->rho_cur);
+    if (h->p32.ready) h->jacobi<float>(h->rho_cur);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    int code = device_error(nullptr, e);
+    delete h;
+    return code;
+  }
+  h->info.scaling_passes = h->scaling_passes;
+  h->info.setup_time = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return QPG_OK;
+}
+
+int qpg_solve(qpg_solver* h) {
+  if (!h) return QPG_ERR_ARG;
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    return h->solve();
+  } catch (const HipError& e) {
+    return device_error(h, e);
+  }
+}
+
+int qpg_get_x(const qpg_solver* h, double* x) {
+  if (!h || !x) return QPG_ERR_ARG;
+  if (h->x_out.size() != (size_t)h->n) return QPG_ERR_STATE;
+  std::copy(h->x_out.begin(), h->x_out.end(), x);
+  return QPG_OK;
+}
+
+int qpg_get_y(const qpg_solver* h, double* y) {
+  if (!h || (!y && h->m > 0)) return QPG_ERR_ARG;
+  if (h->y_out.size() != (size_t)h->m) return QPG_ERR_STATE;
+  std::copy(h->y_out.begin(), h->y_out.end(), y);
+  return QPG_OK;
+}
+
+int qpg_get_z(const qpg_solver* h, double* z) {
+  if (!h || (!z && h->m > 0)) return QPG_ERR_ARG;
+  if (h->z_out.size() != (size_t)h->m) return QPG_ERR_STATE;
+  std::copy(h->z_out.begin(), h->z_out.end(), z);
+  return QPG_OK;
+}
+
+int qpg_get_info(const qpg_solver* h, qpg_info* info) {
+  if (!h || !info) return QPG_ERR_ARG;
+  *info = h->info;
+  return QPG_OK;
+}
+
+int qpg_get_scaling(const qpg_solver* h, double* D, double* E, double* c) {
+  if (!h || !D || (!E && h->m > 0) || !c) return QPG_ERR_ARG;
+  std::copy(h->D.begin(), h->D.end(), D);
+  std::copy(h->E.begin(), h->E.end(), E);
+  *c = h->c;
+  return QPG_OK;
+}
+
+int qpg_apply(qpg_solver* h, int32_t op, int32_t precision, const double* in, double* out) {
+  if (!h || !in || !out) return QPG_ERR_ARG;
+  if (op == QPG_OP_AT && h->m == 0) {
+    std::fill(out, out + h->n, 0.0);
+    return QPG_OK;
+  }
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    if (precision == QPG_FP64) return apply_impl<double>(h, op, in, out);
+    if (precision == QPG_MIXED) {
+      if (!h->p32.ready) {
+        h->err = "qpg_apply: float copies exist only when setup used QPG_MIXED";
+        return QPG_ERR_STATE;
+      }
+      return apply_impl<float>(h, op, in, out);
+    }
+    h->err = "qpg_apply: bad precision";
+    return QPG_ERR_ARG;
+  } catch (const HipError& e) {
+    return device_error(h, e);
+  }
+}
+
+int qpg_pcg(qpg_solver* h, int32_t precision, const double* b, const double* x0, double eps,
+            int32_t rel, int32_t max_iter, double* x, int32_t* iters, double* rnorm) {
+  if (!h || !b || !x0 || !x || max_iter < 0 || !(eps >= 0)) return QPG_ERR_ARG;
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    if (precision == QPG_FP64) return pcg_impl<double>(h, b, x0, eps, rel, max_iter, x, iters, rnorm);
+    if (precision == QPG_MIXED && h->p32.ready)
+      return pcg_impl<float>(h, b, x0, eps, rel, max_iter, x, iters, rnorm);
+    h->err = "qpg_pcg: precision not available";
+    return QPG_ERR_STATE;
+  } catch (const HipError& e) {
+    return device_error(h, e);
+  }
+}
+
+int qpg_set_rho(qpg_solver* h, double rho) {
+  if (!h || !(rho > 0) || !std::isfinite(rho)) return QPG_ERR_ARG;
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    h->rho_cur = rho;
+    h->jacobi<double>(rho);
+    if (h->p32.ready) h->jacobi<float>(rho);
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } catch (const HipError& e) {
+    return device_error(h, e);
+  }
+  return QPG_OK;
+}
+
+int qpg_cleanup(qpg_solver* h) {
+  if (!h) return QPG_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return QPG_OK;
+}
+
+const char* qpg_error_string(int code) {
+  switch (code) {
+    case QPG_OK: return "ok";
+    case QPG_ERR_ARG: return "invalid argument";
+    case QPG_ERR_DATA: return "invalid problem data";
+    case QPG_ERR_SIZE: return "problem too large for int32 indexing";
+    case QPG_ERR_DEVICE: return "HIP device error";
+    case QPG_ERR_OOM: return "out of memory";
+    case QPG_ERR_STATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char* qpg_last_error(const qpg_solver* h) {
+  if (!h) return g_setup_error.c_str();
+  return h->err.c_str();
+}
+
+}  // extern "C"

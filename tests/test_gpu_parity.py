@@ -1,0 +1,291 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle. Needs an MI355X.
+
+Tolerances:
+* SpMV FP64: max_i |Δ_i| / (|M||x|)_i ≤ 1e-12 (the device's reduction order costs at most
+  ≈ rowlen·2⁻⁵³ relative to (|M||x|)_i; the oracle sums in extended precision).
+* SpMV FP32: ≤ 1e-5 on the same scale (inputs rounded to 2⁻²⁴, accumulation in float).
+* Final answer at eps_abs = eps_rel = 1e-5: |f − f*| ≤ 1e-4·max(1, |f*|) and
+  ‖x − x*‖∞ ≤ 1e-3·‖x*‖∞ against the oracle run to 1e-9. Portfolio instances are compared at
+  eps 1e-6: the method itself (the oracle's exact-solve ADMM) stopped at 1e-5 is 3.5e-4 off in
+  objective on them, so no implementation can meet the bar there at 1e-5.
+* Iterate trace with a near-exact PCG (fixed relative tolerance 1e-13) against the oracle's
+  direct KKT solves: 1e-8 relative.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import admm as o_admm
+from oracle import kkt as o_kkt
+from oracle import pcg as o_pcg
+from oracle import ruiz as o_ruiz
+from oracle import spmv as o_spmv
+from paper_1912_04263_amd import problems as pr
+from paper_1912_04263_amd import qpg
+
+pytestmark = pytest.mark.gpu
+
+PROBLEMS = ["random_c0", "random_small", "lasso_small", "portfolio_small", "svm_small", "random2_small"]
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def problem(name):
+    return pr.make(name)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_solution(name):
+    p = problem(name)
+    return o_admm.solve(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, eps_abs=1e-9, eps_rel=1e-9,
+                        max_iter=50000)
+
+
+def spmv_err(M, x, y):
+    M = sp.csr_matrix(M)
+    ref = o_spmv.spmv(M.indptr, M.indices, M.data, x)
+    scale = o_spmv.spmv_abs(M.indptr, M.indices, M.data, x)
+    d = np.abs(y - ref)
+    zero = scale == 0
+    assert np.all(d[zero] == 0)
+    return float(np.max(d[~zero] / scale[~zero])) if np.any(~zero) else 0.0
+
+
+def skewed_problem(seed=0):
+    """Rows of length 0, 1, 7, 300, 3000 (one workgroup), 40000 (split into chunks)."""
+    rng = np.random.default_rng(seed)
+    n = 50000
+    lens = [0, 1, 7, 300, 3000, 40000, 2, 0, 5] + [3] * 5000
+    rows, cols = [], []
+    for i, L in enumerate(lens):
+        c = np.sort(rng.choice(n, L, replace=False))
+        rows.append(np.full(L, i))
+        cols.append(c)
+    r = np.concatenate(rows)
+    c = np.concatenate(cols)
+    A = sp.csc_matrix((rng.standard_normal(r.size), (r, c)), shape=(len(lens), n))
+    d = rng.uniform(0.5, 2.0, n)
+    P = sp.diags(d).tocsc()
+    q = rng.standard_normal(n)
+    m = len(lens)
+    return P, q, A, -np.ones(m), np.ones(m)
+
+
+# ------------------------------------------------------------------------------ SpMV
+@pytest.mark.parametrize("name", PROBLEMS + ["skewed"])
+def test_spmv_fp64_matches_oracle(name):
+    say("spmv fp64", name)
+    if name == "skewed":
+        P, q, A, l, u = skewed_problem()
+    else:
+        p = problem(name)
+        P, q, A, l, u = p.P_triu, p.q, p.A, p.l, p.u
+    Pf = sp.csr_matrix(sp.triu(P) + sp.triu(P, 1).T)
+    rng = np.random.default_rng(1)
+    with qpg.Solver(P, q, A, l, u, scaling_iters=0) as s:
+        x = rng.standard_normal(s.n)
+        y = rng.standard_normal(s.m)
+        assert spmv_err(A, x, s.apply(qpg.QPG_OP_A, x)) <= 1e-12
+        assert spmv_err(sp.csr_matrix(A).T, y, s.apply(qpg.QPG_OP_AT, y)) <= 1e-12
+        assert spmv_err(Pf, x, s.apply(qpg.QPG_OP_P, x)) <= 1e-12
+        # bitwise reproducible
+        assert np.array_equal(s.apply(qpg.QPG_OP_A, x), s.apply(qpg.QPG_OP_A, x))
+
+
+@pytest.mark.parametrize("name", ["lasso_small", "skewed"])
+def test_spmv_fp32_error_bound(name):
+    say("spmv fp32", name)
+    if name == "skewed":
+        P, q, A, l, u = skewed_problem(2)
+    else:
+        p = problem(name)
+        P, q, A, l, u = p.P_triu, p.q, p.A, p.l, p.u
+    rng = np.random.default_rng(3)
+    with qpg.Solver(P, q, A, l, u, scaling_iters=0, precision="mixed") as s:
+        x = rng.standard_normal(s.n)
+        assert spmv_err(A, x, s.apply(qpg.QPG_OP_A, x, qpg.QPG_MIXED)) <= 1e-5
+        y = rng.standard_normal(s.m)
+        assert spmv_err(sp.csr_matrix(A).T, y, s.apply(qpg.QPG_OP_AT, y, qpg.QPG_MIXED)) <= 1e-5
+
+
+def scaled_data(s, p):
+    D, E, c = s.scaling()
+    Pb = (c * sp.diags(D) @ p.P_full() @ sp.diags(D)).tocsr()
+    Ab = (sp.diags(E) @ sp.csr_matrix(p.A) @ sp.diags(D)).tocsr()
+    return D, E, c, Pb, Ab
+
+
+@pytest.mark.parametrize("name", ["random_c0", "lasso_small", "svm_small"])
+def test_scaling_and_kkt_operator_match_oracle(name):
+    say("ruiz + K operator", name)
+    p = problem(name)
+    with qpg.Solver.from_qp(p) as s:
+        D, E, c, Pb, Ab = scaled_data(s, p)
+        Do, Eo, co, *_ = o_ruiz.ruiz(p.P_full(), p.q, sp.csr_matrix(p.A), 10)
+        np.testing.assert_allclose(D, Do, rtol=1e-12)
+        np.testing.assert_allclose(E, Eo, rtol=1e-12)
+        assert c == pytest.approx(co, rel=1e-12)
+        s.set_rho(0.37)
+        v = np.random.default_rng(4).standard_normal(s.n)
+        K = o_pcg.reduced_kkt_matvec(Pb, Ab, 1e-6, 0.37)
+        ref = K(v)
+        got = s.apply(qpg.QPG_OP_K, v)
+        scale = np.abs(Pb) @ np.abs(v) + 1e-6 * np.abs(v) + 0.37 * (abs(Ab).T @ (abs(Ab) @ np.abs(v)))
+        assert np.max(np.abs(got - ref) / scale) <= 1e-11
+
+
+# ------------------------------------------------------------------------------ PCG
+@pytest.mark.parametrize("name", ["random_c0", "lasso_small", "portfolio_small"])
+def test_pcg_matches_oracle(name):
+    say("pcg", name)
+    p = problem(name)
+    with qpg.Solver.from_qp(p) as s:
+        D, E, c, Pb, Ab = scaled_data(s, p)
+        rho = 0.1
+        s.set_rho(rho)
+        b = np.random.default_rng(5).standard_normal(s.n)
+        K = o_pcg.reduced_kkt_matvec(Pb, Ab, 1e-6, rho)
+        minv = 1.0 / o_pcg.jacobi_diag(Pb, Ab, 1e-6, rho)
+        for eps in (1e-3, 1e-8):
+            xo, ko, rno, _ = o_pcg.pcg(K, b, np.zeros(s.n), minv, eps, 2000)
+            xg, kg, rng_, broke = s.pcg(b, eps=eps, max_iter=2000)
+            assert not broke
+            assert abs(kg - ko) <= max(1, ko // 50), (kg, ko)
+            assert rng_ <= eps * np.max(np.abs(b)) * (1 + 1e-6)
+            if kg == ko:
+                np.testing.assert_allclose(xg, xo, rtol=0, atol=1e-8 * np.max(np.abs(xo)))
+
+
+def test_pcg_pins_on_gpu():
+    say("pcg pins")
+    rng = np.random.default_rng(6)
+    n = 3000
+    d = rng.uniform(0.5, 4.0, n)
+    P = sp.diags(d).tocsc()
+    A = sp.csc_matrix((0, n))
+    with qpg.Solver(P, np.zeros(n), A, np.zeros(0), np.zeros(0), scaling_iters=0) as s:
+        b = rng.standard_normal(n)
+        x, k, rn, broke = s.pcg(b, eps=1e-14, max_iter=50)
+        assert k == 1 and not broke  # diagonal K with the Jacobi preconditioner: one step
+        np.testing.assert_allclose(x, b / (d + 1e-6), rtol=1e-14)
+        x2, k2, _, _ = s.pcg(b, x0=x, eps=1e-12, max_iter=50)
+        assert k2 == 0  # warm start at the solution
+
+
+# ------------------------------------------------------------------------------ ADMM
+@pytest.mark.parametrize("name", ["random_c0", "lasso_small"])
+def test_admm_iterates_match_oracle_trace(name):
+    say("admm trace", name)
+    p = problem(name)
+    K = 20
+    ref = o_admm.solve(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, eps_abs=0.0, eps_rel=0.0,
+                       max_iter=K, adaptive_rho=False, record=K)
+    for k in (1, 2, 5, 20):
+        st = qpg.default_settings(rho_update_every=0, pcg_eps_fixed=1e-13, pcg_max_iter=3000,
+                                  check_every=10000, max_iter=k)
+        with qpg.Solver.from_qp(p, settings=st) as s:
+            s.solve()
+            xk, zk, yk = ref.trace[k - 1]
+            for got, want in ((s.x(), xk), (s.z(), zk), (s.y(), yk)):
+                assert np.max(np.abs(got - want)) <= 1e-8 * max(1.0, np.max(np.abs(want))), k
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", PROBLEMS)
+def test_final_answer_matches_oracle(name, precision):
+    say("final answer", name, precision)
+    p = problem(name)
+    ref = oracle_solution(name)
+    assert ref.status == "solved"
+    eps = 1e-6 if name.startswith("portfolio") else 1e-5
+    with qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, max_iter=20000, precision=precision) as s:
+        info = s.solve()
+        assert info.status == "solved", info
+        x = s.x()
+        fs = ref.obj
+        assert abs(info.obj_val - fs) <= 1e-4 * max(1.0, abs(fs))
+        assert np.max(np.abs(x - ref.x)) <= 1e-3 * np.max(np.abs(ref.x))
+        # the reported objective is the objective of the returned x
+        f = o_kkt.objective(p.P_full(), p.q, x)
+        assert abs(f - info.obj_val) <= 1e-6 * max(1.0, abs(f))
+        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, x, s.y(), s.z())
+        eps_p = eps + eps * max(rep["norms"]["Ax"], rep["norms"]["z"])
+        eps_d = eps + eps * max(rep["norms"]["Px"], rep["norms"]["Aty"], rep["norms"]["q"])
+        assert rep["prim"] <= 1.01 * eps_p and rep["dual"] <= 1.01 * eps_d
+        # z and the scaled bounds are held in float in mixed precision
+        box_tol = 1e-6 if precision == "mixed" else 1e-9
+        assert rep["box"] <= box_tol * (1 + rep["norms"]["z"])
+
+
+def test_closed_form_box_on_gpu():
+    say("closed form box")
+    rng = np.random.default_rng(31)
+    n = 5000
+    pd = rng.uniform(0.1, 5, n)
+    q = rng.standard_normal(n) * 3
+    l, u = -rng.random(n), rng.random(n)
+    with qpg.Solver(sp.diags(pd).tocsc(), q, sp.identity(n, format="csc"), l, u, eps_abs=1e-9,
+                    eps_rel=1e-9, pcg_eps_min=1e-13, max_iter=20000) as s:
+        assert s.solve().status == "solved"
+        x = np.clip(-q / pd, l, u)
+        np.testing.assert_allclose(s.x(), x, atol=1e-7)
+        np.testing.assert_allclose(s.y(), -(pd * x + q), atol=1e-7)
+
+
+def test_unconstrained_without_constraints():
+    say("m = 0")
+    p = problem("random_c0")
+    n = p.n
+    with qpg.Solver(p.P_triu, p.q, sp.csc_matrix((0, n)), np.zeros(0), np.zeros(0), eps_abs=1e-9,
+                    eps_rel=1e-9, pcg_eps_min=1e-13, max_iter=20000) as s:
+        assert s.solve().status == "solved"
+        P = p.P_full().toarray()
+        np.testing.assert_allclose(s.x(), -np.linalg.solve(P, p.q), rtol=1e-6, atol=1e-6)
+
+
+def test_repeat_solves_are_bitwise_identical():
+    say("determinism")
+    p = problem("lasso_small")
+    with qpg.Solver.from_qp(p) as s:
+        i1 = s.solve()
+        x1, y1 = s.x(), s.y()
+        i2 = s.solve()
+        assert np.array_equal(x1, s.x()) and np.array_equal(y1, s.y())
+        assert i1.iter == i2.iter and i1.pcg_iter_total == i2.pcg_iter_total
+
+
+def test_full_size_lasso_sampled_spmv_and_kkt_certificate():
+    """The bench workload at full size (Ad 100000×10000, 1%): sampled rows of every SpMV against
+    exact row sums, and the optimality certificate of the returned solution."""
+    say("lasso full size")
+    p = problem("lasso_c1")
+    rng = np.random.default_rng(7)
+    with qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5, scaling_iters=0) as s:
+        A = sp.csr_matrix(p.A)
+        At = sp.csr_matrix(p.A.T)
+        x = rng.standard_normal(s.n)
+        y = rng.standard_normal(s.m)
+        ax = s.apply(qpg.QPG_OP_A, x)
+        aty = s.apply(qpg.QPG_OP_AT, y)
+        for i in rng.choice(s.m, 300, replace=False):
+            ex = o_spmv.row_exact(A.indptr, A.indices, A.data, x, i)
+            sc = float(np.abs(A[i].data) @ np.abs(x[A[i].indices])) if A[i].nnz else 0.0
+            assert abs(ax[i] - ex) <= 1e-12 * sc
+        for i in rng.choice(s.n, 300, replace=False):
+            ex = o_spmv.row_exact(At.indptr, At.indices, At.data, y, i)
+            sc = float(np.abs(At[i].data) @ np.abs(y[At[i].indices])) if At[i].nnz else 0.0
+            assert abs(aty[i] - ex) <= 1e-12 * sc
+    with qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5, max_iter=20000) as s:
+        info = s.solve()
+        say("lasso full size solve", info)
+        assert info.status == "solved"
+        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, s.x(), s.y(), s.z())
+        eps_p = 1e-5 + 1e-5 * max(rep["norms"]["Ax"], rep["norms"]["z"])
+        eps_d = 1e-5 + 1e-5 * max(rep["norms"]["Px"], rep["norms"]["Aty"], rep["norms"]["q"])
+        assert rep["prim"] <= 1.01 * eps_p and rep["dual"] <= 1.01 * eps_d

@@ -157,6 +157,20 @@ def test_kkt_matrix_is_quasi_definite_inertia():
     assert (ev > 0).sum() == 6 and (ev < 0).sum() == 10
 
 
+def test_reduced_pcg_route_matches_direct_route():
+    """Section 6.3: solving the reduced system (eq. kkt_red_sc) by PCG and recovering z̃ = Āx̃
+    gives the same ADMM iterates as the direct solve of eq. kkt with R = ρ̄I."""
+    P, q, A, l, u = _small_qp(24, n=12, m=18)
+    a = admm.solve(sp.csr_matrix(P), q, sp.csr_matrix(A), l, u, eps_abs=0, eps_rel=0, max_iter=30,
+                   adaptive_rho=False, record=30)
+    b = admm.solve(sp.csr_matrix(P), q, sp.csr_matrix(A), l, u, eps_abs=0, eps_rel=0, max_iter=30,
+                   adaptive_rho=False, record=30, linsys="pcg", pcg_tol=1e-14)
+    for (xa, za, ya), (xb, zb, yb) in zip(a.trace, b.trace):
+        np.testing.assert_allclose(xb, xa, rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(zb, za, rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(yb, ya, rtol=1e-9, atol=1e-11)
+
+
 # ---------------------------------------------------------------- ADMM closed forms
 def _solve(P, q, A, l, u, **kw):
     kw.setdefault("eps_abs", 1e-11)
