@@ -59,9 +59,25 @@ __device__ __forceinline__ double comb(int s, double a, double b) {
   return ((MAXMASK >> s) & 1u) ? nmax(a, b) : a + b;
 }
 
+// Two values of one vector entry, loaded together (one 16-byte / 8-byte access).
 template <typename T>
-__device__ __forceinline__ T ldnt(const T* p) {
-  return __builtin_nontemporal_load(p);
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <typename T>
+using pair_t = typename Pair<T>::type;
+
+// Matrix-stream load. Plain loads: on gfx950 the non-temporal variant measured ~30% slower for
+// this access pattern (coalesced value/index streams interleaved with random gathers).
+template <typename T>
+__device__ __forceinline__ T ldm(const T* p) {
+  return *p;
 }
 
 // 256-thread reduction of NS slots; result valid in thread 0. Fixed order: deterministic.
@@ -129,9 +145,9 @@ __device__ __forceinline__ T wave_sum(T x, int width) {
 // Generic CSR SpMV with fused epilogue. Op supplies:
 //   static constexpr int NS;            reduction slots (0: none)
 //   static constexpr unsigned MAXMASK;  bit s set: slot s is an ∞-norm (max), else a sum
-//   static constexpr int NV;            products per entry: 1, or 2 (second vector, Op::gather2)
-//   T gather(int col) const;            multiplied vector, first product
-//   T gather2(int col) const;           second product's vector (NV == 2)
+//   static constexpr int NV;            products per entry: 1, or 2
+//   T gather(int col) const;            multiplied vector (NV == 1)
+//   T2 gather_pair(int col) const;      both multiplied vectors from one load (NV == 2)
 //   void epilogue(int row, T s1, T s2, T s3, double* red) const;
 //        s1 / s2: first product summed over the entries before / from split[row];
 //        s3: second product summed over the entries from split[row]
@@ -163,10 +179,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const Item* __restrict__ items,
 #pragma unroll 8
     for (int t = tid; t < cnt; t += kBlock) {
       const int k = it.k0 + t;
-      const T v = ldnt(&val[k]);
-      const int c = ldnt(&col[k]);
-      prod[0][t] = v * op.gather(c);
-      if constexpr (NV == 2) prod[NV - 1][t] = v * op.gather2(c);
+      const T v = ldm(&val[k]);
+      const int c = ldm(&col[k]);
+      if constexpr (NV == 2) {
+        const auto g = op.gather_pair(c);
+        prod[0][t] = v * g.x;
+        prod[NV - 1][t] = v * g.y;
+      } else {
+        prod[0][t] = v * op.gather(c);
+      }
     }
     __syncthreads();
     const int nrows = it.r1 - it.r0;
@@ -198,14 +219,22 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const Item* __restrict__ items,
     T s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll 4
     for (int k = it.k0 + tid; k < it.k1; k += kBlock) {
-      const T v = ldnt(&val[k]);
-      const int c = ldnt(&col[k]);
-      const T pr = v * op.gather(c);
-      if (k < sp) {
-        s1 += pr;
+      const T v = ldm(&val[k]);
+      const int c = ldm(&col[k]);
+      if constexpr (NV == 2) {
+        const auto g = op.gather_pair(c);
+        if (k < sp) {
+          s1 += v * g.x;
+        } else {
+          s2 += v * g.x;
+          s3 += v * g.y;
+        }
       } else {
-        s2 += pr;
-        if constexpr (NV == 2) s3 += v * op.gather2(c);
+        const T pr = v * op.gather(c);
+        if (k < sp)
+          s1 += pr;
+        else
+          s2 += pr;
       }
     }
     s1 = wave_sum(s1, 64);
@@ -258,9 +287,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const Item* __restrict__ items,
   __device__ void side() const {}
 #define QPG_NO_FIN \
   __device__ void operator()(const double*) const {}
-#define QPG_ONE_PRODUCT                      \
-  static constexpr int NV = 1;               \
-  __device__ T gather2(int) const { return T(0); }
+#define QPG_ONE_PRODUCT \
+  static constexpr int NV = 1;
 
 // out = scale · (M v)   (M = Ā, or the whole of B with v = [vp; vat])
 template <typename T>
@@ -297,11 +325,12 @@ struct OpB {
 };
 
 // Right-hand side of the reduced KKT system (eq. kkt_red_sc) and the warm-started PCG residual
-// (Algorithm 3 initialisation) in one pass over B = [P̄ | Āᵀ], with z̃ = Āx̃ kept from the
-// previous ADMM iteration's update pass:
+// (Algorithm 3 initialisation) in one pass over B = [P̄ | Āᵀ]:
 //   b  = σx − q̄ + Āᵀ(ρ̄z − y)                                   (only ‖b‖∞ is needed)
-//   r⁰ = Kx̃ − b = P̄x̃ + σ(x̃ − x) + q̄ + Āᵀ(ρ̄(z̃ − z) + y)
+//   r⁰ = Kx̃ − b = P̄x̃ + σ(x̃ − x) + q̄ + Āᵀ(ρ̄(z̃ − z) + y),  z̃ = Āx̃
 //   p⁰ = −M⁻¹r⁰;  rᵀM⁻¹r;  ‖r‖∞.
+// The two m-vectors ρ̄(z̃ − z) + y and ρ̄z − y are written, interleaved, by the update pass that
+// produced z̃, z and y (OpUpdate), so each Āᵀ entry costs a single gather.
 template <typename T>
 struct OpRhsR0 {
   QPG_NO_SIDE
@@ -311,25 +340,17 @@ struct OpRhsR0 {
   const T* x;
   const T* xt;
   const T* qb;
-  const T* z;
-  const T* y;
-  const T* zt;
+  const pair_t<T>* vw;  // (ρ̄(z̃ − z) + y, ρ̄z − y)
   const T* dinv;
   T* r;
   T* p;
-  T sigma, rho;
+  T sigma;
   int n, maxit, rel;
   double eps;
   DevState* st;
-  __device__ T gather(int c) const {
-    if (c < n) return xt[c];
-    const int j = c - n;
-    return rho * (zt[j] - z[j]) + y[j];
-  }
-  __device__ T gather2(int c) const {
-    if (c < n) return T(0);
-    const int j = c - n;
-    return rho * z[j] - y[j];
+  __device__ pair_t<T> gather_pair(int c) const {
+    if (c < n) return pair_t<T>{xt[c], T(0)};
+    return vw[c - n];
   }
   __device__ void epilogue(int i, T s1, T s2, T s3, double* red) const {
     const T xi = x[i];
@@ -426,7 +447,8 @@ struct OpKp {
 
 // ADMM update (Algorithm 1, relaxation, projection and dual steps) fused with z̃ = Āx̃
 // (Section 4) over the rows of Ā:
-//   v = αz̃ + (1−α)z;  z⁺ = Π_[l̄,ū](v + y/ρ̄);  y ← y + ρ̄(v − z⁺);  z̃ kept for the next r⁰;
+//   v = αz̃ + (1−α)z;  z⁺ = Π_[l̄,ū](v + y/ρ̄);  y ← y + ρ̄(v − z⁺);  z̃ kept, and the pair
+//   (ρ̄(z̃ − z⁺) + y⁺, ρ̄z⁺ − y⁺) written for the next OpRhsR0;
 //   Āx ← αz̃ + (1−α)Āx when `ax` is tracked (x ← αx̃ + (1−α)x makes this exact);
 //   side task: x ← αx̃ + (1−α)x.
 // With CHECK, the primal residual r̄_p = Āx − z⁺ and its norms are reduced as well:
@@ -442,6 +464,7 @@ struct OpUpdate {
   T* y;
   T* zt;
   T* ax;
+  pair_t<T>* vw;
   const T* lb;
   const T* ub;
   const double* einv;
@@ -455,9 +478,11 @@ struct OpUpdate {
     T zn = v + yi * rho_inv;
     zn = zn < lb[i] ? lb[i] : zn;
     zn = zn > ub[i] ? ub[i] : zn;
-    y[i] = yi + rho * (v - zn);
+    const T yn = yi + rho * (v - zn);
+    y[i] = yn;
     z[i] = zn;
     zt[i] = s1;
+    vw[i] = pair_t<T>{rho * (s1 - zn) + yn, rho * zn - yn};
     if (ax) {
       const T a = alpha * s1 + (T(1) - alpha) * ax[i];
       ax[i] = a;
@@ -601,6 +626,15 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
                                                    double rho) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
     dinv[i] = (T)(1.0 / (diagP[i] + sigma + rho * colsq[i]));
+}
+
+// (ρ̄(z̃ − z) + y, ρ̄z − y) from z̃, z, y — after ρ̄ changes or the precision switches.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pairs(int m, pair_t<T>* __restrict__ vw,
+                                                  const T* __restrict__ zt, const T* __restrict__ z,
+                                                  const T* __restrict__ y, T rho) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock)
+    vw[i] = pair_t<T>{rho * (zt[i] - z[i]) + y[i], rho * z[i] - y[i]};
 }
 
 template <typename T>

@@ -48,6 +48,7 @@ struct Prec {
   T* w = nullptr;   // ρ̄Āp (m)
   T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
   T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
+  pair_t<T>* vw = nullptr;  // (ρ̄(z̃ − z) + y, ρ̄z − y) for the next right-hand side (m)
   bool ready = false;
 };
 
@@ -196,6 +197,14 @@ struct qpg_solver {
   }
 
   template <typename T>
+  void pairs(double rho) {
+    Prec<T>& V = P<T>();
+    if (m > 0)
+      hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, m, V.vw,
+                         (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho);
+  }
+
+  template <typename T>
   void fill(T* v, int count, T val) {
     if (count > 0)
       hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(count)), dim3(kBlock), 0, stream, count, v, val);
@@ -237,6 +246,7 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.w = alloc<double>(m);
   V.zt = alloc<double>(m);
   V.ax = alloc<double>(m);
+  V.vw = alloc<double2>(m);
   V.ready = true;
 }
 
@@ -258,6 +268,7 @@ void qpg_solver::alloc_prec32(const HostProblem& H) {
   V.y = alloc<float>(m);
   V.w = alloc<float>(m);
   V.zt = alloc<float>(m);
+  V.vw = alloc<float2>(m);
   V.ready = true;
 }
 
@@ -275,8 +286,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   int k = k_start;
   for (; k <= s.max_iter; ++k) {
     // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
-    OpRhsR0<T> rr{V.x, V.xt, V.qb, V.z, V.y, V.zt, V.dinv, V.r, V.p, (T)sigma, (T)rho,
-                  n, s.pcg_max_iter, s.pcg_rel_test, eps_pcg, st};
+    OpRhsR0<T> rr{V.x, V.xt, V.qb, V.vw, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
+                  s.pcg_rel_test, eps_pcg, st};
     finalize(rr, spmv_B<T>(rr));
     // (a3)–(a6) PCG iterations
     int it = pcg_loop<T>(rho, s.pcg_max_iter);
@@ -300,12 +311,12 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     const bool check = (k % s.check_every == 0 || k == s.max_iter);
     T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
     if (check && ax) {
-      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.lb, V.ub, escale, (T)alpha, (T)rho,
-                           (T)(1.0 / rho), n, st};
+      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.vw, V.lb, V.ub, escale, (T)alpha,
+                           (T)rho, (T)(1.0 / rho), n, st};
       finalize(up, spmv_A<T>(up));
     } else {
-      spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.lb, V.ub, escale, (T)alpha,
-                                   (T)rho, (T)(1.0 / rho), n, st});
+      spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.vw, V.lb, V.ub, escale,
+                                   (T)alpha, (T)rho, (T)(1.0 / rho), n, st});
     }
     // (a9) residuals and termination every check_every iterations
     if (check) {
@@ -363,6 +374,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
               rho = est;
               info.rho_updates++;
               jacobi<T>(rho);
+              pairs<T>(rho);
             }
           }
         }
@@ -396,6 +408,7 @@ int qpg_solver::solve() {
     fill(V.z, m, 0.f);
     fill(V.y, m, 0.f);
     fill(V.zt, m, 0.f);
+    pairs<float>(rho);
     jacobi<float>(rho);
     int fb = 0;
     k_end = admm<float>(1, rho, eps_pcg, status, fb);
@@ -413,6 +426,7 @@ int qpg_solver::solve() {
       // z̃ = Āx̃ and the tracked Āx are recomputed in FP64 from the converted iterates
       spmv_A<double>(OpScaled<double>{W.xt, W.zt, 1.0});
       spmv_A<double>(OpScaled<double>{W.x, W.ax, 1.0});
+      pairs<double>(rho);
       jacobi<double>(rho);
       int fb2 = 0;
       last_pcg = 1;
@@ -426,6 +440,7 @@ int qpg_solver::solve() {
     fill(V.y, m, 0.0);
     fill(V.zt, m, 0.0);
     fill(V.ax, m, 0.0);
+    pairs<double>(rho);
     jacobi<double>(rho);
     int fb = 0;
     k_end = admm<double>(1, rho, eps_pcg, status, fb);
