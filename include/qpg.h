@@ -49,7 +49,14 @@ extern "C" {
                        ratios accumulated in double; falls back to QPG_FP64 on PCG stagnation */
 
 /* Preconditioner of the PCG step. */
-#define QPG_PRECOND_JACOBI 0 /* M = diag(P + σI + ρ̄AᵀA) (Section 6.3.1) */
+#define QPG_PRECOND_JACOBI 0  /* M = diag(P + σI + ρ̄AᵀA) (Section 6.3.1) */
+#define QPG_PRECOND_LEARNED 1 /* M⁻¹_ii = softplus(g_i) / K_ii with g from a message-passing network
+                                 over the graph of A (parameters in settings.precond_weights): still
+                                 diagonal and positive, so Algorithm 3 is unchanged; softplus = 1
+                                 reproduces Jacobi. Not part of the paper. */
+
+/* Number of float parameters of the learned preconditioner's network. */
+#define QPG_NET_NPARAMS 16705
 
 /* Compressed sparse column matrix (Section 5.3.3), zero-based. Row indices within each column
  * must be strictly increasing. CSC of A is the CSR of Aᵀ (Section 5.3.3). */
@@ -83,6 +90,12 @@ typedef struct {
   int32_t device;         /* HIP device ordinal, default 0 */
   void* stream;           /* hipStream_t for all device work, NULL = null stream */
   int32_t verbose;        /* 1: one line per residual check on stderr */
+  const float* precond_weights; /* QPG_NET_NPARAMS floats for QPG_PRECOND_LEARNED (copied at setup) */
+  int32_t precond_trial;  /* 1 (default): before the first PCG solve and after each ρ̄ change, solve
+                             once with each preconditioner from the same warm start and keep the
+                             learned one only if it needs fewer iterations (or, both capped, ends
+                             with a smaller residual); 0: always learned. In both cases a capped or
+                             broken-down learned solve switches to Jacobi. */
 } qpg_settings;
 
 typedef struct {
@@ -101,6 +114,9 @@ typedef struct {
   int32_t precond_used;    /* preconditioner the last solve finished with */
   int32_t fallback_events; /* precision fallbacks taken during the last solve */
   int32_t scaling_passes;  /* Ruiz passes performed at setup */
+  int32_t precond_trials;  /* learned-vs-Jacobi trials run in the last solve */
+  int32_t precond_learned_chosen; /* trials won by the learned preconditioner */
+  int32_t precond_switches; /* runtime switches from learned to Jacobi (capped or broken-down PCG) */
 } qpg_info;
 
 typedef struct qpg_solver qpg_solver;
@@ -169,6 +185,37 @@ int qpg_set_rho(qpg_solver* h, double rho);
 #define QPG_KERNEL_PCG_UPDATE 2
 #define QPG_KERNEL_PCG_DIR 3
 int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t reps, double* avg_us);
+
+/* K_ii = diag(P̄)_i + σ + ρ̄‖Ā_i‖² of the scaled reduced KKT matrix (Section 6.3.1), n values. */
+int qpg_get_kdiag(const qpg_solver* h, double rho, double* kdiag);
+
+/* Hutchinson estimate of diag(K⁻¹) for K = P̄ + σI + ρ̄ĀᵀĀ: (1/s) Σ_k z_k ∘ K⁻¹z_k over the s
+ * probes z_k given in `signs` (s×n, row-major, entries ±1 only; the caller draws them), each
+ * K⁻¹z_k by the solver's own Jacobi PCG (Algorithm 3) from 0 to ‖r‖∞ ≤ eps‖z‖∞ or max_iter.
+ * Writes n values to diag. Not part of the paper: training targets of QPG_PRECOND_LEARNED. */
+int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho, double eps,
+                   int32_t max_iter, double* diag);
+
+/* Network of the learned preconditioner, its evaluation on a solver's problem and its training
+ * (forward, loss, backward and Adam all run on the device). Not part of the paper.
+ *   create:    params = QPG_NET_NPARAMS floats, or NULL for the seeded initialisation (output
+ *              layer at softplus = 1, i.e. Jacobi); bf16 = 1: dense layers on bf16 MFMA with
+ *              float32 accumulation (bf16 weights; activations and gradients as hi + lo bf16
+ *              pairs), 0: plain float32 (validation)
+ *   forward:   g (n floats, may be NULL) = pre-softplus outputs for the solver's problem at ρ̄
+ *   loss_grad: loss = mean_i (e_i − ē)², e_i = log softplus(g_i) − target_i (target = log(ĥ_i K_ii),
+ *              n floats); gradient kept on the device for adam_step and copied to grad if non-NULL
+ *   adam_step: Adam (β = 0.9, 0.999, ε = 1e-8) on the float32 master parameters
+ * The net and the solver must be on the same device. */
+typedef struct qpg_net qpg_net;
+int qpg_net_create(qpg_net** out, const float* params, uint64_t seed, int32_t bf16, int32_t device);
+int qpg_net_get_params(const qpg_net* net, float* params);
+int qpg_net_set_params(qpg_net* net, const float* params);
+int qpg_net_forward(qpg_net* net, qpg_solver* h, double rho, float* g);
+int qpg_net_loss_grad(qpg_net* net, qpg_solver* h, double rho, const float* target, double* loss,
+                      float* grad);
+int qpg_net_adam_step(qpg_net* net, float lr);
+int qpg_net_destroy(qpg_net* net);
 
 /* Release all device and host memory of h. NULL is accepted. */
 int qpg_cleanup(qpg_solver* h);

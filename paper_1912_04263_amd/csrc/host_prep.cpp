@@ -87,7 +87,9 @@ int validate_settings(const qpg_settings* s, std::string* msg) {
             s->pcg_max_iter >= 1 && (s->pcg_rel_test == 0 || s->pcg_rel_test == 1) &&
             s->scaling_iters >= 0 && s->scaling_iters <= 100 &&
             (s->precision == QPG_FP64 || s->precision == QPG_MIXED) &&
-            s->precond == QPG_PRECOND_JACOBI && s->device >= 0;
+            (s->precond == QPG_PRECOND_JACOBI ||
+             (s->precond == QPG_PRECOND_LEARNED && s->precond_weights != nullptr)) &&
+            (s->precond_trial == 0 || s->precond_trial == 1) && s->device >= 0;
   if (!ok) {
     *msg = "settings: value out of range";
     return QPG_ERR_ARG;

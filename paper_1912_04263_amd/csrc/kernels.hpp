@@ -437,10 +437,11 @@ struct OpKp {
     if (t[0] > 0.0) {
       st->alpha = st->rz / t[0];
     } else {
-      // p = 0 only when r = 0 (an exact solve); any other pᵀKp ≤ 0 or NaN is a breakdown
+      // with M⁻¹ positive, p = 0 only when r = 0 (an exact solve); any other pᵀKp ≤ 0 or NaN
+      // is a breakdown
       st->alpha = 0.0;
       st->done = 1;
-      if (!(t[0] == 0.0 && st->rz == 0.0)) st->breakdown = 1;
+      if (!(t[0] == 0.0 && st->rnorm == 0.0)) st->breakdown = 1;
     }
   }
 };

@@ -1,231 +1,13 @@
 // Solver object and C ABI: device memory, SpMV schedules, the ADMM loop of Algorithm 1 with the
 // inexact reduced-KKT PCG step of Section 6.3, termination (Section 3.1), the PCG tolerance
 // rule (Section 6.3.3) and the ρ̄ update (Section 3.4, 6.3.2).
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <chrono>
-#include <cmath>
-#include <cstdio>
-#include <cstring>
-#include <string>
-#include <type_traits>
-#include <vector>
-
-#include "kernels.hpp"
-#include "qpg_internal.hpp"
+#include "solver_internal.hpp"
 
 using namespace qpg;
 
 namespace {
-
 thread_local std::string g_setup_error;
-
-struct HipError {
-  hipError_t code;
-  const char* what;
-};
-
-#define HIPCHK(expr)                                         \
-  do {                                                       \
-    hipError_t e_ = (expr);                                  \
-    if (e_ != hipSuccess) throw HipError{e_, #expr};         \
-  } while (0)
-
-int grid_for(int n) {
-  int g = (n + kBlock - 1) / kBlock;
-  return std::max(1, std::min(g, 1024));
-}
-
-// Device arrays of one precision.
-template <typename T>
-struct Prec {
-  T* a_val = nullptr;  // Ā values (CSR)
-  T* b_val = nullptr;  // [P̄ | Āᵀ] values (CSR)
-  T *qb = nullptr, *lb = nullptr, *ub = nullptr;
-  T *x = nullptr, *z = nullptr, *y = nullptr, *xt = nullptr;  // ADMM iterates, PCG solution
-  T *r = nullptr, *p = nullptr, *kp = nullptr, *b = nullptr, *dinv = nullptr;  // PCG (n)
-  T* w = nullptr;   // ρ̄Āp (m)
-  T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
-  T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
-  pair_t<T>* vw = nullptr;  // (ρ̄(z̃ − z) + y, ρ̄z − y) for the next right-hand side (m)
-  bool ready = false;
-};
-
 }  // namespace
-
-struct qpg_solver {
-  qpg_settings s{};
-  int32_t n = 0, m = 0;
-  int device = 0;
-  hipStream_t stream = nullptr;
-  std::vector<void*> allocs;
-
-  // structure shared by both precisions
-  int32_t *a_ptr = nullptr, *a_col = nullptr, *b_ptr = nullptr, *b_split = nullptr,
-          *b_col = nullptr;
-  Item *a_items = nullptr, *b_items = nullptr;
-  int32_t na_items = 0, nb_items = 0;
-  double *diagP = nullptr, *colsq = nullptr, *dscale = nullptr, *escale = nullptr;  // D⁻¹, E⁻¹
-  DevState* st = nullptr;
-  DevState* st_host = nullptr;  // pinned
-  RedBuf rb{};
-  int32_t vgrid = 1;
-
-  Prec<double> p64;
-  Prec<float> p32;
-
-  // host copies
-  std::vector<double> D, E, diagP_h, colsq_h, x_out, y_out, z_out;
-  double c = 1.0, q_norm = 0.0, qb_norm = 0.0;
-  double rho_cur = 0.1;
-  int32_t scaling_passes = 0;
-  int32_t last_pcg = 1;
-  qpg_info info{};
-  std::string err;
-
-  template <typename T>
-  Prec<T>& P();
-
-  template <typename T>
-  T* alloc(size_t count) {
-    void* ptr = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-    if (e != hipSuccess) throw HipError{e, "hipMalloc"};
-    allocs.push_back(ptr);
-    return static_cast<T*>(ptr);
-  }
-  template <typename T>
-  T* upload(const std::vector<T>& h) {
-    T* d = alloc<T>(h.size());
-    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream));
-    return d;
-  }
-  template <typename T, typename S>
-  T* upload_as(const std::vector<S>& h) {
-    std::vector<T> t(h.begin(), h.end());
-    T* d = upload(t);
-    HIPCHK(hipStreamSynchronize(stream));  // t goes out of scope
-    return d;
-  }
-
-  ~qpg_solver() {
-    for (void* p : allocs) (void)hipFree(p);
-    if (st_host) (void)hipHostFree(st_host);
-  }
-
-  // ----------------------------------------------------------------- launches
-  // SpMV launches; the returned grid size is the number of partials a finalize must combine.
-  template <typename T, class Op>
-  int spmv_A(const Op& op, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(na_items), dim3(kBlock), 0, stream, a_items, a_ptr,
-                       (const int32_t*)nullptr, a_col, P<T>().a_val, op, rb, gate);
-    return na_items;
-  }
-  template <typename T, class Op>
-  int spmv_B(const Op& op, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(nb_items), dim3(kBlock), 0, stream, b_items, b_ptr,
-                       b_split, b_col, P<T>().b_val, op, rb, gate);
-    return nb_items;
-  }
-  // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
-  template <class Op>
-  void finalize(const Op& op, int count, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_finalize<Op::NS, Op::MAXMASK, Op>), dim3(1), dim3(kBlock), 0, stream,
-                       (const double*)rb.partials, count, op, gate);
-  }
-  template <int NS, unsigned MASK, class Fin>
-  void finalize_fn(const Fin& fin, int count, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_finalize<NS, MASK, Fin>), dim3(1), dim3(kBlock), 0, stream,
-                       (const double*)rb.partials, count, fin, gate);
-  }
-
-  void sync_state() {
-    HIPCHK(hipMemcpyAsync(st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
-  }
-
-  template <typename T>
-  void jacobi(double rho) {
-    hipLaunchKernelGGL((k_jacobi<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, P<T>().dinv, diagP,
-                       colsq, s.sigma, rho);
-  }
-
-  // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set.
-  template <typename T>
-  void pcg_iteration(double rho) {
-    Prec<T>& V = P<T>();
-    const int32_t* gate = &st->done;
-    spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho}, gate);
-    OpKp<T> kp{V.p, V.w, V.kp, (T)s.sigma, n, st};
-    finalize(kp, spmv_B<T>(kp, gate), gate);
-    hipLaunchKernelGGL((k_pcg_update<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.xt, V.r, V.p,
-                       V.kp, V.dinv, (const DevState*)st, rb.partials, gate);
-    finalize_fn<2, 2u>(FinPcgUpdate{st}, vgrid, gate);
-    hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, V.r, V.dinv,
-                       (const DevState*)st, gate);
-  }
-
-  // Run PCG iterations after the initialisation kernel until st->done. The first batch is one
-  // shorter than the previous PCG solve took, so that iterations launched after convergence
-  // (which exit at once) stay rare; then one iteration per host check. Returns the count.
-  template <typename T>
-  int pcg_loop(double rho, int maxit) {
-    int issued = 0;
-    int batch = std::max(1, std::min(last_pcg - 1, maxit));
-    for (;;) {
-      int k = std::min(batch, maxit - issued);
-      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho);
-      issued += k;
-      sync_state();
-      if (st_host->done || issued >= maxit) break;
-      batch = 1;
-    }
-    last_pcg = std::max(1, st_host->iter);
-    return st_host->iter;
-  }
-
-  // PCG on K x̃ = b with b already in P<T>().b and the threshold in st; starts from P<T>().xt.
-  template <typename T>
-  int pcg_solve(double rho, int maxit) {
-    Prec<T>& V = P<T>();
-    spmv_A<T>(OpScaled<T>{V.xt, V.w, (T)rho});
-    OpR0<T> r0{V.xt, V.w, V.b, V.dinv, V.r, V.p, (T)s.sigma, n, maxit, st};
-    finalize(r0, spmv_B<T>(r0));
-    return pcg_loop<T>(rho, maxit);
-  }
-
-  template <typename T>
-  void pairs(double rho) {
-    Prec<T>& V = P<T>();
-    if (m > 0)
-      hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, m, V.vw,
-                         (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho);
-  }
-
-  template <typename T>
-  void fill(T* v, int count, T val) {
-    if (count > 0)
-      hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(count)), dim3(kBlock), 0, stream, count, v, val);
-  }
-
-  template <typename T>
-  int admm(int k_start, double& rho, double& eps_pcg, int& status, int& fallback_request);
-
-  int solve();
-  void alloc_prec64(const HostProblem& H);
-  void alloc_prec32(const HostProblem& H);
-};
-
-template <>
-Prec<double>& qpg_solver::P<double>() {
-  return p64;
-}
-template <>
-Prec<float>& qpg_solver::P<float>() {
-  return p32;
-}
 
 void qpg_solver::alloc_prec64(const HostProblem& H) {
   Prec<double>& V = p64;
@@ -280,6 +62,17 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   Prec<T>& V = P<T>();
   const double sigma = s.sigma, alpha = s.alpha;
   const bool fixed_eps = s.pcg_eps_fixed > 0;
+  // Preconditioner policy. Jacobi (Section 6.3.1), or the learned diagonal: with trials on, the
+  // first PCG solve and the first one after every ρ̄ change run with both preconditioners from the
+  // same warm start, and the learned one is kept only if it needs fewer iterations (or, when both
+  // hit the cap, ends with a smaller residual); a capped learned solve falls back to Jacobi.
+  const bool learned_ok = (s.precond == QPG_PRECOND_LEARNED);
+  bool trial = learned_ok && s.precond_trial;
+  bool use_learned = learned_ok && !s.precond_trial;
+  if (use_learned)
+    learned_dinv<T>(rho);
+  else
+    jacobi<T>(rho);
   int cap_streak = 0;
   double best_ratio = INFINITY;
   int since_best = 0;
@@ -288,9 +81,39 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
     OpRhsR0<T> rr{V.x, V.xt, V.qb, V.vw, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
                   s.pcg_rel_test, eps_pcg, st};
-    finalize(rr, spmv_B<T>(rr));
-    // (a3)–(a6) PCG iterations
-    int it = pcg_loop<T>(rho, s.pcg_max_iter);
+    int it;
+    if (trial) {
+      copy(V.b, (const T*)V.xt, n);  // the warm start, kept for the second run
+      learned_dinv<T>(rho);
+      finalize(rr, spmv_B<T>(rr));
+      const int it_l = pcg_loop<T>(rho, s.pcg_max_iter);
+      const double rn_l = st_host->rnorm;
+      const bool cap_l = it_l >= s.pcg_max_iter && rn_l > st_host->thresh;
+      const bool broke_l = st_host->breakdown != 0;
+      copy(V.xt, (const T*)V.b, n);
+      jacobi<T>(rho);
+      finalize(rr, spmv_B<T>(rr));
+      it = pcg_loop<T>(rho, s.pcg_max_iter);
+      const bool cap_j = it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh;
+      use_learned = !broke_l && ((!cap_l && it_l < it) || (cap_l && cap_j && rn_l < st_host->rnorm));
+      info.precond_trials++;
+      if (use_learned) {
+        info.precond_learned_chosen++;
+        learned_dinv<T>(rho);
+      }
+      info.pcg_iter_total += it_l;
+      trial = false;
+    } else {
+      finalize(rr, spmv_B<T>(rr));
+      // (a3)–(a6) PCG iterations
+      it = pcg_loop<T>(rho, s.pcg_max_iter);
+      if (use_learned && (st_host->breakdown ||
+                          (it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh))) {
+        use_learned = false;  // runtime guard
+        info.precond_switches++;
+        jacobi<T>(rho);
+      }
+    }
     info.pcg_iter_total += it;
     info.pcg_iter_max = std::max(info.pcg_iter_max, it);
     if (st_host->breakdown) {
@@ -299,6 +122,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         return k;
       }
       status = QPG_NUMERICAL_ERROR;
+      last_precond_learned = use_learned;
       return k;
     }
     cap_streak = (it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh) ? cap_streak + 1 : 0;
@@ -345,10 +169,12 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
           return k;
         }
         status = QPG_NUMERICAL_ERROR;
+        last_precond_learned = use_learned;
         return k;
       }
       if (prim <= eps_p && dual <= eps_d) {
         status = QPG_SOLVED;
+        last_precond_learned = use_learned;
         return k;
       }
       // FP32 stagnation: no 1% improvement of the worse normalised residual in 20 checks
@@ -373,7 +199,12 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
             if (est != rho) {
               rho = est;
               info.rho_updates++;
-              jacobi<T>(rho);
+              if (learned_ok && s.precond_trial)
+                trial = true;
+              else if (use_learned)
+                learned_dinv<T>(rho);
+              else
+                jacobi<T>(rho);
               pairs<T>(rho);
             }
           }
@@ -382,6 +213,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     }
   }
   status = QPG_MAX_ITER_REACHED;
+  last_precond_learned = use_learned;
   return std::min(k, s.max_iter);
 }
 
@@ -393,6 +225,9 @@ int qpg_solver::solve() {
   info.pcg_iter_max = 0;
   info.rho_updates = 0;
   info.fallback_events = 0;
+  info.precond_trials = 0;
+  info.precond_learned_chosen = 0;
+  info.precond_switches = 0;
   info.prim_res = info.dual_res = INFINITY;
   info.obj_val = NAN;
   double rho = s.rho;
@@ -409,7 +244,6 @@ int qpg_solver::solve() {
     fill(V.y, m, 0.f);
     fill(V.zt, m, 0.f);
     pairs<float>(rho);
-    jacobi<float>(rho);
     int fb = 0;
     k_end = admm<float>(1, rho, eps_pcg, status, fb);
     if (fb) {
@@ -427,7 +261,6 @@ int qpg_solver::solve() {
       spmv_A<double>(OpScaled<double>{W.xt, W.zt, 1.0});
       spmv_A<double>(OpScaled<double>{W.x, W.ax, 1.0});
       pairs<double>(rho);
-      jacobi<double>(rho);
       int fb2 = 0;
       last_pcg = 1;
       k_end = admm<double>(k_end, rho, eps_pcg, status, fb2);
@@ -441,14 +274,13 @@ int qpg_solver::solve() {
     fill(V.zt, m, 0.0);
     fill(V.ax, m, 0.0);
     pairs<double>(rho);
-    jacobi<double>(rho);
     int fb = 0;
     k_end = admm<double>(1, rho, eps_pcg, status, fb);
   }
   info.status = status;
   info.rho_final = rho;
+  info.precond_used = last_precond_learned ? QPG_PRECOND_LEARNED : QPG_PRECOND_JACOBI;
   info.precision_used = use32 ? QPG_MIXED : QPG_FP64;
-  info.precond_used = QPG_PRECOND_JACOBI;
   // unscaled iterates: x = D x̄, z = E⁻¹ z̄, y = E ȳ / c
   x_out.assign(n, 0.0);
   y_out.assign(m, 0.0);
@@ -644,6 +476,8 @@ int qpg_default_settings(qpg_settings* s) {
   s->device = 0;
   s->stream = nullptr;
   s->verbose = 0;
+  s->precond_weights = nullptr;
+  s->precond_trial = 1;
   return QPG_OK;
 }
 
@@ -715,6 +549,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
       for (float* v : {h->p32.x, h->p32.xt, h->p32.r, h->p32.p, h->p32.kp, h->p32.b}) h->fill(v, h->n, 0.f);
       for (float* v : {h->p32.z, h->p32.y, h->p32.w, h->p32.zt}) h->fill(v, h->m, 0.f);
     }
+    h->nnzA = (int32_t)H.a_col.size();
+    h->nnzB = (int32_t)H.b_col.size();
+    h->diagP_h = H.diagP;
+    h->colsq_h = H.colsq;
     h->D = H.D;
     h->E = H.E;
     h->c = H.c;
@@ -726,6 +564,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->rho_cur = settings->rho;
     h->jacobi<double>(h->rho_cur);
     if (h->p32.ready) h->jacobi<float>(h->rho_cur);
+    if (settings->precond == QPG_PRECOND_LEARNED) {
+      h->precond_weights.assign(settings->precond_weights, settings->precond_weights + QPG_NET_NPARAMS);
+      h->learned_prepare();  // graph and message-passing trunk: once per setup
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {

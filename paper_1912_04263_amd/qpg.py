@@ -20,7 +20,8 @@ QPG_OK = 0
 QPG_ERR_ARG, QPG_ERR_DATA, QPG_ERR_SIZE, QPG_ERR_DEVICE, QPG_ERR_OOM, QPG_ERR_STATE = -1, -2, -3, -4, -5, -6
 QPG_UNSOLVED, QPG_SOLVED, QPG_MAX_ITER_REACHED, QPG_NUMERICAL_ERROR = 0, 1, 2, 3
 QPG_FP64, QPG_MIXED = 0, 1
-QPG_PRECOND_JACOBI = 0
+QPG_PRECOND_JACOBI, QPG_PRECOND_LEARNED = 0, 1
+QPG_NET_NPARAMS = 16705
 QPG_OP_A, QPG_OP_AT, QPG_OP_P, QPG_OP_K = 0, 1, 2, 3
 QPG_KERNEL_SPMV_A, QPG_KERNEL_SPMV_B, QPG_KERNEL_PCG_UPDATE, QPG_KERNEL_PCG_DIR = 0, 1, 2, 3
 STATUS = {0: "unsolved", 1: "solved", 2: "max_iter_reached", 3: "numerical_error"}
@@ -40,7 +41,8 @@ class Settings(C.Structure):
                 ("pcg_eps_min", C.c_double), ("pcg_eps_fixed", C.c_double),
                 ("pcg_max_iter", C.c_int32), ("pcg_rel_test", C.c_int32),
                 ("scaling_iters", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
-                ("device", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
+                ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -49,11 +51,15 @@ class Info(C.Structure):
                 ("prim_res", C.c_double), ("dual_res", C.c_double), ("rho_final", C.c_double),
                 ("setup_time", C.c_double), ("solve_time", C.c_double),
                 ("precision_used", C.c_int32), ("precond_used", C.c_int32),
-                ("fallback_events", C.c_int32), ("scaling_passes", C.c_int32)]
+                ("fallback_events", C.c_int32), ("scaling_passes", C.c_int32),
+                ("precond_trials", C.c_int32), ("precond_learned_chosen", C.c_int32),
+                ("precond_switches", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
 _PI = C.POINTER(C.c_int32)
+_PF = C.POINTER(C.c_float)
+_PB = C.POINTER(C.c_int8)
 _lib = None
 
 # name -> (restype, argtypes); the full exported surface of include/qpg.h
@@ -73,6 +79,15 @@ SIGNATURES = {
     "qpg_set_rho": (C.c_int, [C.c_void_p, C.c_double]),
     "qpg_time_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _PD]),
     "qpg_cleanup": (C.c_int, [C.c_void_p]),
+    "qpg_get_kdiag": (C.c_int, [C.c_void_p, C.c_double, _PD]),
+    "qpg_hutchinson": (C.c_int, [C.c_void_p, _PB, C.c_int32, C.c_double, C.c_double, C.c_int32, _PD]),
+    "qpg_net_create": (C.c_int, [C.POINTER(C.c_void_p), _PF, C.c_uint64, C.c_int32, C.c_int32]),
+    "qpg_net_get_params": (C.c_int, [C.c_void_p, _PF]),
+    "qpg_net_set_params": (C.c_int, [C.c_void_p, _PF]),
+    "qpg_net_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, _PF]),
+    "qpg_net_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, _PF, _PD, _PF]),
+    "qpg_net_adam_step": (C.c_int, [C.c_void_p, C.c_float]),
+    "qpg_net_destroy": (C.c_int, [C.c_void_p]),
     "qpg_error_string": (C.c_char_p, [C.c_int]),
     "qpg_last_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -110,12 +125,22 @@ def _iptr(a):
 def default_settings(**kw) -> Settings:
     s = Settings()
     lib().qpg_default_settings(C.byref(s))
+    keep = []
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": QPG_FP64, "mixed": QPG_MIXED}[v]
+        if k == "precond" and isinstance(v, str):
+            v = {"jacobi": QPG_PRECOND_JACOBI, "learned": QPG_PRECOND_LEARNED}[v]
+        if k == "precond_weights":
+            w = np.ascontiguousarray(v, dtype=np.float32)
+            if w.size != QPG_NET_NPARAMS:
+                raise ValueError(f"precond_weights needs {QPG_NET_NPARAMS} floats")
+            keep.append(w)
+            v = w.ctypes.data_as(_PF)
         if not hasattr(s, k):
             raise TypeError(f"unknown setting {k}")
         setattr(s, k, v)
+    s._keep = keep  # arrays referenced by pointer fields (read during setup)
     return s
 
 
@@ -135,6 +160,10 @@ class SolveInfo:
     precision_used: str
     fallback_events: int
     scaling_passes: int
+    precond_used: str = "jacobi"
+    precond_trials: int = 0
+    precond_learned_chosen: int = 0
+    precond_switches: int = 0
 
 
 class _CscArrays:
@@ -187,7 +216,9 @@ class Solver:
         return SolveInfo(STATUS.get(i.status, str(i.status)), i.iter, i.pcg_iter_total, i.pcg_iter_max,
                          i.rho_updates, i.obj_val, i.prim_res, i.dual_res, i.rho_final, i.setup_time,
                          i.solve_time, "mixed" if i.precision_used == QPG_MIXED else "fp64",
-                         i.fallback_events, i.scaling_passes)
+                         i.fallback_events, i.scaling_passes,
+                         "learned" if i.precond_used == QPG_PRECOND_LEARNED else "jacobi",
+                         i.precond_trials, i.precond_learned_chosen, i.precond_switches)
 
     def x(self):
         out = np.empty(self.n)
@@ -237,6 +268,21 @@ class Solver:
         self._check(lib().qpg_time_kernel(self._h, kernel, precision, reps, C.byref(us)))
         return us.value
 
+    def kdiag(self, rho: float):
+        out = np.empty(self.n)
+        self._check(lib().qpg_get_kdiag(self._h, float(rho), _dptr(out)))
+        return out
+
+    def hutchinson(self, signs, rho: float, eps: float = 1e-10, max_iter: int = 5000):
+        """Hutchinson estimate of diag(K⁻¹) from the given ±1 probes (s×n)."""
+        z = np.ascontiguousarray(signs, dtype=np.int8)
+        if z.ndim != 2 or z.shape[1] != self.n:
+            raise ValueError("signs must be s×n")
+        out = np.empty(self.n)
+        self._check(lib().qpg_hutchinson(self._h, z.ctypes.data_as(_PB), z.shape[0], float(rho), float(eps),
+                                         int(max_iter), _dptr(out)))
+        return out
+
     def set_rho(self, rho: float):
         self._check(lib().qpg_set_rho(self._h, float(rho)))
 
@@ -263,3 +309,58 @@ def solve(P_triu, q, A, l, u, **kw):
     with Solver(P_triu, q, A, l, u, **kw) as s:
         info = s.solve()
         return s.x(), s.y(), info
+
+
+class Net:
+    """Network of the learned preconditioner (device-resident parameters and Adam state)."""
+
+    def __init__(self, params=None, seed: int = 0, bf16: bool = True, device: int = 0):
+        h = C.c_void_p()
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        if p is not None and p.size != QPG_NET_NPARAMS:
+            raise ValueError(f"params needs {QPG_NET_NPARAMS} floats")
+        rc = lib().qpg_net_create(C.byref(h), None if p is None else p.ctypes.data_as(_PF), int(seed),
+                                  int(bool(bf16)), int(device))
+        if rc != QPG_OK:
+            raise QpgError(rc, "qpg_net_create")
+        self._h = h
+
+    def _check(self, rc, what):
+        if rc != QPG_OK:
+            raise QpgError(rc, what)
+
+    def params(self):
+        out = np.empty(QPG_NET_NPARAMS, dtype=np.float32)
+        self._check(lib().qpg_net_get_params(self._h, out.ctypes.data_as(_PF)), "get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(lib().qpg_net_set_params(self._h, p.ctypes.data_as(_PF)), "set_params")
+
+    def forward(self, solver: Solver, rho: float):
+        g = np.empty(solver.n, dtype=np.float32)
+        self._check(lib().qpg_net_forward(self._h, solver._h, float(rho), g.ctypes.data_as(_PF)), "forward")
+        return g
+
+    def loss_grad(self, solver: Solver, rho: float, target, want_grad: bool = True):
+        t = np.ascontiguousarray(target, dtype=np.float32)
+        loss = C.c_double()
+        grad = np.empty(QPG_NET_NPARAMS, dtype=np.float32) if want_grad else None
+        self._check(lib().qpg_net_loss_grad(self._h, solver._h, float(rho), t.ctypes.data_as(_PF), C.byref(loss),
+                                            None if grad is None else grad.ctypes.data_as(_PF)), "loss_grad")
+        return loss.value, grad
+
+    def adam_step(self, lr: float):
+        self._check(lib().qpg_net_adam_step(self._h, float(lr)), "adam_step")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qpg_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

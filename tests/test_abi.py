@@ -24,7 +24,7 @@ def declared_functions():
 def test_library_exports_every_declared_symbol():
     L = qpg.lib()
     names = declared_functions()
-    assert len(names) >= 14
+    assert len(names) >= 24
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(qpg.SIGNATURES)
@@ -39,8 +39,10 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(qpg_csc), sizeof(qpg_settings), sizeof(qpg_info));
   printf("%zu %zu %zu %zu\n", offsetof(qpg_settings, pcg_max_iter), offsetof(qpg_settings, stream),
          offsetof(qpg_settings, verbose), offsetof(qpg_settings, rho_update_gate));
-  printf("%zu %zu %zu\n", offsetof(qpg_info, obj_val), offsetof(qpg_info, solve_time),
-         offsetof(qpg_info, scaling_passes));
+  printf("%zu %zu %zu %zu\n", offsetof(qpg_info, obj_val), offsetof(qpg_info, solve_time),
+         offsetof(qpg_info, scaling_passes), offsetof(qpg_info, precond_switches));
+  printf("%zu %zu\n", offsetof(qpg_settings, precond_weights), offsetof(qpg_settings, precond_trial));
+  printf("%d\n", QPG_NET_NPARAMS);
   return 0;
 }
 """
@@ -54,8 +56,14 @@ int main(void) {
     S, I = qpg.Settings, qpg.Info
     want = [C.sizeof(qpg.Csc), C.sizeof(S), C.sizeof(I),
             S.pcg_max_iter.offset, S.stream.offset, S.verbose.offset, S.rho_update_gate.offset,
-            I.obj_val.offset, I.solve_time.offset, I.scaling_passes.offset]
+            I.obj_val.offset, I.solve_time.offset, I.scaling_passes.offset, I.precond_switches.offset,
+            S.precond_weights.offset, S.precond_trial.offset, qpg.QPG_NET_NPARAMS]
     assert got == want
+
+
+def test_parameter_count_matches_oracle_layout():
+    from oracle import mpnn
+    assert mpnn.nparams() == qpg.QPG_NET_NPARAMS
 
 
 def test_default_settings_follow_the_paper():

@@ -1,0 +1,184 @@
+"""Learned diagonal preconditioner on the GPU against the float64 oracle. Needs an MI355X.
+
+Tolerances (relative to the ∞-norm of the oracle quantity):
+* network outputs and gradients: 1e-4 with float32 dense layers, 2e-2 with bf16 MFMA layers;
+* Hutchinson estimates with the same probes: 1e-8 (the device PCG runs to 1e-12);
+* a solve with any positive learned diagonal must still meet the final-answer bars (checked
+  at eps 1e-7, where the stopping point no longer depends on the iterate path).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import admm as o_admm
+from oracle import hutchinson as o_hutch
+from oracle import mpnn
+from oracle import pcg as o_pcg
+from oracle import ruiz as o_ruiz
+from paper_1912_04263_amd import problems as pr
+from paper_1912_04263_amd import qpg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def problem(name):
+    return pr.make(name)
+
+
+def oracle_graph(p, rho, sigma=1e-6):
+    D, E, c, Pb, qb, Ab, _ = o_ruiz.ruiz(p.P_full(), p.q, sp.csr_matrix(p.A), 10)
+    lb, ub = E * np.maximum(p.l, -1e20), E * np.minimum(p.u, 1e20)
+    fv, fc, dP, colsq = mpnn.features(Pb, Ab, sigma, lb, ub)
+    Ahat, Acheck = mpnn.graph(Ab)
+    phi, K = mpnn.head_inputs(dP, colsq, sigma, rho)
+    return fv, fc, Ahat, Acheck, phi, K, Pb, Ab
+
+
+def make_params(seed=0, noise=0.3):
+    rng = np.random.default_rng(seed + 100)
+    th = mpnn.init_params(seed)
+    return (th + noise * rng.standard_normal(th.size)).astype(np.float32)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("name", ["portfolio_small", "lasso_small"])
+def test_network_forward_and_gradient_match_oracle(name, bf16):
+    say("net fwd/bwd", name, "bf16" if bf16 else "fp32")
+    p = problem(name)
+    rho = 0.4
+    fv, fc, Ahat, Acheck, phi, K, Pb, Ab = oracle_graph(p, rho)
+    theta = make_params(1)
+    rng = np.random.default_rng(3)
+    target = np.log(1.0 + rng.random(p.n)).astype(np.float32)
+    # with bf16 layers the model's weights are the bf16-rounded ones: the oracle evaluates those
+    th_o = mpnn.bf16_round(theta) if bf16 else theta.astype(np.float64)
+    L_o, G_o, g_o = mpnn.loss_grad(th_o, fv, fc, Ahat, Acheck, phi, target.astype(np.float64))
+    tol = 2e-2 if bf16 else 1e-4
+    with qpg.Solver.from_qp(p) as s:
+        net = qpg.Net(theta, bf16=bf16)
+        g = net.forward(s, rho)
+        assert np.max(np.abs(g - g_o)) <= tol * np.max(np.abs(g_o))
+        L, G = net.loss_grad(s, rho, target)
+        assert abs(L - L_o) <= tol * abs(L_o)
+        assert np.max(np.abs(G - G_o)) <= tol * np.max(np.abs(G_o))
+        # per parameter block, relative to the block's own scale (bf16 blocks at 5e-2)
+        btol = 5e-2 if bf16 else 1e-3
+        o = 0
+        for bname, shape in mpnn.layout():
+            k = int(np.prod(shape))
+            go, gg = G_o[o:o + k], G[o:o + k]
+            if np.max(np.abs(go)) > 1e-3 * np.max(np.abs(G_o)):
+                assert np.max(np.abs(gg - go)) <= btol * np.max(np.abs(go)), bname
+            o += k
+        net.close()
+
+
+def test_initial_network_reproduces_jacobi_on_device():
+    say("init = jacobi")
+    p = problem("portfolio_small")
+    with qpg.Solver.from_qp(p) as s:
+        net = qpg.Net(None, seed=5, bf16=True)
+        g = net.forward(s, 0.1)
+        np.testing.assert_allclose(g, mpnn.INIT_BIAS, rtol=1e-6)
+        net.close()
+    base = qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5)
+    ib = base.solve()
+    w = qpg.Net(None, seed=5).params()
+    lrn = qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5, precond="learned", precond_weights=w,
+                             precond_trial=0)
+    il = lrn.solve()
+    assert il.precond_used == "learned"
+    assert abs(il.iter - ib.iter) <= 10 and abs(il.pcg_iter_total - ib.pcg_iter_total) <= 0.05 * ib.pcg_iter_total
+    assert np.max(np.abs(lrn.x() - base.x())) <= 1e-4 * np.max(np.abs(base.x()))
+    base.close()
+    lrn.close()
+
+
+@pytest.mark.parametrize("name", ["random_c0", "portfolio_small"])
+def test_hutchinson_matches_oracle_with_same_probes(name):
+    say("hutchinson", name)
+    p = problem(name)
+    rho = 0.2
+    rng = np.random.default_rng(11)
+    z = rng.choice(np.array([-1, 1], dtype=np.int8), size=(6, p.n))
+    with qpg.Solver.from_qp(p) as s:
+        h = s.hutchinson(z, rho, eps=1e-12)
+        D, E, c = s.scaling()
+        Pb = (c * sp.diags(D) @ p.P_full() @ sp.diags(D)).tocsr()
+        Ab = (sp.diags(E) @ sp.csr_matrix(p.A) @ sp.diags(D)).tocsr()
+        Kd = o_pcg.reduced_kkt_dense(Pb, Ab, 1e-6, rho)
+        Kinv = np.linalg.inv(Kd)
+        ref = o_hutch.estimate(lambda v: Kinv @ v, z)
+        assert np.max(np.abs(h - ref)) <= 1e-8 * np.max(np.abs(ref))
+        np.testing.assert_allclose(s.kdiag(rho), np.diag(Kd), rtol=1e-12)
+
+
+def test_hutchinson_exhaustive_probes_give_the_exact_diagonal_inverse():
+    say("hutchinson exhaustive")
+    rng = np.random.default_rng(2)
+    n, m = 9, 12
+    Mq = rng.standard_normal((n, n))
+    P = sp.csc_matrix(np.triu(Mq @ Mq.T + np.eye(n)))
+    A = sp.csc_matrix(rng.standard_normal((m, n)) * (rng.random((m, n)) < 0.6))
+    with qpg.Solver(P, rng.standard_normal(n), A, -np.ones(m), np.ones(m), scaling_iters=0) as s:
+        z = o_hutch.all_sign_vectors(n).astype(np.int8)
+        h = s.hutchinson(z, 0.7, eps=1e-13)
+        Pf = (P + sp.triu(P, 1).T).toarray()
+        Ad = A.toarray()
+        K = Pf + 1e-6 * np.eye(n) + 0.7 * Ad.T @ Ad
+        np.testing.assert_allclose(h, np.diag(np.linalg.inv(K)), rtol=1e-9)
+
+
+def test_learned_preconditioner_keeps_the_answer():
+    """The ADMM fixed point does not depend on M: a perturbed network (always used) must still
+    reach the oracle's solution within the final-answer bars."""
+    say("learned keeps the answer")
+    p = problem("portfolio_small")
+    ref = o_admm.solve(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, eps_abs=1e-9, eps_rel=1e-9, max_iter=50000)
+    w = make_params(7, noise=0.5)
+    with qpg.Solver.from_qp(p, eps_abs=1e-7, eps_rel=1e-7, max_iter=20000, precond="learned",
+                            precond_weights=w, precond_trial=0) as s:
+        info = s.solve()
+        assert info.status == "solved"
+        assert abs(info.obj_val - ref.obj) <= 1e-4 * max(1.0, abs(ref.obj))
+        assert np.max(np.abs(s.x() - ref.x)) <= 1e-3 * np.max(np.abs(ref.x))
+
+
+def test_trial_policy_falls_back_to_jacobi_for_a_bad_network():
+    """A network scaled far off (every M⁻¹_ii ≈ random factor) loses the trial against Jacobi."""
+    say("trial fallback")
+    p = problem("lasso_small")
+    w = make_params(9, noise=3.0)
+    with qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5, precond="learned", precond_weights=w) as s:
+        info = s.solve()
+        assert info.status == "solved"
+        assert info.precond_trials >= 1
+        assert info.precond_learned_chosen < info.precond_trials
+
+
+def test_adam_steps_reduce_the_loss():
+    say("adam")
+    p = problem("portfolio_small")
+    rho = 0.1
+    with qpg.Solver.from_qp(p) as s:
+        rng = np.random.default_rng(4)
+        z = rng.choice(np.array([-1, 1], dtype=np.int8), size=(16, p.n))
+        hh = s.hutchinson(z, rho, eps=1e-8)
+        K = s.kdiag(rho)
+        target = np.log(np.maximum(hh, 1.0 / K) * K).astype(np.float32)
+        net = qpg.Net(None, seed=3)
+        l0, _ = net.loss_grad(s, rho, target, want_grad=False)
+        for _ in range(30):
+            net.loss_grad(s, rho, target, want_grad=False)
+            net.adam_step(3e-3)
+        l1, _ = net.loss_grad(s, rho, target, want_grad=False)
+        assert l1 < 0.7 * l0
+        net.close()
