@@ -160,8 +160,9 @@ int qpg_get_scaling(const qpg_solver* h, double* D, double* E, double* c);
 #define QPG_OP_K 3
 int qpg_apply(qpg_solver* h, int32_t op, int32_t precision, const double* in, double* out);
 
-/* Algorithm 3 on the scaled reduced system (P̄ + σI + ρ̄ĀᵀĀ)x = b with the Jacobi preconditioner
- * of Section 6.3.1 and the current ρ̄: starts from x0 (n), stops when ‖r‖∞ ≤ eps·‖b‖∞ (rel = 1)
+/* Algorithm 3 on the scaled reduced system (P̄ + σI + ρ̄ĀᵀĀ)x = b with the current ρ̄ and the
+ * solver's preconditioner (Jacobi, Section 6.3.1, or the learned diagonal when the solver was set
+ * up with QPG_PRECOND_LEARNED): starts from x0 (n), stops when ‖r‖∞ ≤ eps·‖b‖∞ (rel = 1)
  * or ‖r‖∞ ≤ eps (rel = 0) or after max_iter iterations. Writes x (n), the iteration count and
  * the final ‖r‖∞. Same kernels as the PCG inside qpg_solve. */
 int qpg_pcg(qpg_solver* h, int32_t precision, const double* b, const double* x0, double eps,

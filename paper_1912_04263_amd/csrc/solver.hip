@@ -186,9 +186,13 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         fallback_request = 1;
         return k;
       }
-      // PCG tolerance from the scaled residuals (Section 6.3.3)
-      if (!fixed_eps)
+      // PCG tolerance from the scaled residuals (Section 6.3.3). With the relative test
+      // ‖r‖ ≤ ε‖b‖ the rule is capped at λ: a larger ε (residuals above 1/λ²) would let PCG stop
+      // at zero iterations, freezing x̃ while ADMM stalls.
+      if (!fixed_eps) {
         eps_pcg = std::max(s.pcg_lambda * std::sqrt(nm[0] * nm[6]), s.pcg_eps_min);
+        if (s.pcg_rel_test) eps_pcg = std::min(eps_pcg, s.pcg_lambda);
+      }
       // ρ̄ update (Section 3.4, every rho_update_every iterations, Section 6.3.2)
       if (s.rho_update_every > 0 && k % s.rho_update_every == 0) {
         const double num = nm[0] / std::max(std::max(nm[2], nm[4]), 1e-10);
@@ -385,7 +389,10 @@ int pcg_impl(qpg_solver* h, const double* b, const double* x0, double eps, int r
   Prec<T>& V = h->P<T>();
   to_device<T>(h, V.b, b, h->n);
   to_device<T>(h, V.xt, x0, h->n);
-  h->jacobi<T>(h->rho_cur);
+  if (h->s.precond == QPG_PRECOND_LEARNED)
+    h->learned_dinv<T>(h->rho_cur);
+  else
+    h->jacobi<T>(h->rho_cur);
   hipLaunchKernelGGL((k_absmax<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, (const T*)V.b,
                      h->rb.partials);
   h->finalize_fn<1, 1u>(FinThresh{h->st, eps, rel}, h->vgrid);

@@ -304,6 +304,17 @@ class Solver:
         self.close()
 
 
+WEIGHTS_DIR = os.path.join(HERE, "weights")
+
+
+def load_weights(name: str = "portfolio_h32") -> np.ndarray:
+    """Trained parameters of the learned preconditioner (raw little-endian float32)."""
+    w = np.fromfile(os.path.join(WEIGHTS_DIR, name + ".f32"), dtype="<f4")
+    if w.size != QPG_NET_NPARAMS:
+        raise ValueError(f"{name}: {w.size} floats, expected {QPG_NET_NPARAMS}")
+    return w
+
+
 def solve(P_triu, q, A, l, u, **kw):
     """One-shot solve; returns (x, y, SolveInfo)."""
     with Solver(P_triu, q, A, l, u, **kw) as s:

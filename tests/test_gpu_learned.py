@@ -182,3 +182,40 @@ def test_adam_steps_reduce_the_loss():
         l1, _ = net.loss_grad(s, rho, target, want_grad=False)
         assert l1 < 0.7 * l0
         net.close()
+
+
+def test_trained_network_gains_over_jacobi_on_heldout_portfolios():
+    """The committed network (trained on portfolio instances n = 20,000, seeds 50000–50255) on
+    held-out instances (seeds 60000–60003): fewer PCG iterations than Jacobi on random systems
+    and in full solves, with both solves reaching the same tight-tolerance answer."""
+    say("gain over jacobi")
+    w = qpg.load_weights("portfolio_h32")
+    its_j, its_l, pcg_j, pcg_l = [], [], 0, 0
+    for i in range(4):
+        p = pr.portfolio_qp(20000, 200, 0.5, 60000 + i)
+        sj = qpg.Solver.from_qp(p)
+        sl = qpg.Solver.from_qp(p, precond="learned", precond_weights=w)
+        rng = np.random.default_rng(i)
+        for rho in (0.1, 1.0):
+            b = rng.standard_normal(p.n)
+            sj.set_rho(rho)
+            sl.set_rho(rho)
+            its_j.append(sj.pcg(b, eps=1e-6, max_iter=5000)[1])
+            its_l.append(sl.pcg(b, eps=1e-6, max_iter=5000)[1])
+        sj.close()
+        sl.close()
+        if i < 2:
+            a = qpg.Solver.from_qp(p, eps_abs=1e-6, eps_rel=1e-6, max_iter=20000)
+            b2 = qpg.Solver.from_qp(p, eps_abs=1e-6, eps_rel=1e-6, max_iter=20000, precond="learned",
+                                    precond_weights=w)
+            ia, ib = a.solve(), b2.solve()
+            assert ia.status == "solved" and ib.status == "solved"
+            assert abs(ia.obj_val - ib.obj_val) <= 1e-3 * max(1.0, abs(ia.obj_val))
+            pcg_j += ia.pcg_iter_total
+            pcg_l += ib.pcg_iter_total
+            a.close()
+            b2.close()
+    say("pcg iterations on random systems: jacobi", np.mean(its_j), "learned", np.mean(its_l),
+        "| full solves: jacobi", pcg_j, "learned", pcg_l)
+    assert np.mean(its_l) < 0.6 * np.mean(its_j)
+    assert pcg_l < 0.8 * pcg_j
