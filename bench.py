@@ -95,11 +95,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="lasso_c1")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "learned"])
+    ap.add_argument("--weights", default="portfolio_h32", help="learned-preconditioner weights name")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--ref-eps", type=float, default=0.0,
+                    help="also solve to this tolerance (FP64/Jacobi, untimed) and report each "
+                         "variant's objective error against it")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (reference for counter scaling)")
     args = ap.parse_args()
@@ -122,9 +127,13 @@ def main():
     log(f"[bench] generated {args.workload}: n={p.n} m={p.m} nnz(P)={p.meta['nnz_P_full']} "
         f"nnz(A)={p.meta['nnz_A']} in {time.perf_counter() - t0:.1f}s")
 
-    def run(precision, steps, warmup):
+    weights = qpg.load_weights(args.weights)
+
+    def run(precision, steps, warmup, precond=None):
+        precond = precond or args.precond
+        extra = dict(precond="learned", precond_weights=weights) if precond == "learned" else {}
         s = qpg.Solver.from_qp(p, eps_abs=args.eps, eps_rel=args.eps, precision=precision,
-                               stream=stream, device=0, max_iter=20000)
+                               stream=stream, device=0, max_iter=20000, **extra)
         setup = s.info().setup_time
         for _ in range(warmup):
             s.solve()
@@ -148,7 +157,7 @@ def main():
     steps = max(1, args.steps)
     last = infos[-1] if infos else s.info()
     admm_iters = sum(i.iter for i in infos)
-    log(f"[bench] {args.precision}: {last.status} in {last.iter} ADMM / {last.pcg_iter_total} PCG "
+    log(f"[bench] {args.precision}/{args.precond}: {last.status} in {last.iter} ADMM / {last.pcg_iter_total} PCG "
         f"iterations, solve {elapsed / steps * 1e3:.2f} ms, setup {setup_s:.2f} s, obj {last.obj_val:.10g}")
 
     prec_id = qpg.QPG_MIXED if args.precision == "mixed" else qpg.QPG_FP64
@@ -174,17 +183,36 @@ def main():
                 "pcg_iteration": {"bytes": pcg_bytes, "kernel_us": pcg_us, "GBs": pcg_bytes / pcg_us / 1e3}}
     s.close()
 
-    compare = None
+    variants = []
     if not args.no_compare:
-        other = "mixed" if args.precision == "fp64" else "fp64"
-        s2, su2, inf2, el2 = run(other, max(1, args.steps // 2), 1)
-        compare = {"precision": other, "tts_ms": el2 / len(inf2) * 1e3,
-                   "admm_iter_per_s": sum(i.iter for i in inf2) / el2, "admm_iters": inf2[-1].iter,
-                   "pcg_iters": inf2[-1].pcg_iter_total, "status": inf2[-1].status,
-                   "obj": inf2[-1].obj_val, "precision_used": inf2[-1].precision_used,
-                   "obj_rel_diff_vs_main": abs(inf2[-1].obj_val - last.obj_val) / max(1.0, abs(last.obj_val))}
-        log(f"[bench] {other}: {compare}")
-        s2.close()
+        for prec, pc in (("fp64", "jacobi"), ("mixed", "jacobi"), ("mixed", "learned"), ("fp64", "learned")):
+            if (prec, pc) == (args.precision, args.precond):
+                continue
+            s2, su2, inf2, el2 = run(prec, max(1, args.steps // 2), 1, pc)
+            last2 = inf2[-1]
+            v = {"precision": prec, "precond": pc, "tts_ms": el2 / len(inf2) * 1e3,
+                 "admm_iter_per_s": sum(i.iter for i in inf2) / el2, "admm_iters": last2.iter,
+                 "pcg_iters": last2.pcg_iter_total, "status": last2.status, "obj": last2.obj_val,
+                 "precision_used": last2.precision_used, "precond_used": last2.precond_used,
+                 "precond_trials_won": [last2.precond_learned_chosen, last2.precond_trials],
+                 "setup_s": su2,
+                 "obj_rel_diff_vs_main": abs(last2.obj_val - last.obj_val) / max(1.0, abs(last.obj_val))}
+            variants.append(v)
+            log(f"[bench] {prec}/{pc}: {v['status']} tts {v['tts_ms']:.2f} ms, {v['admm_iters']} ADMM / "
+                f"{v['pcg_iters']} PCG, obj {v['obj']:.10g}")
+            s2.close()
+
+    ref = None
+    if args.ref_eps > 0:
+        sr = qpg.Solver.from_qp(p, eps_abs=args.ref_eps, eps_rel=args.ref_eps, stream=stream, device=0,
+                                max_iter=100000)
+        ir = sr.solve()
+        sr.close()
+        ref = {"eps": args.ref_eps, "obj": ir.obj_val, "status": ir.status, "iters": ir.iter}
+        scale = max(1.0, abs(ir.obj_val))
+        for v in variants:
+            v["obj_rel_err_vs_ref"] = abs(v["obj"] - ir.obj_val) / scale
+        log(f"[bench] reference at eps {args.ref_eps}: {ir.status}, obj {ir.obj_val:.10g}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -207,7 +235,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "nnz_P": p.meta["nnz_P_full"], "nnz_A": nnz_a,
                    "eps_abs": args.eps, "eps_rel": args.eps, "precision": args.precision,
-                   "preconditioner": "jacobi", "step": "one full solve from a cold start"},
+                   "preconditioner": args.precond, "step": "one full solve from a cold start"},
         "tts_s": elapsed / steps if args.steps else None,
         "setup_s": setup_s,
         "status": last.status,
@@ -216,7 +244,9 @@ def main():
         "obj": last.obj_val,
         "kernels": kernels,
         "roofline": roofline,
-        "compare": compare,
+        "variants": variants,
+        "reference": ref,
+        "obj_rel_err_vs_ref": (abs(last.obj_val - ref["obj"]) / max(1.0, abs(ref["obj"]))) if ref else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

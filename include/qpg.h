@@ -91,11 +91,13 @@ typedef struct {
   void* stream;           /* hipStream_t for all device work, NULL = null stream */
   int32_t verbose;        /* 1: one line per residual check on stderr */
   const float* precond_weights; /* QPG_NET_NPARAMS floats for QPG_PRECOND_LEARNED (copied at setup) */
-  int32_t precond_trial;  /* 1 (default): before the first PCG solve and after each ρ̄ change, solve
-                             once with each preconditioner from the same warm start and keep the
-                             learned one only if it needs fewer iterations (or, both capped, ends
-                             with a smaller residual); 0: always learned. In both cases a capped or
-                             broken-down learned solve switches to Jacobi. */
+  int32_t precond_trial;  /* 1 (default): before the first PCG solve, and after a ρ̄ change that
+                             moves ρ̄ by more than 2× since the last trial, solve once with each
+                             preconditioner from the same warm start and keep the learned one only
+                             if it needs fewer iterations (or, both capped, ends with a smaller
+                             residual); after two lost trials in a row, Jacobi for the rest of the
+                             solve. 0: always learned. In both cases a capped or broken-down learned
+                             solve switches to Jacobi. */
 } qpg_settings;
 
 typedef struct {

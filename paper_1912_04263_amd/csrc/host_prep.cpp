@@ -97,12 +97,12 @@ int validate_settings(const qpg_settings* s, std::string* msg) {
   return QPG_OK;
 }
 
-Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows) {
+Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap) {
   Plan p;
   int32_t r = 0;
   while (r < nrows) {
     int32_t len = rowptr[r + 1] - rowptr[r];
-    if (len > kStreamCap) {
+    if (len > cap) {
       if (len <= kLongCap) {
         p.items.push_back({r, r + 1, rowptr[r], rowptr[r + 1], 0, 0, 0, 0});
       } else {
@@ -124,7 +124,7 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows) {
     int32_t acc = 0;
     while (r < nrows) {
       int32_t l2 = rowptr[r + 1] - rowptr[r];
-      if (l2 > kStreamCap || acc + l2 > kStreamCap || (r - r0) >= kStreamCap) break;
+      if (l2 > cap || acc + l2 > cap || (r - r0) >= cap) break;
       acc += l2;
       ++r;
     }

@@ -118,21 +118,43 @@ __device__ __forceinline__ void publish(double (&v)[NS], double* partials) {
   }
 }
 
-// One workgroup: combine `count` partials in workgroup order, then run the scalar finalisation.
+// One 1024-thread workgroup: combine `count` partials in a fixed order (thread t takes
+// workgroups t, t + 1024, …; then a fixed tree), run the scalar finalisation, and mirror the
+// device scalars into host-visible memory for the host's checks.
+constexpr int kFinBlock = 1024;
+
 template <int NS, unsigned MAXMASK, class Fin>
-__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int count,
-                                                     Fin fin, const int32_t* __restrict__ gate) {
+__global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict__ partials, int count,
+                                                        Fin fin, const int32_t* __restrict__ gate,
+                                                        const DevState* st, DevState* mirror) {
   if (gate && *gate) return;
-  __shared__ double lds[kMaxSlots * 4];
+  __shared__ double lds[kMaxSlots][kFinBlock / 64];
   double acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-  for (int b = threadIdx.x; b < count; b += kBlock) {
+#pragma unroll 4
+  for (int b = threadIdx.x; b < count; b += kFinBlock) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) acc[s] = comb<MAXMASK>(s, acc[s], partials[(size_t)b * kMaxSlots + s]);
   }
-  block_reduce<NS, MAXMASK>(acc, lds);
-  if (threadIdx.x == 0) fin(acc);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    double x = acc[s];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = comb<MAXMASK>(s, x, __shfl_xor(x, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[s][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double x = lds[s][0];
+      for (int w = 1; w < kFinBlock / 64; ++w) x = comb<MAXMASK>(s, x, lds[s][w]);
+      acc[s] = x;
+    }
+    fin(acc);
+    if (mirror) *mirror = *st;
+  }
 }
 
 template <typename T>
@@ -168,12 +190,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const Item* __restrict__ items,
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
 
-  __shared__ T prod[NV][kStreamCap];
+  constexpr int kCap = kStreamCap / NV;  // the two-product work list holds half as many nnz
+  __shared__ T prod[NV][kCap];
   __shared__ T wsum[3][kBlock / 64];
   const Item it = items[blockIdx.x];
   const int tid = threadIdx.x;
 
-  if (it.nchunk == 0 && it.k1 - it.k0 <= kStreamCap) {
+  if (it.nchunk == 0 && it.k1 - it.k0 <= kCap) {
     // ---- a run of whole rows: stage the products in LDS, then one lane group per row
     const int cnt = it.k1 - it.k0;
 #pragma unroll 8

@@ -33,7 +33,7 @@ struct Plan {
 
 // Build the work list of a CSR matrix with nrows rows (Section 5.1.4: SpMV row sums are a
 // segmented reduction over the RowPointer segments; this balances it over workgroups).
-Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows);
+Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = kStreamCap);
 
 // The problem after validation, format conversion and Ruiz equilibration, all on the host.
 struct HostProblem {

@@ -66,9 +66,13 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // first PCG solve and the first one after every ρ̄ change run with both preconditioners from the
   // same warm start, and the learned one is kept only if it needs fewer iterations (or, when both
   // hit the cap, ends with a smaller residual); a capped learned solve falls back to Jacobi.
+  // A new trial is run only when ρ̄ has moved by more than a factor 2 since the last one, and
+  // trials stop for the rest of the solve after the learned diagonal has lost two in a row.
   const bool learned_ok = (s.precond == QPG_PRECOND_LEARNED);
   bool trial = learned_ok && s.precond_trial;
   bool use_learned = learned_ok && !s.precond_trial;
+  double rho_trial = rho;
+  int lost_in_a_row = 0;
   if (use_learned)
     learned_dinv<T>(rho);
   else
@@ -96,6 +100,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       it = pcg_loop<T>(rho, s.pcg_max_iter);
       const bool cap_j = it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh;
       use_learned = !broke_l && ((!cap_l && it_l < it) || (cap_l && cap_j && rn_l < st_host->rnorm));
+      lost_in_a_row = use_learned ? 0 : lost_in_a_row + 1;
+      rho_trial = rho;
       info.precond_trials++;
       if (use_learned) {
         info.precond_learned_chosen++;
@@ -203,7 +209,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
             if (est != rho) {
               rho = est;
               info.rho_updates++;
-              if (learned_ok && s.precond_trial)
+              const bool moved = est > 2.0 * rho_trial || est < 0.5 * rho_trial;
+              if (learned_ok && s.precond_trial && moved && lost_in_a_row < 2)
                 trial = true;
               else if (use_learned)
                 learned_dinv<T>(rho);
@@ -518,10 +525,12 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     HIPCHK(hipSetDevice(h->device));
     Plan pa = make_plan(H.a_ptr, H.m);
     Plan pb = make_plan(H.b_ptr, H.n);
-    if (pa.items.empty()) pa.items.push_back({0, 0, 0, 0, 0, 0, 0, 0});
-    if (pb.items.empty()) pb.items.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+    Plan pb2 = make_plan(H.b_ptr, H.n, kStreamCap / 2);
+    for (Plan* pl : {&pa, &pb, &pb2})
+      if (pl->items.empty()) pl->items.push_back({0, 0, 0, 0, 0, 0, 0, 0});
     h->na_items = (int32_t)pa.items.size();
     h->nb_items = (int32_t)pb.items.size();
+    h->nb2_items = (int32_t)pb2.items.size();
     h->vgrid = grid_for(h->n);
     h->a_ptr = h->upload(H.a_ptr);
     h->a_col = h->upload(H.a_col);
@@ -530,6 +539,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->b_col = h->upload(H.b_col);
     h->a_items = h->upload(pa.items);
     h->b_items = h->upload(pb.items);
+    h->b2_items = h->upload(pb2.items);
     h->diagP = h->upload(H.diagP);
     h->colsq = h->upload(H.colsq);
     std::vector<double> dinv(H.n), einv(H.m);
@@ -537,17 +547,18 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     for (int i = 0; i < H.m; ++i) einv[i] = 1.0 / H.E[i];
     h->dscale = h->upload(dinv);
     h->escale = h->upload(einv);
-    int maxgrid = std::max(std::max(h->na_items, h->nb_items), 1024);
+    int maxgrid = std::max(std::max(h->na_items, std::max(h->nb_items, h->nb2_items)), 1024);
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
-    int slots = std::max(std::max(pa.n_chunk_slots, pb.n_chunk_slots), 1);
-    int tickets = std::max(std::max(pa.n_split_rows, pb.n_split_rows), 1);
+    int slots = std::max(std::max(pa.n_chunk_slots, std::max(pb.n_chunk_slots, pb2.n_chunk_slots)), 1);
+    int tickets = std::max(std::max(pa.n_split_rows, std::max(pb.n_split_rows, pb2.n_split_rows)), 1);
     h->rb.chunk_part = h->alloc<double>(3 * (size_t)slots);
     h->rb.chunk_ticket = h->alloc<uint32_t>(tickets);
     HIPCHK(hipMemsetAsync(h->rb.chunk_ticket, 0, tickets * sizeof(uint32_t), h->stream));
     h->st = h->alloc<DevState>(1);
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream));
-    HIPCHK(hipHostMalloc((void**)&h->st_host, sizeof(DevState), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&h->st_host, sizeof(DevState), hipHostMallocMapped));
     std::memset(h->st_host, 0, sizeof(DevState));
+    HIPCHK(hipHostGetDevicePointer((void**)&h->st_mirror_dev, h->st_host, 0));
     h->alloc_prec64(H);
     if (settings->precision == QPG_MIXED) h->alloc_prec32(H);
     for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);

@@ -65,12 +65,13 @@ struct qpg_solver {
   // structure shared by both precisions
   int32_t *a_ptr = nullptr, *a_col = nullptr, *b_ptr = nullptr, *b_split = nullptr,
           *b_col = nullptr;
-  Item *a_items = nullptr, *b_items = nullptr;
-  int32_t na_items = 0, nb_items = 0;
+  Item *a_items = nullptr, *b_items = nullptr, *b2_items = nullptr;
+  int32_t na_items = 0, nb_items = 0, nb2_items = 0;
   int32_t nnzA = 0, nnzB = 0;
   double *diagP = nullptr, *colsq = nullptr, *dscale = nullptr, *escale = nullptr;  // D⁻¹, E⁻¹
   DevState* st = nullptr;
-  DevState* st_host = nullptr;  // pinned
+  DevState* st_host = nullptr;        // mapped pinned host memory, written by finalize kernels
+  DevState* st_mirror_dev = nullptr;  // its device-side address
   RedBuf rb{};
   int32_t vgrid = 1;
 
@@ -136,25 +137,32 @@ struct qpg_solver {
   }
   template <typename T, class Op>
   int spmv_B(const Op& op, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(nb_items), dim3(kBlock), 0, stream, b_items, b_ptr,
-                       b_split, b_col, P<T>().b_val, op, rb, gate);
-    return nb_items;
+    // two-product passes stage twice the products: they use the half-size work list
+    const Item* items = Op::NV == 2 ? b2_items : b_items;
+    const int ni = Op::NV == 2 ? nb2_items : nb_items;
+    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(ni), dim3(kBlock), 0, stream, items, b_ptr, b_split,
+                       b_col, P<T>().b_val, op, rb, gate);
+    return ni;
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
   template <class Op>
   void finalize(const Op& op, int count, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_finalize<Op::NS, Op::MAXMASK, Op>), dim3(1), dim3(kBlock), 0, stream,
-                       (const double*)rb.partials, count, op, gate);
+    hipLaunchKernelGGL((k_finalize<Op::NS, Op::MAXMASK, Op>), dim3(1), dim3(kFinBlock), 0, stream,
+                       (const double*)rb.partials, count, op, gate, (const DevState*)st, st_mirror_dev);
   }
   template <int NS, unsigned MASK, class Fin>
   void finalize_fn(const Fin& fin, int count, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_finalize<NS, MASK, Fin>), dim3(1), dim3(kBlock), 0, stream,
-                       (const double*)rb.partials, count, fin, gate);
+    hipLaunchKernelGGL((k_finalize<NS, MASK, Fin>), dim3(1), dim3(kFinBlock), 0, stream,
+                       (const double*)rb.partials, count, fin, gate, (const DevState*)st, st_mirror_dev);
   }
 
+  // Wait for the stream and read the device scalars. Every finalize kernel leaves a copy of
+  // them in mapped host memory (st_host), so no copy is queued: the host polls the stream.
   void sync_state() {
-    HIPCHK(hipMemcpyAsync(st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, stream));
-    HIPCHK(hipStreamSynchronize(stream));
+    hipError_t e;
+    while ((e = hipStreamQuery(stream)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) throw HipError{e, "hipStreamQuery"};
   }
 
   template <typename T>

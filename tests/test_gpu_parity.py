@@ -260,6 +260,37 @@ def test_repeat_solves_are_bitwise_identical():
         assert i1.iter == i2.iter and i1.pcg_iter_total == i2.pcg_iter_total
 
 
+def sampled_spmv_check(p, rows=200, seed=7):
+    """Sampled rows of Ā x, Āᵀ y, P x against exact rational row sums (unscaled data)."""
+    rng = np.random.default_rng(seed)
+    A = sp.csr_matrix(p.A)
+    At = sp.csr_matrix(p.A.T)
+    Pf = p.P_full()
+    with qpg.Solver.from_qp(p, scaling_iters=0) as s:
+        x = rng.standard_normal(s.n)
+        y = rng.standard_normal(s.m)
+        for M, v, op in ((A, x, qpg.QPG_OP_A), (At, y, qpg.QPG_OP_AT), (Pf, x, qpg.QPG_OP_P)):
+            out = s.apply(op, v)
+            for i in rng.choice(M.shape[0], min(rows, M.shape[0]), replace=False):
+                a, b = M.indptr[i], M.indptr[i + 1]
+                ex = o_spmv.row_exact(M.indptr, M.indices, M.data, v, i)
+                sc = float(np.abs(M.data[a:b]) @ np.abs(v[M.indices[a:b]]))
+                assert abs(out[i] - ex) <= 1e-12 * sc, (op, i)
+
+
+def kkt_certificate(p, eps, **kw):
+    with qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, max_iter=40000, **kw) as s:
+        info = s.solve()
+        say("full size", p.name, kw, info)
+        assert info.status == "solved"
+        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, s.x(), s.y(), s.z())
+        eps_p = eps + eps * max(rep["norms"]["Ax"], rep["norms"]["z"])
+        eps_d = eps + eps * max(rep["norms"]["Px"], rep["norms"]["Aty"], rep["norms"]["q"])
+        assert rep["prim"] <= 1.01 * eps_p and rep["dual"] <= 1.01 * eps_d
+        assert abs(info.obj_val - rep["obj"]) <= 1e-6 * max(1.0, abs(rep["obj"]))
+        return info, rep
+
+
 def test_full_size_lasso_sampled_spmv_and_kkt_certificate():
     """The bench workload at full size (Ad 100000×10000, 1%): sampled rows of every SpMV against
     exact row sums, and the optimality certificate of the returned solution."""
@@ -289,3 +320,21 @@ def test_full_size_lasso_sampled_spmv_and_kkt_certificate():
         eps_p = 1e-5 + 1e-5 * max(rep["norms"]["Ax"], rep["norms"]["z"])
         eps_d = 1e-5 + 1e-5 * max(rep["norms"]["Px"], rep["norms"]["Aty"], rep["norms"]["q"])
         assert rep["prim"] <= 1.01 * eps_p and rep["dual"] <= 1.01 * eps_d
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name, eps, kw", [
+    ("random_c2", 1e-5, {}),
+    ("portfolio_c3", 1e-6, {}),
+    ("svm_c4", 1e-5, {}),
+    ("svm_c4", 1e-5, {"precision": "mixed"}),
+])
+def test_full_size_sampled_spmv_and_kkt_certificate(name, eps, kw):
+    """The remaining benchmark workloads at full size: sampled SpMV rows against exact sums, and
+    the optimality certificate (primal and dual residuals within the termination test, measured
+    by the oracle on the unscaled data) of the returned solution."""
+    say("full size", name, kw)
+    p = problem(name)
+    if not kw:
+        sampled_spmv_check(p, rows=100)
+    kkt_certificate(p, eps, **kw)
