@@ -98,6 +98,9 @@ typedef struct {
                              residual); after two lost trials in a row, Jacobi for the rest of the
                              solve. 0: always learned. In both cases a capped or broken-down learned
                              solve switches to Jacobi. */
+  int32_t spmv_tile_nnz;  /* SpMV work-list granularity: matrix entries per workgroup when it stages
+                             a gather window in LDS; default 32768, 0 = default */
+  int32_t spmv_plain_nnz; /* the same for workgroups without a window; default 8192, 0 = default */
 } qpg_settings;
 
 typedef struct {

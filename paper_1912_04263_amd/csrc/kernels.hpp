@@ -1,20 +1,21 @@
 // Device kernels of the ADMM / reduced-KKT PCG path for gfx950 (wavefront 64, 256-thread
 // workgroups). Included by solver.hip only.
 //
-// All SpMVs run through one kernel template, k_spmv, driven by the host-built work list (Item):
-// each workgroup either streams a run of short rows through LDS (coalesced value/index loads,
-// products staged in LDS, then one power-of-two lane group per row reduces its segment), or
-// reduces one long row with all 256 threads, or one chunk of a very long row whose partial
-// sums are combined, in chunk order, by the last chunk to finish. The row sum then goes to an
-// operation-specific epilogue (the fused vector work of the ADMM / PCG step), whose reduction
-// contributions (FP64 sums and ∞-norms) are combined deterministically: per-workgroup partials,
-// reduced in a fixed order by the last workgroup to arrive, which also runs the scalar
-// finalisation (α, β, stopping flags) on the device.
+// All SpMVs run through one kernel template, k_spmv, driven by a host-built Tile work list:
+// each workgroup takes a block of rows restricted to one column range, optionally stages a window
+// of the gathered vector in LDS (gathers inside it read LDS, the rest read memory), and sums each
+// row with a group of lanes (1–64 lanes, several rows in flight per group) or with the whole
+// workgroup for long rows. Complete row sums go to an operation-specific epilogue (the fused
+// vector work of the ADMM / PCG step); the partial sums of multi-range blocks are added in range
+// order by k_combine, which then runs the same epilogue. Reduction contributions (FP64 sums and
+// ∞-norms) are combined deterministically: per-workgroup partials, reduced in a fixed order by
+// k_finalize, which also runs the scalar finalisation (α, β, stopping flags) on the device.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "qpg_internal.hpp"
 
@@ -42,9 +43,7 @@ struct DevState {
 };
 
 struct RedBuf {
-  double* partials;        // [gridDim.x][kMaxSlots], read by the following k_finalize
-  double* chunk_part;      // [chunk slots][3]
-  uint32_t* chunk_ticket;  // [split rows] (kept at 0 between launches)
+  double* partials;  // [workgroups][kMaxSlots], read by the following k_finalize
 };
 
 // NaN-propagating max (a NaN residual must not disappear inside a norm).
@@ -164,7 +163,7 @@ __device__ __forceinline__ T wave_sum(T x, int width) {
 }
 
 // ----------------------------------------------------------------------------------------------
-// Generic CSR SpMV with fused epilogue. Op supplies:
+// CSR SpMV with fused epilogue, driven by a Tile work list (one workgroup per tile). Op supplies:
 //   static constexpr int NS;            reduction slots (0: none)
 //   static constexpr unsigned MAXMASK;  bit s set: slot s is an ∞-norm (max), else a sum
 //   static constexpr int NV;            products per entry: 1, or 2
@@ -176,134 +175,185 @@ __device__ __forceinline__ T wave_sum(T x, int width) {
 //   void side() const;                  extra elementwise work (grid-stride)
 //   void operator()(const double* totals) const;  scalar finalisation (run by k_finalize)
 // ----------------------------------------------------------------------------------------------
+template <class Op, typename T>
+struct Gathered {
+  using type = typename std::conditional<Op::NV == 2, pair_t<T>, T>::type;
+};
+
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_spmv(const Item* __restrict__ items,
-                                                 const int32_t* __restrict__ rowptr,
-                                                 const int32_t* __restrict__ split,
+__device__ __forceinline__ typename Gathered<Op, T>::type fetch(const Op& op, int c) {
+  if constexpr (Op::NV == 2)
+    return op.gather_pair(c);
+  else
+    return op.gather(c);
+}
+
+// Complete row sums go to the epilogue; partial ones to the partial planes (s1, s2, s3 at
+// offsets 0, pstride, 2·pstride).
+template <typename T, class Op>
+__device__ __forceinline__ void row_done(const Op& op, const Tile& t, int i, T s1, T s2, T s3,
+                                         double* red, T* __restrict__ tpart, int64_t pstride,
+                                         bool has_split) {
+  if (t.part < 0) {
+    op.epilogue(t.r0 + i, s1, s2, s3, red);
+  } else {
+    const int64_t x = (int64_t)t.part + i;
+    tpart[x] = s1;
+    if (has_split) tpart[pstride + x] = s2;
+    if constexpr (Op::NV == 2) tpart[2 * pstride + x] = s3;
+  }
+}
+
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_spmv(const Tile* __restrict__ tiles,
+                                                 const Sub* __restrict__ subs,
+                                                 const int32_t* __restrict__ trp,
+                                                 const int32_t* __restrict__ tsp,
                                                  const int32_t* __restrict__ col,
-                                                 const T* __restrict__ val, Op op, RedBuf rb,
+                                                 const T* __restrict__ val, Op op,
+                                                 T* __restrict__ tpart, int64_t pstride,
+                                                 double* __restrict__ partials,
                                                  const int32_t* __restrict__ gate) {
   if (gate && *gate) return;  // uniform across the grid: set before the launch
-  constexpr int NS = Op::NS > 0 ? Op::NS : 1;
+  using G = typename Gathered<Op, T>::type;
   constexpr int NV = Op::NV;
+  constexpr int NS = Op::NS > 0 ? Op::NS : 1;
   double red[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
 
-  constexpr int kCap = kStreamCap / NV;  // the two-product work list holds half as many nnz
-  __shared__ T prod[NV][kCap];
+  extern __shared__ __align__(16) unsigned char smem[];
+  G* win = reinterpret_cast<G*>(smem);
+  __shared__ T prod[NV][kSubCap];
   __shared__ T wsum[3][kBlock / 64];
-  const Item it = items[blockIdx.x];
+  const Tile t = tiles[blockIdx.x];
   const int tid = threadIdx.x;
+  const bool has_split = tsp != nullptr;
 
-  if (it.nchunk == 0 && it.k1 - it.k0 <= kCap) {
-    // ---- a run of whole rows: stage the products in LDS, then one lane group per row
-    const int cnt = it.k1 - it.k0;
+  // stage the gather window
+  if (t.wlen > 0) {
 #pragma unroll 8
-    for (int t = tid; t < cnt; t += kBlock) {
-      const int k = it.k0 + t;
-      const T v = ldm(&val[k]);
-      const int c = ldm(&col[k]);
-      if constexpr (NV == 2) {
-        const auto g = op.gather_pair(c);
-        prod[0][t] = v * g.x;
-        prod[NV - 1][t] = v * g.y;
-      } else {
-        prod[0][t] = v * op.gather(c);
-      }
-    }
+    for (int i = tid; i < t.wlen; i += kBlock) win[i] = fetch<T>(op, t.wlo + i);
     __syncthreads();
-    const int nrows = it.r1 - it.r0;
-    int L = 64;
-    while (L > 1 && L * nrows > kBlock) L >>= 1;
-    const int groups = kBlock / L;
-    const int g = tid / L, lane = tid % L;
-    for (int rr = g; rr < nrows; rr += groups) {
-      const int r = it.r0 + rr;
-      const int a = rowptr[r] - it.k0, b = rowptr[r + 1] - it.k0;
-      const int sp = split ? split[r] - it.k0 : b;
+  }
+  const unsigned wlen = (unsigned)t.wlen;
+  const int wlo = t.wlo;
+  auto gx = [&](int c) -> G {
+    const unsigned o = (unsigned)(c - wlo);
+    return o < wlen ? win[o] : fetch<T>(op, c);
+  };
+
+  for (int si = 0; si < t.nsub; ++si) {
+    const Sub u = subs[t.sub0 + si];
+    const int cnt = u.k1 - u.k0;
+    if (cnt > kSubCap) {
+      // ---- one long row: all threads stride its entries
+      const int i = u.i0;
+      const int sp = has_split ? tsp[t.tr + i] : u.k1;
       T s1 = T(0), s2 = T(0), s3 = T(0);
-      for (int t = a + lane; t < sp; t += L) s1 += prod[0][t];
-      for (int t = sp + lane; t < b; t += L) {
-        s2 += prod[0][t];
-        if constexpr (NV == 2) s3 += prod[NV - 1][t];
-      }
-      if (L > 1) {
-        s1 = wave_sum(s1, L);
-        s2 = wave_sum(s2, L);
-        if constexpr (NV == 2) s3 = wave_sum(s3, L);
-      }
-      if (lane == 0) op.epilogue(r, s1, s2, s3, red);
-    }
-  } else {
-    // ---- one long row (or one chunk of a very long row): all 256 threads stride its entries
-    const int r = it.r0;
-    const int sp = split ? split[r] : it.k1;
-    T s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll 4
-    for (int k = it.k0 + tid; k < it.k1; k += kBlock) {
-      const T v = ldm(&val[k]);
-      const int c = ldm(&col[k]);
-      if constexpr (NV == 2) {
-        const auto g = op.gather_pair(c);
-        if (k < sp) {
-          s1 += v * g.x;
-        } else {
-          s2 += v * g.x;
-          s3 += v * g.y;
-        }
-      } else {
-        const T pr = v * op.gather(c);
-        if (k < sp)
-          s1 += pr;
-        else
-          s2 += pr;
-      }
-    }
-    s1 = wave_sum(s1, 64);
-    s2 = wave_sum(s2, 64);
-    s3 = wave_sum(s3, 64);
-    if ((tid & 63) == 0) {
-      wsum[0][tid >> 6] = s1;
-      wsum[1][tid >> 6] = s2;
-      wsum[2][tid >> 6] = s3;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      s1 = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
-      s2 = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
-      s3 = (wsum[2][0] + wsum[2][1]) + (wsum[2][2] + wsum[2][3]);
-      if (it.nchunk == 0) {
-        op.epilogue(r, s1, s2, s3, red);
-      } else {
-        // rows longer than kLongCap: chunk partials, combined in chunk order by the last chunk
-        double* cp = rb.chunk_part + 3 * (size_t)(it.slot + it.chunk);
-        __hip_atomic_store(&cp[0], (double)s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&cp[1], (double)s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&cp[2], (double)s3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        uint32_t t = __hip_atomic_fetch_add(&rb.chunk_ticket[it.ticket], 1u, __ATOMIC_ACQ_REL,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        if (t == (uint32_t)(it.nchunk - 1)) {
-          __threadfence();
-          T S1 = T(0), S2 = T(0), S3 = T(0);
-          for (int c = 0; c < it.nchunk; ++c) {
-            const double* q = rb.chunk_part + 3 * (size_t)(it.slot + c);
-            S1 += (T)__hip_atomic_load(&q[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            S2 += (T)__hip_atomic_load(&q[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            S3 += (T)__hip_atomic_load(&q[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int k = u.k0 + tid; k < u.k1; k += kBlock) {
+        const T v = val[k];
+        const G x = gx(col[k]);
+        if constexpr (NV == 2) {
+          if (k < sp) {
+            s1 += v * x.x;
+          } else {
+            s2 += v * x.x;
+            s3 += v * x.y;
           }
-          __hip_atomic_store(&rb.chunk_ticket[it.ticket], 0u, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          op.epilogue(r, S1, S2, S3, red);
+        } else {
+          if (k < sp)
+            s1 += v * x;
+          else
+            s2 += v * x;
         }
       }
+      s1 = wave_sum(s1, 64);
+      s2 = wave_sum(s2, 64);
+      s3 = wave_sum(s3, 64);
+      if ((tid & 63) == 0) {
+        wsum[0][tid >> 6] = s1;
+        wsum[1][tid >> 6] = s2;
+        wsum[2][tid >> 6] = s3;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        s1 = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
+        s2 = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
+        s3 = (wsum[2][0] + wsum[2][1]) + (wsum[2][2] + wsum[2][3]);
+        row_done<T>(op, t, i, s1, s2, s3, red, tpart, pstride, has_split);
+      }
+      __syncthreads();
+    } else {
+      // ---- whole rows: products through LDS, then one power-of-two lane group per row
+#pragma unroll 8
+      for (int q = tid; q < cnt; q += kBlock) {
+        const int k = u.k0 + q;
+        const T v = val[k];
+        const G x = gx(col[k]);
+        if constexpr (NV == 2) {
+          prod[0][q] = v * x.x;
+          prod[NV - 1][q] = v * x.y;
+        } else {
+          prod[0][q] = v * x;
+        }
+      }
+      __syncthreads();
+      const int nr = u.i1 - u.i0;
+      int L = 64;
+      while (L > 1 && L * nr > kBlock) L >>= 1;
+      const int groups = kBlock / L, g = tid / L, lane = tid % L;
+      for (int rr = g; rr < nr; rr += groups) {
+        const int i = u.i0 + rr;
+        const int a = trp[t.tr + i] - u.k0, b = trp[t.tr + i + 1] - u.k0;
+        const int sp = has_split ? tsp[t.tr + i] - u.k0 : b;
+        T s1 = T(0), s2 = T(0), s3 = T(0);
+        for (int q = a + lane; q < sp; q += L) s1 += prod[0][q];
+        for (int q = sp + lane; q < b; q += L) {
+          s2 += prod[0][q];
+          if constexpr (NV == 2) s3 += prod[NV - 1][q];
+        }
+        if (L > 1) {
+          s1 = wave_sum(s1, L);
+          s2 = wave_sum(s2, L);
+          if constexpr (NV == 2) s3 = wave_sum(s3, L);
+        }
+        if (lane == 0) row_done<T>(op, t, i, s1, s2, s3, red, tpart, pstride, has_split);
+      }
+      __syncthreads();
     }
   }
   op.side();
-  if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, rb.partials);
+  if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }
 
+// Rows of multi-range blocks: add the partial sums in range order, then the epilogue. One
+// thread per row; the reduction partials go after those of the k_spmv launch.
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__ items,
+                                                    const T* __restrict__ tpart, int64_t pstride,
+                                                    int planes, Op op, double* __restrict__ partials,
+                                                    const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;
+  constexpr int NS = Op::NS > 0 ? Op::NS : 1;
+  double red[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) red[s] = 0.0;
+  const CombItem c = items[blockIdx.x];
+  const int r = c.r0 + (int)threadIdx.x;
+  if (r < c.r1) {
+    T s1 = T(0), s2 = T(0), s3 = T(0);
+    for (int j = 0; j < c.nrange; ++j) {
+      const int64_t i = (int64_t)c.part + (int64_t)j * c.stride + threadIdx.x;
+      s1 += tpart[i];
+      if (planes > 1) s2 += tpart[pstride + i];
+      if (planes > 2) s3 += tpart[2 * pstride + i];
+    }
+    op.epilogue(r, s1, s2, s3, red);
+  }
+  if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
+}
 // ------------------------------------------------------------------------------- SpMV epilogues
 
 #define QPG_NO_SIDE \

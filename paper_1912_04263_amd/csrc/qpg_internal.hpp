@@ -14,6 +14,9 @@ constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64
 constexpr int kStreamCap = 2048;    // nnz staged through LDS by one workgroup (rows fully inside)
 constexpr int kLongCap = 65536;     // a longer row is split into chunks of at most kChunk nnz
 constexpr int kChunk = 32768;
+constexpr int kTileNnz = 32768;    // SpMV entries per workgroup with an LDS gather window
+constexpr int kPlainNnz = 8192;    // SpMV entries per workgroup without one
+constexpr int kTileMaxRows = 4096; // rows per SpMV row block at most
 
 // One workgroup's share of a CSR SpMV.
 //   nchunk == 0: rows [r0, r1) entirely, entries [k0, k1) = [rowptr[r0], rowptr[r1]).
@@ -31,9 +34,69 @@ struct Plan {
   int32_t n_chunk_slots = 0;   // chunk partial slots needed
 };
 
-// Build the work list of a CSR matrix with nrows rows (Section 5.1.4: SpMV row sums are a
-// segmented reduction over the RowPointer segments; this balances it over workgroups).
+// Build the row work list of a CSR matrix with nrows rows (used by the learned preconditioner's
+// SpMM; Section 5.1.4: row sums are a segmented reduction over the RowPointer segments).
 Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = kStreamCap);
+
+// ---- SpMV work list (k_spmv / k_combine)
+//
+// The rows are cut into row blocks. A block is either single-range (each workgroup's row sums
+// are complete and go straight to the operation's epilogue) or multi-range: its column space is
+// cut into ranges, one workgroup per (block, range) computes partial row sums over the range,
+// and k_combine adds them in range order before the epilogue. Each workgroup may stage one
+// window of the gathered vector in LDS; gathers of columns inside it read LDS, the others read
+// memory. A random gather from memory costs a whole cache line for one value, so a window that
+// many of a workgroup's entries fall into turns most of the gather traffic into LDS reads.
+// The kernel streams entries in the plan's order: CSR order, except that a multi-range block's
+// entries are grouped range by range, so that each workgroup's entries are contiguous.
+
+constexpr int kSubCap = 1920;  // entries loaded through LDS at a time by one workgroup
+constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most)
+
+// One workgroup: rows r0 .. r0 + nrow − 1, restricted to one column range of their block. Row i
+// (local) has entries [trp[tr + i], trp[tr + i + 1]) in the plan's order; with a column split,
+// those from tsp[tr + i] on belong to the second part. The rows are processed in sub-runs
+// subs[sub0 .. sub0 + nsub). Columns in [wlo, wlo + wlen) are gathered from the LDS copy
+// (wlen = 0: no window). part < 0: complete row sums, epilogue here; otherwise partial sums,
+// stored at part + i.
+struct Tile {
+  int32_t r0, nrow, sub0, nsub, tr, wlo, wlen, part;
+};
+
+// Local rows [i0, i1) with entries [k0, k1): either whole rows with at most kSubCap entries in
+// total, or one longer row.
+struct Sub {
+  int32_t i0, i1, k0, k1;
+};
+
+// Rows [r0, r1) (at most kBlock) of a multi-range block: the partial sum of range j for row r
+// is at part + j·stride + (r − r0).
+struct CombItem {
+  int32_t r0, r1, nrange, part, stride, pad0, pad1, pad2;
+};
+
+struct TilePlan {
+  std::vector<Tile> tiles;
+  std::vector<Sub> subs;
+  std::vector<int32_t> trp;   // row starts per workgroup (nrow + 1 each)
+  std::vector<int32_t> tsp;   // first second-part entry per row (split matrices; same indexing)
+  std::vector<int32_t> perm;  // plan order → CSR index (empty: CSR order throughout)
+  std::vector<CombItem> comb;
+  int64_t n_part = 0;    // partial-sum slots per component
+  int32_t max_wlen = 0;  // largest staged window (gathered elements)
+};
+
+struct TileParams {
+  int32_t wcap;       // window capacity in columns (a power of two)
+  int32_t tile_nnz;   // target entries per workgroup when it stages a window
+  int32_t plain_nnz;  // target entries per workgroup without a window
+  int32_t max_rows;   // rows per block at most
+};
+
+// nrows × ncols CSR matrix with sorted column indices in each row; columns below nsplit form the
+// first part of a row (nsplit = ncols: no split).
+TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col, int32_t nrows,
+                    int32_t ncols, int32_t nsplit, const TileParams& tp);
 
 // The problem after validation, format conversion and Ruiz equilibration, all on the host.
 struct HostProblem {

@@ -452,6 +452,49 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
 
 }  // namespace
 
+void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr,
+                            const std::vector<int32_t>& col, int32_t nrows, int32_t ncols, int32_t nsplit) {
+  TileParams tp{win_cols, s.spmv_tile_nnz > 0 ? s.spmv_tile_nnz : kTileNnz,
+                s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows};
+  TilePlan t = make_tiles(rowptr, col, nrows, ncols, nsplit, tp);
+  if (t.tiles.empty()) {
+    t.tiles.push_back(Tile{0, 0, 0, 0, 0, 0, 0, -1});
+    t.trp.push_back(0);
+  }
+  pl.ntiles = (int32_t)t.tiles.size();
+  pl.tiles = upload(t.tiles);
+  pl.subs = upload(t.subs);
+  pl.trp = upload(t.trp);
+  pl.tsp = t.tsp.empty() ? nullptr : upload(t.tsp);
+  pl.ncomb = (int32_t)t.comb.size();
+  pl.comb = upload(t.comb);
+  pl.npart = t.n_part;
+  pl.part = alloc<double>(3 * (size_t)std::max<int64_t>(t.n_part, 1));
+  pl.max_wlen = t.max_wlen;
+  if (!t.perm.empty()) {
+    std::vector<int32_t> c(t.perm.size());
+    for (size_t k = 0; k < c.size(); ++k) c[k] = col[t.perm[k]];
+    pl.col = upload(c);
+    HIPCHK(hipStreamSynchronize(stream));
+    pl.perm = std::move(t.perm);
+  }
+  HIPCHK(hipStreamSynchronize(stream));  // t's host arrays go out of scope
+}
+
+// Values in the plan's order (a copy only where the plan reorders entries).
+template <typename T>
+void qpg_solver::place_values(DevPlan& pl, const std::vector<double>& csr_val) {
+  if (pl.perm.empty()) return;
+  std::vector<T> v(pl.perm.size());
+  for (size_t k = 0; k < v.size(); ++k) v[k] = (T)csr_val[pl.perm[k]];
+  T* d = upload(v);
+  HIPCHK(hipStreamSynchronize(stream));
+  if (std::is_same<T, double>::value)
+    pl.val64 = (double*)d;
+  else
+    pl.val32 = (float*)d;
+}
+
 extern "C" {
 
 int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t reps, double* avg_us) {
@@ -492,6 +535,8 @@ int qpg_default_settings(qpg_settings* s) {
   s->verbose = 0;
   s->precond_weights = nullptr;
   s->precond_trial = 1;
+  s->spmv_tile_nnz = kTileNnz;
+  s->spmv_plain_nnz = kPlainNnz;
   return QPG_OK;
 }
 
@@ -525,12 +570,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     HIPCHK(hipSetDevice(h->device));
     Plan pa = make_plan(H.a_ptr, H.m);
     Plan pb = make_plan(H.b_ptr, H.n);
-    Plan pb2 = make_plan(H.b_ptr, H.n, kStreamCap / 2);
-    for (Plan* pl : {&pa, &pb, &pb2})
+    for (Plan* pl : {&pa, &pb})
       if (pl->items.empty()) pl->items.push_back({0, 0, 0, 0, 0, 0, 0, 0});
     h->na_items = (int32_t)pa.items.size();
     h->nb_items = (int32_t)pb.items.size();
-    h->nb2_items = (int32_t)pb2.items.size();
     h->vgrid = grid_for(h->n);
     h->a_ptr = h->upload(H.a_ptr);
     h->a_col = h->upload(H.a_col);
@@ -539,7 +582,6 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->b_col = h->upload(H.b_col);
     h->a_items = h->upload(pa.items);
     h->b_items = h->upload(pb.items);
-    h->b2_items = h->upload(pb2.items);
     h->diagP = h->upload(H.diagP);
     h->colsq = h->upload(H.colsq);
     std::vector<double> dinv(H.n), einv(H.m);
@@ -547,13 +589,19 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     for (int i = 0; i < H.m; ++i) einv[i] = 1.0 / H.E[i];
     h->dscale = h->upload(dinv);
     h->escale = h->upload(einv);
-    int maxgrid = std::max(std::max(h->na_items, std::max(h->nb_items, h->nb2_items)), 1024);
+    // SpMV work lists: the window is sized so that a window of FP64 pairs, the product buffer
+    // and the reduction scratch fit in one workgroup's LDS
+    int lds_max = 0;
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    h->win_cols = kWinCols;
+    while (h->win_cols > 1024 &&
+           (size_t)h->win_cols * 16 + 2 * kSubCap * sizeof(double) + 2048 > (size_t)lds_max)
+      h->win_cols >>= 1;
+    h->build_plan(h->plan_a, H.a_ptr, H.a_col, H.m, H.n, H.n);
+    h->build_plan(h->plan_b, H.b_ptr, H.b_col, H.n, H.n + H.m, H.n);
+    int maxgrid = std::max(1024, std::max(h->na_items, h->nb_items));
+    for (const DevPlan* pl : {&h->plan_a, &h->plan_b}) maxgrid = std::max(maxgrid, pl->ntiles + pl->ncomb);
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
-    int slots = std::max(std::max(pa.n_chunk_slots, std::max(pb.n_chunk_slots, pb2.n_chunk_slots)), 1);
-    int tickets = std::max(std::max(pa.n_split_rows, std::max(pb.n_split_rows, pb2.n_split_rows)), 1);
-    h->rb.chunk_part = h->alloc<double>(3 * (size_t)slots);
-    h->rb.chunk_ticket = h->alloc<uint32_t>(tickets);
-    HIPCHK(hipMemsetAsync(h->rb.chunk_ticket, 0, tickets * sizeof(uint32_t), h->stream));
     h->st = h->alloc<DevState>(1);
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream));
     HIPCHK(hipHostMalloc((void**)&h->st_host, sizeof(DevState), hipHostMallocMapped));
@@ -561,6 +609,12 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     HIPCHK(hipHostGetDevicePointer((void**)&h->st_mirror_dev, h->st_host, 0));
     h->alloc_prec64(H);
     if (settings->precision == QPG_MIXED) h->alloc_prec32(H);
+    for (DevPlan* pl : {&h->plan_a, &h->plan_b}) {
+      const std::vector<double>& v = pl == &h->plan_a ? H.a_val : H.b_val;
+      h->place_values<double>(*pl, v);
+      if (settings->precision == QPG_MIXED) h->place_values<float>(*pl, v);
+      pl->perm = std::vector<int32_t>();
+    }
     for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);
     for (double* v : {h->p64.z, h->p64.y, h->p64.w, h->p64.zt, h->p64.ax}) h->fill(v, h->m, 0.0);
     if (h->p32.ready) {

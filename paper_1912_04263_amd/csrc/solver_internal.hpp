@@ -50,6 +50,25 @@ struct Prec {
   bool ready = false;
 };
 
+// Device copy of a SpMV work list (TilePlan). When the plan keeps CSR order, col and the value
+// arrays are null and the matrix's own CSR arrays are streamed.
+struct DevPlan {
+  Tile* tiles = nullptr;
+  int32_t ntiles = 0;
+  Sub* subs = nullptr;
+  int32_t* trp = nullptr;
+  int32_t* tsp = nullptr;
+  CombItem* comb = nullptr;
+  int32_t ncomb = 0;
+  int32_t* col = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  void* part = nullptr;  // partial sums: up to 3 planes of npart values (double-sized)
+  int64_t npart = 0;
+  int32_t max_wlen = 0;  // largest staged window, in columns
+  std::vector<int32_t> perm;  // host copy of the plan order (until the values are placed)
+};
+
 struct LearnedState;  // learned-preconditioner data of a solver (learned.hip)
 void destroy_learned(LearnedState* L);
 
@@ -65,8 +84,10 @@ struct qpg_solver {
   // structure shared by both precisions
   int32_t *a_ptr = nullptr, *a_col = nullptr, *b_ptr = nullptr, *b_split = nullptr,
           *b_col = nullptr;
-  Item *a_items = nullptr, *b_items = nullptr, *b2_items = nullptr;
-  int32_t na_items = 0, nb_items = 0, nb2_items = 0;
+  Item *a_items = nullptr, *b_items = nullptr;  // row work lists of the learned SpMM
+  int32_t na_items = 0, nb_items = 0;
+  DevPlan plan_a, plan_b;  // SpMV work lists of Ā and B
+  int32_t win_cols = 8192;  // LDS gather window capacity (columns)
   int32_t nnzA = 0, nnzB = 0;
   double *diagP = nullptr, *colsq = nullptr, *dscale = nullptr, *escale = nullptr;  // D⁻¹, E⁻¹
   DevState* st = nullptr;
@@ -128,21 +149,38 @@ struct qpg_solver {
   }
 
   // ----------------------------------------------------------------- launches
-  // SpMV launches; the returned grid size is the number of partials a finalize must combine.
+  // SpMV launches (k_spmv, then k_combine for multi-range blocks); the returned count is the
+  // number of workgroup partials a finalize must combine.
+  template <typename T, class Op>
+  int spmv(const DevPlan& pl, const int32_t* csr_col, const T* csr_val, bool split, const Op& op,
+           const int32_t* gate) {
+    using G = typename Gathered<Op, T>::type;
+    const size_t shmem = (size_t)pl.max_wlen * sizeof(G);
+    static size_t lds_allowed = 0;  // per instantiation: raise the dynamic LDS limit once
+    if (shmem > lds_allowed) {
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<T, Op>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+      lds_allowed = shmem;
+    }
+    const int32_t* col = pl.col ? pl.col : csr_col;
+    const T* val = csr_val;
+    if (pl.col) val = std::is_same<T, double>::value ? (const T*)pl.val64 : (const T*)pl.val32;
+    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kBlock), shmem, stream, pl.tiles, pl.subs,
+                       pl.trp, split ? pl.tsp : nullptr, col, val, op, static_cast<T*>(pl.part), pl.npart,
+                       rb.partials, gate);
+    if (pl.ncomb > 0)
+      hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb,
+                         (const T*)static_cast<T*>(pl.part), pl.npart, split ? (Op::NV == 2 ? 3 : 2) : 1, op,
+                         rb.partials + (size_t)pl.ntiles * kMaxSlots, gate);
+    return pl.ntiles + pl.ncomb;
+  }
   template <typename T, class Op>
   int spmv_A(const Op& op, const int32_t* gate = nullptr) {
-    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(na_items), dim3(kBlock), 0, stream, a_items, a_ptr,
-                       (const int32_t*)nullptr, a_col, P<T>().a_val, op, rb, gate);
-    return na_items;
+    return spmv<T>(plan_a, a_col, P<T>().a_val, false, op, gate);
   }
   template <typename T, class Op>
   int spmv_B(const Op& op, const int32_t* gate = nullptr) {
-    // two-product passes stage twice the products: they use the half-size work list
-    const Item* items = Op::NV == 2 ? b2_items : b_items;
-    const int ni = Op::NV == 2 ? nb2_items : nb_items;
-    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(ni), dim3(kBlock), 0, stream, items, b_ptr, b_split,
-                       b_col, P<T>().b_val, op, rb, gate);
-    return ni;
+    return spmv<T>(plan_b, b_col, P<T>().b_val, true, op, gate);
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
   template <class Op>
@@ -239,6 +277,10 @@ struct qpg_solver {
   int admm(int k_start, double& rho, double& eps_pcg, int& status, int& fallback_request);
 
   int solve();
+  void build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
+                  int32_t nrows, int32_t ncols, int32_t nsplit);
+  template <typename T>
+  void place_values(DevPlan& pl, const std::vector<double>& csr_val);
   void alloc_prec64(const HostProblem& H);
   void alloc_prec32(const HostProblem& H);
 };

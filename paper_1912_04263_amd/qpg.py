@@ -42,7 +42,8 @@ class Settings(C.Structure):
                 ("pcg_max_iter", C.c_int32), ("pcg_rel_test", C.c_int32),
                 ("scaling_iters", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
                 ("device", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
-                ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32)]
+                ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32),
+                ("spmv_tile_nnz", C.c_int32), ("spmv_plain_nnz", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -41,7 +41,8 @@ int main(void) {
          offsetof(qpg_settings, verbose), offsetof(qpg_settings, rho_update_gate));
   printf("%zu %zu %zu %zu\n", offsetof(qpg_info, obj_val), offsetof(qpg_info, solve_time),
          offsetof(qpg_info, scaling_passes), offsetof(qpg_info, precond_switches));
-  printf("%zu %zu\n", offsetof(qpg_settings, precond_weights), offsetof(qpg_settings, precond_trial));
+  printf("%zu %zu %zu\n", offsetof(qpg_settings, precond_weights), offsetof(qpg_settings, precond_trial),
+         offsetof(qpg_settings, spmv_plain_nnz));
   printf("%d\n", QPG_NET_NPARAMS);
   return 0;
 }
@@ -57,7 +58,7 @@ int main(void) {
     want = [C.sizeof(qpg.Csc), C.sizeof(S), C.sizeof(I),
             S.pcg_max_iter.offset, S.stream.offset, S.verbose.offset, S.rho_update_gate.offset,
             I.obj_val.offset, I.solve_time.offset, I.scaling_passes.offset, I.precond_switches.offset,
-            S.precond_weights.offset, S.precond_trial.offset, qpg.QPG_NET_NPARAMS]
+            S.precond_weights.offset, S.precond_trial.offset, S.spmv_plain_nnz.offset, qpg.QPG_NET_NPARAMS]
     assert got == want
 
 

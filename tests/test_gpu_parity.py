@@ -6,8 +6,9 @@ Tolerances:
 * SpMV FP32: ≤ 1e-5 on the same scale (inputs rounded to 2⁻²⁴, accumulation in float).
 * Final answer at eps_abs = eps_rel = 1e-5: |f − f*| ≤ 1e-4·max(1, |f*|) and
   ‖x − x*‖∞ ≤ 1e-3·‖x*‖∞ against the oracle run to 1e-9. Portfolio instances are compared at
-  eps 1e-6: the method itself (the oracle's exact-solve ADMM) stopped at 1e-5 is 3.5e-4 off in
-  objective on them, so no implementation can meet the bar there at 1e-5.
+  eps 1e-7: the method itself (the oracle's exact-solve ADMM) stopped at 1e-5 is 3.5e-4 off in
+  objective on them, and stopped at 1e-6 it is still ≈1e-3 off in x (measured: 0.98e-3 in
+  FP64), so only a tighter stop separates implementation error from the method's own.
 * Iterate trace with a near-exact PCG (fixed relative tolerance 1e-13) against the oracle's
   direct KKT solves: 1e-8 relative.
 """
@@ -203,7 +204,7 @@ def test_final_answer_matches_oracle(name, precision):
     p = problem(name)
     ref = oracle_solution(name)
     assert ref.status == "solved"
-    eps = 1e-6 if name.startswith("portfolio") else 1e-5
+    eps = 1e-7 if name.startswith("portfolio") else 1e-5
     with qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, max_iter=20000, precision=precision) as s:
         info = s.solve()
         assert info.status == "solved", info

@@ -1,0 +1,94 @@
+"""Host logic of the SpMV work lists (csrc/tiles.cpp), checked on the CPU.
+
+tests/native/plan_check.cpp is built with g++ against tiles.cpp; on each matrix it checks every
+bound the SpMV kernels rely on (rows, sub-runs, row starts, split positions, LDS windows, partial
+and combine slots), that the entry order is a permutation, that every entry is streamed exactly
+once, and that the row sums formed the kernels' way match a plain CSR product to 1e-12.
+"""
+import functools
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1912_04263_amd import problems as pr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1912_04263_amd", "csrc")
+
+
+@functools.lru_cache(maxsize=None)
+def checker(tmpdir):
+    exe = os.path.join(tmpdir, "plan_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "native", "plan_check.cpp"),
+                    os.path.join(CSRC, "tiles.cpp"), "-o", exe], check=True)
+    return exe
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    return checker(str(tmp_path_factory.mktemp("plan")))
+
+
+def run(exe, tmp_path, M, nsplit=None, tile_nnz=32768, plain_nnz=8192, wcap=8192):
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    pre = str(tmp_path / "m")
+    M.indptr.astype(np.int32).tofile(pre + "_ptr.bin")
+    M.indices.astype(np.int32).tofile(pre + "_col.bin")
+    ncols = M.shape[1]
+    out = subprocess.run([exe, pre, str(ncols), str(ncols if nsplit is None else nsplit), str(tile_nnz),
+                          str(plain_nnz), str(wcap)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    return out.stdout
+
+
+def reduced_pair(p):
+    A = sp.csr_matrix(p.A)
+    B = sp.hstack([p.P_full().tocsr(), A.T.tocsr()]).tocsr()
+    return A, B
+
+
+@pytest.mark.parametrize("name", ["random_c0", "random_small", "lasso_small", "portfolio_small", "svm_small",
+                                  "random2_small"])
+@pytest.mark.parametrize("wcap", [1024, 8192])
+def test_work_lists_of_the_generated_workloads(exe, tmp_path, name, wcap):
+    p = pr.make(name)
+    A, B = reduced_pair(p)
+    run(exe, tmp_path, A, wcap=wcap)
+    run(exe, tmp_path, B, nsplit=p.n, wcap=wcap)
+
+
+def test_wide_rows_take_the_multi_range_layout(exe, tmp_path):
+    rng = np.random.default_rng(1)
+    M = sp.random(200, 100000, density=0.02, random_state=rng, format="csr")
+    out = run(exe, tmp_path, M, nsplit=30000)
+    assert "reordered 1" in out and " multi 0 " not in out
+
+
+def test_long_rows_in_a_narrow_band_and_empty_rows(exe, tmp_path):
+    rng = np.random.default_rng(2)
+    rows, cols = [], []
+    for r in range(60):
+        if r % 7 == 3:
+            continue  # empty row
+        n = 6000 if r % 2 else int(rng.integers(1, 40))
+        c0 = int(rng.integers(0, 2000))
+        rows += [r] * n
+        cols += list(range(c0, c0 + n))
+    M = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(60, 9000))
+    out = run(exe, tmp_path, M, nsplit=4000)
+    assert " long 0 " not in out
+
+
+def test_empty_and_one_entry_matrices(exe, tmp_path):
+    run(exe, tmp_path, sp.csr_matrix((5, 7)))
+    run(exe, tmp_path, sp.csr_matrix(([2.0], ([3], [6])), shape=(5, 7)), nsplit=4)
+
+
+def test_small_work_units_on_a_random_matrix(exe, tmp_path):
+    rng = np.random.default_rng(3)
+    M = sp.random(3000, 50000, density=2e-3, random_state=rng, format="csr")
+    run(exe, tmp_path, M, nsplit=20000, tile_nnz=1024, plain_nnz=1024, wcap=2048)
