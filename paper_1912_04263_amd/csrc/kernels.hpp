@@ -1,13 +1,11 @@
 // Device kernels of the ADMM / reduced-KKT PCG path for gfx950 (wavefront 64, 256-thread
 // workgroups). Included by solver.hip only.
 //
-// All SpMVs run through one kernel template, k_spmv, driven by a host-built Tile work list:
-// each workgroup takes a block of rows restricted to one column range, optionally stages a window
-// of the gathered vector in LDS (gathers inside it read LDS, the rest read memory), and sums each
-// row with a group of lanes (1–64 lanes, several rows in flight per group) or with the whole
-// workgroup for long rows. Complete row sums go to an operation-specific epilogue (the fused
-// vector work of the ADMM / PCG step); the partial sums of multi-range blocks are added in range
-// order by k_combine, which then runs the same epilogue. Reduction contributions (FP64 sums and
+// Every SpMV runs in two launches of one kernel pair: k_spmv streams the matrix in SELL chunks
+// (one lane per row segment, 64 consecutive entries per load instruction, no barrier), gathering
+// from a window of the multiplied vector staged in LDS where one is planned, and writes segment
+// sums to slots; k_combine adds each row's slots in a fixed order and runs an operation-specific
+// epilogue (the fused vector work of the ADMM / PCG step). Reduction contributions (FP64 sums and
 // ∞-norms) are combined deterministically: per-workgroup partials, reduced in a fixed order by
 // k_finalize, which also runs the scalar finalisation (α, β, stopping flags) on the device.
 #pragma once
@@ -163,16 +161,17 @@ __device__ __forceinline__ T wave_sum(T x, int width) {
 }
 
 // ----------------------------------------------------------------------------------------------
-// CSR SpMV with fused epilogue, driven by a Tile work list (one workgroup per tile). Op supplies:
+// CSR SpMV with fused epilogue, in two launches: k_spmv sums the segments of a Tile work list
+// (SELL chunks, one lane per segment, no barrier after the window is staged) into slots, and
+// k_combine adds each row's slots in order and runs the epilogue. Op supplies:
 //   static constexpr int NS;            reduction slots (0: none)
 //   static constexpr unsigned MAXMASK;  bit s set: slot s is an ∞-norm (max), else a sum
-//   static constexpr int NV;            products per entry: 1, or 2
-//   T gather(int col) const;            multiplied vector (NV == 1)
-//   T2 gather_pair(int col) const;      both multiplied vectors from one load (NV == 2)
+//   static constexpr int NV;            products per entry: 1, or 2 (a pair of vectors)
+//   G gather(int col) const;            the multiplied value(s) of column col (G = T, or a pair)
 //   void epilogue(int row, T s1, T s2, T s3, double* red) const;
-//        s1 / s2: first product summed over the entries before / from split[row];
-//        s3: second product summed over the entries from split[row]
-//   void side() const;                  extra elementwise work (grid-stride)
+//        s1 / s2: first product summed over the entries with column < nsplit / ≥ nsplit;
+//        s3: second product summed over the entries with column ≥ nsplit
+//   void side() const;                  extra elementwise work (grid-stride, in k_spmv)
 //   void operator()(const double* totals) const;  scalar finalisation (run by k_finalize)
 // ----------------------------------------------------------------------------------------------
 template <class Op, typename T>
@@ -180,159 +179,77 @@ struct Gathered {
   using type = typename std::conditional<Op::NV == 2, pair_t<T>, T>::type;
 };
 
-template <typename T, class Op>
-__device__ __forceinline__ typename Gathered<Op, T>::type fetch(const Op& op, int c) {
-  if constexpr (Op::NV == 2)
-    return op.gather_pair(c);
-  else
-    return op.gather(c);
-}
-
-// Complete row sums go to the epilogue; partial ones to the partial planes (s1, s2, s3 at
-// offsets 0, pstride, 2·pstride).
-template <typename T, class Op>
-__device__ __forceinline__ void row_done(const Op& op, const Tile& t, int i, T s1, T s2, T s3,
-                                         double* red, T* __restrict__ tpart, int64_t pstride,
-                                         bool has_split) {
-  if (t.part < 0) {
-    op.epilogue(t.r0 + i, s1, s2, s3, red);
+template <typename T, class G>
+__device__ __forceinline__ void accumulate(T v, const G& x, bool first, T& s1, T& s2, T& s3) {
+  if constexpr (std::is_same<G, T>::value) {
+    const T pr = v * x;
+    s1 += first ? pr : T(0);
+    s2 += first ? T(0) : pr;
   } else {
-    const int64_t x = (int64_t)t.part + i;
-    tpart[x] = s1;
-    if (has_split) tpart[pstride + x] = s2;
-    if constexpr (Op::NV == 2) tpart[2 * pstride + x] = s3;
+    const T p0 = v * x.x, p1 = v * x.y;
+    s1 += first ? p0 : T(0);
+    s2 += first ? T(0) : p0;
+    s3 += first ? T(0) : p1;
   }
 }
 
+constexpr int kSpmvUnroll = 8;  // SELL steps in flight per lane
+
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_spmv(const Tile* __restrict__ tiles,
-                                                 const Sub* __restrict__ subs,
-                                                 const int32_t* __restrict__ trp,
-                                                 const int32_t* __restrict__ tsp,
-                                                 const int32_t* __restrict__ col,
-                                                 const T* __restrict__ val, Op op,
-                                                 T* __restrict__ tpart, int64_t pstride,
-                                                 double* __restrict__ partials,
+__global__ __launch_bounds__(kSpmvBlock) void k_spmv(const Tile* __restrict__ tiles,
+                                                 const Chunk* __restrict__ chunks,
+                                                 const int32_t* __restrict__ segslot,
+                                                 const uint16_t* __restrict__ col16,
+                                                 const int32_t* __restrict__ col32,
+                                                 const T* __restrict__ val, int nsplit, Op op,
+                                                 T* __restrict__ slots, int64_t pstride, int planes,
                                                  const int32_t* __restrict__ gate) {
   if (gate && *gate) return;  // uniform across the grid: set before the launch
   using G = typename Gathered<Op, T>::type;
-  constexpr int NV = Op::NV;
-  constexpr int NS = Op::NS > 0 ? Op::NS : 1;
-  double red[NS];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) red[s] = 0.0;
-
   extern __shared__ __align__(16) unsigned char smem[];
   G* win = reinterpret_cast<G*>(smem);
-  __shared__ T prod[NV][kSubCap];
-  __shared__ T wsum[3][kBlock / 64];
   const Tile t = tiles[blockIdx.x];
-  const int tid = threadIdx.x;
-  const bool has_split = tsp != nullptr;
-
-  // stage the gather window
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (t.wlen > 0) {
 #pragma unroll 8
-    for (int i = tid; i < t.wlen; i += kBlock) win[i] = fetch<T>(op, t.wlo + i);
+    for (int i = threadIdx.x; i < t.wlen; i += kSpmvBlock) win[i] = op.gather(t.wlo + i);
     __syncthreads();
   }
-  const unsigned wlen = (unsigned)t.wlen;
-  const int wlo = t.wlo;
-  auto gx = [&](int c) -> G {
-    const unsigned o = (unsigned)(c - wlo);
-    return o < wlen ? win[o] : fetch<T>(op, c);
-  };
-
-  for (int si = 0; si < t.nsub; ++si) {
-    const Sub u = subs[t.sub0 + si];
-    const int cnt = u.k1 - u.k0;
-    if (cnt > kSubCap) {
-      // ---- one long row: all threads stride its entries
-      const int i = u.i0;
-      const int sp = has_split ? tsp[t.tr + i] : u.k1;
-      T s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll 4
-      for (int k = u.k0 + tid; k < u.k1; k += kBlock) {
-        const T v = val[k];
-        const G x = gx(col[k]);
-        if constexpr (NV == 2) {
-          if (k < sp) {
-            s1 += v * x.x;
-          } else {
-            s2 += v * x.x;
-            s3 += v * x.y;
-          }
-        } else {
-          if (k < sp)
-            s1 += v * x;
-          else
-            s2 += v * x;
-        }
+  for (int ci = t.chunk0 + wave; ci < t.chunk0 + t.nchunk; ci += kSpmvBlock / 64) {
+    const Chunk ch = chunks[ci];
+    const int slot = segslot[ch.seg0 + lane];
+    const T* vp = val + ch.base + lane;
+    T s1 = T(0), s2 = T(0), s3 = T(0);
+    if (t.wlen > 0) {
+      const uint16_t* cp = col16 + ch.cbase + lane;
+      const int lim = nsplit - t.wlo;  // window offsets below lim belong to the first part
+#pragma unroll kSpmvUnroll
+      for (int s = 0; s < ch.steps; ++s) {
+        const int o = cp[64 * s];
+        accumulate(vp[64 * s], win[o], o < lim, s1, s2, s3);
       }
-      s1 = wave_sum(s1, 64);
-      s2 = wave_sum(s2, 64);
-      s3 = wave_sum(s3, 64);
-      if ((tid & 63) == 0) {
-        wsum[0][tid >> 6] = s1;
-        wsum[1][tid >> 6] = s2;
-        wsum[2][tid >> 6] = s3;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        s1 = (wsum[0][0] + wsum[0][1]) + (wsum[0][2] + wsum[0][3]);
-        s2 = (wsum[1][0] + wsum[1][1]) + (wsum[1][2] + wsum[1][3]);
-        s3 = (wsum[2][0] + wsum[2][1]) + (wsum[2][2] + wsum[2][3]);
-        row_done<T>(op, t, i, s1, s2, s3, red, tpart, pstride, has_split);
-      }
-      __syncthreads();
     } else {
-      // ---- whole rows: products through LDS, then one power-of-two lane group per row
-#pragma unroll 8
-      for (int q = tid; q < cnt; q += kBlock) {
-        const int k = u.k0 + q;
-        const T v = val[k];
-        const G x = gx(col[k]);
-        if constexpr (NV == 2) {
-          prod[0][q] = v * x.x;
-          prod[NV - 1][q] = v * x.y;
-        } else {
-          prod[0][q] = v * x;
-        }
+      const int32_t* cp = col32 + ch.cbase + lane;
+#pragma unroll kSpmvUnroll
+      for (int s = 0; s < ch.steps; ++s) {
+        const int c = cp[64 * s];
+        accumulate(vp[64 * s], op.gather(c), c < nsplit, s1, s2, s3);
       }
-      __syncthreads();
-      const int nr = u.i1 - u.i0;
-      int L = 64;
-      while (L > 1 && L * nr > kBlock) L >>= 1;
-      const int groups = kBlock / L, g = tid / L, lane = tid % L;
-      for (int rr = g; rr < nr; rr += groups) {
-        const int i = u.i0 + rr;
-        const int a = trp[t.tr + i] - u.k0, b = trp[t.tr + i + 1] - u.k0;
-        const int sp = has_split ? tsp[t.tr + i] - u.k0 : b;
-        T s1 = T(0), s2 = T(0), s3 = T(0);
-        for (int q = a + lane; q < sp; q += L) s1 += prod[0][q];
-        for (int q = sp + lane; q < b; q += L) {
-          s2 += prod[0][q];
-          if constexpr (NV == 2) s3 += prod[NV - 1][q];
-        }
-        if (L > 1) {
-          s1 = wave_sum(s1, L);
-          s2 = wave_sum(s2, L);
-          if constexpr (NV == 2) s3 = wave_sum(s3, L);
-        }
-        if (lane == 0) row_done<T>(op, t, i, s1, s2, s3, red, tpart, pstride, has_split);
-      }
-      __syncthreads();
+    }
+    if (slot >= 0) {
+      slots[slot] = s1;
+      if (planes > 1) slots[pstride + slot] = s2;
+      if (planes > 2) slots[2 * pstride + slot] = s3;
     }
   }
   op.side();
-  if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }
 
-// Rows of multi-range blocks: add the partial sums in range order, then the epilogue. One
-// thread per row; the reduction partials go after those of the k_spmv launch.
+// Row sums from the slots (fixed order: the row's segments in column order), then the epilogue.
+// One thread per row; reduction partials per workgroup for k_finalize.
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__ items,
-                                                    const T* __restrict__ tpart, int64_t pstride,
+__global__ __launch_bounds__(kBlock) void k_combine(int nrows, const int32_t* __restrict__ rowslot,
+                                                    const T* __restrict__ slots, int64_t pstride,
                                                     int planes, Op op, double* __restrict__ partials,
                                                     const int32_t* __restrict__ gate) {
   if (gate && *gate) return;
@@ -340,15 +257,14 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
   double red[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
-  const CombItem c = items[blockIdx.x];
-  const int r = c.r0 + (int)threadIdx.x;
-  if (r < c.r1) {
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  if (r < nrows) {
     T s1 = T(0), s2 = T(0), s3 = T(0);
-    for (int j = 0; j < c.nrange; ++j) {
-      const int64_t i = (int64_t)c.part + (int64_t)j * c.stride + threadIdx.x;
-      s1 += tpart[i];
-      if (planes > 1) s2 += tpart[pstride + i];
-      if (planes > 2) s3 += tpart[2 * pstride + i];
+    const int q1 = rowslot[r + 1];
+    for (int q = rowslot[r]; q < q1; ++q) {
+      s1 += slots[q];
+      if (planes > 1) s2 += slots[pstride + q];
+      if (planes > 2) s3 += slots[2 * pstride + q];
     }
     op.epilogue(r, s1, s2, s3, red);
   }
@@ -402,8 +318,9 @@ struct OpB {
 //   b  = σx − q̄ + Āᵀ(ρ̄z − y)                                   (only ‖b‖∞ is needed)
 //   r⁰ = Kx̃ − b = P̄x̃ + σ(x̃ − x) + q̄ + Āᵀ(ρ̄(z̃ − z) + y),  z̃ = Āx̃
 //   p⁰ = −M⁻¹r⁰;  rᵀM⁻¹r;  ‖r‖∞.
-// The two m-vectors ρ̄(z̃ − z) + y and ρ̄z − y are written, interleaved, by the update pass that
-// produced z̃, z and y (OpUpdate), so each Āᵀ entry costs a single gather.
+// The update pass that produced z̃, z and y (OpUpdate) writes one array of n + m pairs: (x̃_i, 0)
+// for the P̄ columns, then (ρ̄(z̃ − z) + y, ρ̄z − y) for the Āᵀ columns, so each entry of B costs
+// a single gather from a single array.
 template <typename T>
 struct OpRhsR0 {
   QPG_NO_SIDE
@@ -413,7 +330,7 @@ struct OpRhsR0 {
   const T* x;
   const T* xt;
   const T* qb;
-  const pair_t<T>* vw;  // (ρ̄(z̃ − z) + y, ρ̄z − y)
+  const pair_t<T>* gp;  // n + m pairs: (x̃, 0), then (ρ̄(z̃ − z) + y, ρ̄z − y)
   const T* dinv;
   T* r;
   T* p;
@@ -421,10 +338,7 @@ struct OpRhsR0 {
   int n, maxit, rel;
   double eps;
   DevState* st;
-  __device__ pair_t<T> gather_pair(int c) const {
-    if (c < n) return pair_t<T>{xt[c], T(0)};
-    return vw[c - n];
-  }
+  __device__ pair_t<T> gather(int c) const { return gp[c]; }
   __device__ void epilogue(int i, T s1, T s2, T s3, double* red) const {
     const T xi = x[i];
     const T bi = sigma * xi - qb[i] + s3;
@@ -486,6 +400,7 @@ struct OpR0 {
 };
 
 // PCG K-matvec, second half: Kp = P̄p + σp + Āᵀw (w = ρ̄Āp); κ = pᵀKp; α = rᵀM⁻¹r / κ.
+// p and w are the two parts of one allocation (w = p + n), so column c of B gathers p[c].
 template <typename T>
 struct OpKp {
   QPG_NO_SIDE
@@ -498,7 +413,7 @@ struct OpKp {
   T sigma;
   int n;
   DevState* st;
-  __device__ T gather(int c) const { return c < n ? p[c] : w[c - n]; }
+  __device__ T gather(int c) const { return p[c]; }
   __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
     const T pi = p[i];
     const T k = s1 + s2 + sigma * pi;
@@ -522,9 +437,9 @@ struct OpKp {
 // ADMM update (Algorithm 1, relaxation, projection and dual steps) fused with z̃ = Āx̃
 // (Section 4) over the rows of Ā:
 //   v = αz̃ + (1−α)z;  z⁺ = Π_[l̄,ū](v + y/ρ̄);  y ← y + ρ̄(v − z⁺);  z̃ kept, and the pair
-//   (ρ̄(z̃ − z⁺) + y⁺, ρ̄z⁺ − y⁺) written for the next OpRhsR0;
+//   (ρ̄(z̃ − z⁺) + y⁺, ρ̄z⁺ − y⁺) written for the next OpRhsR0 (after the n pairs (x̃, 0));
 //   Āx ← αz̃ + (1−α)Āx when `ax` is tracked (x ← αx̃ + (1−α)x makes this exact);
-//   side task: x ← αx̃ + (1−α)x.
+//   side task: x ← αx̃ + (1−α)x, and the pairs (x̃, 0).
 // With CHECK, the primal residual r̄_p = Āx − z⁺ and its norms are reduced as well:
 // slots ‖r̄_p‖, ‖E⁻¹r̄_p‖, ‖Āx‖, ‖E⁻¹Āx‖, ‖z‖, ‖E⁻¹z‖ → norms[0..5].
 template <typename T, bool CHECK>
@@ -538,7 +453,7 @@ struct OpUpdate {
   T* y;
   T* zt;
   T* ax;
-  pair_t<T>* vw;
+  pair_t<T>* gp;  // n + m pairs read by the next OpRhsR0
   const T* lb;
   const T* ub;
   const double* einv;
@@ -556,7 +471,7 @@ struct OpUpdate {
     y[i] = yn;
     z[i] = zn;
     zt[i] = s1;
-    vw[i] = pair_t<T>{rho * (s1 - zn) + yn, rho * zn - yn};
+    gp[n + i] = pair_t<T>{rho * (s1 - zn) + yn, rho * zn - yn};
     if (ax) {
       const T a = alpha * s1 + (T(1) - alpha) * ax[i];
       ax[i] = a;
@@ -573,8 +488,11 @@ struct OpUpdate {
     }
   }
   __device__ void side() const {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-      x[i] = alpha * xt[i] + (T(1) - alpha) * x[i];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+      const T xti = xt[i];
+      x[i] = alpha * xti + (T(1) - alpha) * x[i];
+      gp[i] = pair_t<T>{xti, T(0)};
+    }
   }
   __device__ void operator()(const double* t) const {
     for (int s = 0; s < 6; ++s) st->norms[s] = t[s];
@@ -623,7 +541,7 @@ struct OpRDual {
   const double* dinv_scale;
   int n;
   DevState* st;
-  __device__ T gather(int c) const { return c < n ? x[c] : y[c - n]; }
+  __device__ T gather(int c) const { return x[c]; }  // y = x + n (one allocation)
   __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
     const double px = (double)s1, aty = (double)s2, d = dinv_scale[i];
     const double rd = px + (double)qb[i] + aty;
@@ -702,13 +620,20 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
     dinv[i] = (T)(1.0 / (diagP[i] + sigma + rho * colsq[i]));
 }
 
-// (ρ̄(z̃ − z) + y, ρ̄z − y) from z̃, z, y — after ρ̄ changes or the precision switches.
+// The pairs read by OpRhsR0: (x̃, 0) for the n P̄ columns, (ρ̄(z̃ − z) + y, ρ̄z − y) for the m
+// Āᵀ columns — at the start, after ρ̄ changes, and after the precision switches.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pairs(int m, pair_t<T>* __restrict__ vw,
-                                                  const T* __restrict__ zt, const T* __restrict__ z,
-                                                  const T* __restrict__ y, T rho) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock)
-    vw[i] = pair_t<T>{rho * (zt[i] - z[i]) + y[i], rho * z[i] - y[i]};
+__global__ __launch_bounds__(kBlock) void k_pairs(int n, int m, pair_t<T>* __restrict__ gp,
+                                                  const T* __restrict__ xt, const T* __restrict__ zt,
+                                                  const T* __restrict__ z, const T* __restrict__ y, T rho) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + m; i += gridDim.x * kBlock) {
+    if (i < n) {
+      gp[i] = pair_t<T>{xt[i], T(0)};
+    } else {
+      const int j = i - n;
+      gp[i] = pair_t<T>{rho * (zt[j] - z[j]) + y[j], rho * z[j] - y[j]};
+    }
+  }
 }
 
 template <typename T>

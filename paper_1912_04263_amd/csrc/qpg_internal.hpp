@@ -40,63 +40,61 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = 
 
 // ---- SpMV work list (k_spmv / k_combine)
 //
-// The rows are cut into row blocks. A block is either single-range (each workgroup's row sums
-// are complete and go straight to the operation's epilogue) or multi-range: its column space is
-// cut into ranges, one workgroup per (block, range) computes partial row sums over the range,
-// and k_combine adds them in range order before the epilogue. Each workgroup may stage one
-// window of the gathered vector in LDS; gathers of columns inside it read LDS, the others read
-// memory. A random gather from memory costs a whole cache line for one value, so a window that
-// many of a workgroup's entries fall into turns most of the gather traffic into LDS reads.
-// The kernel streams entries in the plan's order: CSR order, except that a multi-range block's
-// entries are grouped range by range, so that each workgroup's entries are contiguous.
+// Each row is cut into segments of at most kSegMax entries. One lane sums one segment; 64
+// segments form a chunk, stored in SELL order (entry s of lane j at base + 64·s + j, so that
+// every load instruction of a wavefront reads 64 consecutive entries), and a workgroup streams
+// the chunks of one tile with no barrier. The segments of a tile are sorted by length so that
+// the lanes of a chunk end together; the shorter ones are padded with zero values (and a column
+// the lane reads anyway).
+//
+// A tile either gathers from a window of the vector staged in LDS (all its entries fall inside
+// the window; their column indices are stored as 16-bit offsets into it), or from memory (32-bit
+// column indices). A random gather from memory costs a whole cache line for one value; an LDS
+// window that many entries fall into turns that traffic into LDS reads.
+//
+// Row blocks are single-range (all columns) or, where rows are wide, multi-range: the columns are
+// cut at dense windows and each (block, range) gets its own windowed tile. Segment sums go to
+// slots, numbered row by row; k_combine adds each row's slots in order and runs the operation's
+// epilogue.
 
-constexpr int kSubCap = 1920;  // entries loaded through LDS at a time by one workgroup
-constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most)
+constexpr int kSegMax = 256;   // entries of one segment at most
+constexpr int kSpmvBlock = 256; // threads per SpMV workgroup (one chunk at a time per wavefront)
+constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most; ≤ 65536)
 
-// One workgroup: rows r0 .. r0 + nrow − 1, restricted to one column range of their block. Row i
-// (local) has entries [trp[tr + i], trp[tr + i + 1]) in the plan's order; with a column split,
-// those from tsp[tr + i] on belong to the second part. The rows are processed in sub-runs
-// subs[sub0 .. sub0 + nsub). Columns in [wlo, wlo + wlen) are gathered from the LDS copy
-// (wlen = 0: no window). part < 0: complete row sums, epilogue here; otherwise partial sums,
-// stored at part + i.
+struct Chunk {
+  int32_t base;   // first value (SELL order)
+  int32_t cbase;  // first column index, in the 16-bit array (windowed tile) or the 32-bit one
+  int32_t steps;  // length of the longest segment
+  int32_t seg0;   // index of the chunk's first segment slot
+};
+
+// chunks [chunk0, chunk0 + nchunk); wlen > 0: gathers read the LDS copy of [wlo, wlo + wlen).
 struct Tile {
-  int32_t r0, nrow, sub0, nsub, tr, wlo, wlen, part;
-};
-
-// Local rows [i0, i1) with entries [k0, k1): either whole rows with at most kSubCap entries in
-// total, or one longer row.
-struct Sub {
-  int32_t i0, i1, k0, k1;
-};
-
-// Rows [r0, r1) (at most kBlock) of a multi-range block: the partial sum of range j for row r
-// is at part + j·stride + (r − r0).
-struct CombItem {
-  int32_t r0, r1, nrange, part, stride, pad0, pad1, pad2;
+  int32_t chunk0, nchunk, wlo, wlen;
 };
 
 struct TilePlan {
   std::vector<Tile> tiles;
-  std::vector<Sub> subs;
-  std::vector<int32_t> trp;   // row starts per workgroup (nrow + 1 each)
-  std::vector<int32_t> tsp;   // first second-part entry per row (split matrices; same indexing)
-  std::vector<int32_t> perm;  // plan order → CSR index (empty: CSR order throughout)
-  std::vector<CombItem> comb;
-  int64_t n_part = 0;    // partial-sum slots per component
-  int32_t max_wlen = 0;  // largest staged window (gathered elements)
+  std::vector<Chunk> chunks;
+  std::vector<int32_t> segslot;  // per segment (64 per chunk, −1 for an empty lane): output slot
+  std::vector<int32_t> rowslot;  // nrows + 1: the slots of row r are [rowslot[r], rowslot[r + 1])
+  std::vector<int32_t> src;      // per SELL value position: CSR index, −1 for padding
+  std::vector<uint16_t> col16;   // column offsets of windowed tiles (SELL order)
+  std::vector<int32_t> col32;    // columns of the other tiles (SELL order)
+  int64_t nslot = 0;
+  int32_t max_wlen = 0;          // largest staged window (columns)
 };
 
 struct TileParams {
-  int32_t wcap;       // window capacity in columns (a power of two)
-  int32_t tile_nnz;   // target entries per workgroup when it stages a window
-  int32_t plain_nnz;  // target entries per workgroup without a window
+  int32_t wcap;       // window capacity in columns (a power of two, ≤ 65536)
+  int32_t tile_nnz;   // target entries per windowed tile
+  int32_t plain_nnz;  // target entries per tile without a window
   int32_t max_rows;   // rows per block at most
 };
 
-// nrows × ncols CSR matrix with sorted column indices in each row; columns below nsplit form the
-// first part of a row (nsplit = ncols: no split).
+// nrows × ncols CSR matrix with sorted column indices in each row.
 TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col, int32_t nrows,
-                    int32_t ncols, int32_t nsplit, const TileParams& tp);
+                    int32_t ncols, const TileParams& tp);
 
 // The problem after validation, format conversion and Ruiz equilibration, all on the host.
 struct HostProblem {

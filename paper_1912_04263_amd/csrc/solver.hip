@@ -16,19 +16,19 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.qb = upload(H.qb);
   V.lb = upload(H.lb);
   V.ub = upload(H.ub);
-  V.x = alloc<double>(n);
+  V.x = alloc<double>((size_t)n + m);
+  V.y = V.x + n;
   V.xt = alloc<double>(n);
   V.r = alloc<double>(n);
-  V.p = alloc<double>(n);
+  V.p = alloc<double>((size_t)n + m);
+  V.w = V.p + n;
   V.kp = alloc<double>(n);
   V.b = alloc<double>(n);
   V.dinv = alloc<double>(n);
   V.z = alloc<double>(m);
-  V.y = alloc<double>(m);
-  V.w = alloc<double>(m);
   V.zt = alloc<double>(m);
   V.ax = alloc<double>(m);
-  V.vw = alloc<double2>(m);
+  V.gp = alloc<double2>((size_t)n + m);
   V.ready = true;
 }
 
@@ -39,18 +39,18 @@ void qpg_solver::alloc_prec32(const HostProblem& H) {
   V.qb = upload_as<float>(H.qb);
   V.lb = upload_as<float>(H.lb);
   V.ub = upload_as<float>(H.ub);
-  V.x = alloc<float>(n);
+  V.x = alloc<float>((size_t)n + m);
+  V.y = V.x + n;
   V.xt = alloc<float>(n);
   V.r = alloc<float>(n);
-  V.p = alloc<float>(n);
+  V.p = alloc<float>((size_t)n + m);
+  V.w = V.p + n;
   V.kp = alloc<float>(n);
   V.b = alloc<float>(n);
   V.dinv = alloc<float>(n);
   V.z = alloc<float>(m);
-  V.y = alloc<float>(m);
-  V.w = alloc<float>(m);
   V.zt = alloc<float>(m);
-  V.vw = alloc<float2>(m);
+  V.gp = alloc<float2>((size_t)n + m);
   V.ready = true;
 }
 
@@ -83,7 +83,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   int k = k_start;
   for (; k <= s.max_iter; ++k) {
     // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
-    OpRhsR0<T> rr{V.x, V.xt, V.qb, V.vw, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
+    OpRhsR0<T> rr{V.x, V.xt, V.qb, V.gp, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
                   s.pcg_rel_test, eps_pcg, st};
     int it;
     if (trial) {
@@ -141,11 +141,11 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     const bool check = (k % s.check_every == 0 || k == s.max_iter);
     T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
     if (check && ax) {
-      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.vw, V.lb, V.ub, escale, (T)alpha,
+      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
                            (T)rho, (T)(1.0 / rho), n, st};
       finalize(up, spmv_A<T>(up));
     } else {
-      spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.vw, V.lb, V.ub, escale,
+      spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
                                    (T)alpha, (T)rho, (T)(1.0 / rho), n, st});
     }
     // (a9) residuals and termination every check_every iterations
@@ -453,40 +453,31 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
 }  // namespace
 
 void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr,
-                            const std::vector<int32_t>& col, int32_t nrows, int32_t ncols, int32_t nsplit) {
+                            const std::vector<int32_t>& col, int32_t nrows, int32_t ncols) {
   TileParams tp{win_cols, s.spmv_tile_nnz > 0 ? s.spmv_tile_nnz : kTileNnz,
                 s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows};
-  TilePlan t = make_tiles(rowptr, col, nrows, ncols, nsplit, tp);
-  if (t.tiles.empty()) {
-    t.tiles.push_back(Tile{0, 0, 0, 0, 0, 0, 0, -1});
-    t.trp.push_back(0);
-  }
+  TilePlan t = make_tiles(rowptr, col, nrows, ncols, tp);
+  if (t.tiles.empty()) t.tiles.push_back(Tile{0, 0, 0, 0});
   pl.ntiles = (int32_t)t.tiles.size();
   pl.tiles = upload(t.tiles);
-  pl.subs = upload(t.subs);
-  pl.trp = upload(t.trp);
-  pl.tsp = t.tsp.empty() ? nullptr : upload(t.tsp);
-  pl.ncomb = (int32_t)t.comb.size();
-  pl.comb = upload(t.comb);
-  pl.npart = t.n_part;
-  pl.part = alloc<double>(3 * (size_t)std::max<int64_t>(t.n_part, 1));
+  pl.chunks = upload(t.chunks);
+  pl.segslot = upload(t.segslot);
+  pl.rowslot = upload(t.rowslot);
+  pl.col16 = upload(t.col16);
+  pl.col32 = upload(t.col32);
+  pl.nslot = t.nslot;
+  pl.nrows = nrows;
+  pl.slots = alloc<double>(3 * (size_t)std::max<int64_t>(t.nslot, 1));
   pl.max_wlen = t.max_wlen;
-  if (!t.perm.empty()) {
-    std::vector<int32_t> c(t.perm.size());
-    for (size_t k = 0; k < c.size(); ++k) c[k] = col[t.perm[k]];
-    pl.col = upload(c);
-    HIPCHK(hipStreamSynchronize(stream));
-    pl.perm = std::move(t.perm);
-  }
   HIPCHK(hipStreamSynchronize(stream));  // t's host arrays go out of scope
+  pl.src = std::move(t.src);
 }
 
-// Values in the plan's order (a copy only where the plan reorders entries).
+// Values in the plan's SELL order (zero in the padding).
 template <typename T>
 void qpg_solver::place_values(DevPlan& pl, const std::vector<double>& csr_val) {
-  if (pl.perm.empty()) return;
-  std::vector<T> v(pl.perm.size());
-  for (size_t k = 0; k < v.size(); ++k) v[k] = (T)csr_val[pl.perm[k]];
+  std::vector<T> v(pl.src.size());
+  for (size_t k = 0; k < v.size(); ++k) v[k] = pl.src[k] >= 0 ? (T)csr_val[pl.src[k]] : T(0);
   T* d = upload(v);
   HIPCHK(hipStreamSynchronize(stream));
   if (std::is_same<T, double>::value)
@@ -589,18 +580,18 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     for (int i = 0; i < H.m; ++i) einv[i] = 1.0 / H.E[i];
     h->dscale = h->upload(dinv);
     h->escale = h->upload(einv);
-    // SpMV work lists: the window is sized so that a window of FP64 pairs, the product buffer
-    // and the reduction scratch fit in one workgroup's LDS
+    // SpMV work lists: the window is sized so that a window of FP64 pairs fits in one
+    // workgroup's LDS
     int lds_max = 0;
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->win_cols = kWinCols;
     while (h->win_cols > 1024 &&
-           (size_t)h->win_cols * 16 + 2 * kSubCap * sizeof(double) + 2048 > (size_t)lds_max)
+           (size_t)h->win_cols * sizeof(double2) + 1024 > (size_t)lds_max)
       h->win_cols >>= 1;
-    h->build_plan(h->plan_a, H.a_ptr, H.a_col, H.m, H.n, H.n);
-    h->build_plan(h->plan_b, H.b_ptr, H.b_col, H.n, H.n + H.m, H.n);
+    h->build_plan(h->plan_a, H.a_ptr, H.a_col, H.m, H.n);
+    h->build_plan(h->plan_b, H.b_ptr, H.b_col, H.n, H.n + H.m);
     int maxgrid = std::max(1024, std::max(h->na_items, h->nb_items));
-    for (const DevPlan* pl : {&h->plan_a, &h->plan_b}) maxgrid = std::max(maxgrid, pl->ntiles + pl->ncomb);
+    maxgrid = std::max(maxgrid, (std::max(H.n, H.m) + kBlock - 1) / kBlock);
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
     h->st = h->alloc<DevState>(1);
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream));
@@ -613,7 +604,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
       const std::vector<double>& v = pl == &h->plan_a ? H.a_val : H.b_val;
       h->place_values<double>(*pl, v);
       if (settings->precision == QPG_MIXED) h->place_values<float>(*pl, v);
-      pl->perm = std::vector<int32_t>();
+      pl->src = std::vector<int32_t>();
     }
     for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);
     for (double* v : {h->p64.z, h->p64.y, h->p64.w, h->p64.zt, h->p64.ax}) h->fill(v, h->m, 0.0);

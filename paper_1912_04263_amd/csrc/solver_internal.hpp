@@ -41,32 +41,35 @@ struct Prec {
   T* a_val = nullptr;  // Ā values (CSR)
   T* b_val = nullptr;  // [P̄ | Āᵀ] values (CSR)
   T *qb = nullptr, *lb = nullptr, *ub = nullptr;
-  T *x = nullptr, *z = nullptr, *y = nullptr, *xt = nullptr;  // ADMM iterates, PCG solution
-  T *r = nullptr, *p = nullptr, *kp = nullptr, *b = nullptr, *dinv = nullptr;  // PCG (n)
-  T* w = nullptr;   // ρ̄Āp (m)
+  // Vectors gathered by the B pass come in pairs of parts in one allocation (n then m entries),
+  // so that column c of B = [P̄ | Āᵀ] reads element c of a single array.
+  T *x = nullptr, *y = nullptr;  // ADMM iterates: x = xy, y = xy + n
+  T *z = nullptr, *xt = nullptr;  // z (m), PCG solution x̃ (n)
+  T *r = nullptr, *p = nullptr, *kp = nullptr, *b = nullptr, *dinv = nullptr;  // PCG (n); p = pw
+  T* w = nullptr;   // ρ̄Āp (m) = pw + n
   T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
   T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
-  pair_t<T>* vw = nullptr;  // (ρ̄(z̃ − z) + y, ρ̄z − y) for the next right-hand side (m)
+  pair_t<T>* gp = nullptr;  // (x̃, 0) (n), then (ρ̄(z̃ − z) + y, ρ̄z − y) (m), for the right-hand side
   bool ready = false;
 };
 
-// Device copy of a SpMV work list (TilePlan). When the plan keeps CSR order, col and the value
-// arrays are null and the matrix's own CSR arrays are streamed.
+// Device copy of a SpMV work list (TilePlan): the work list, the matrix in SELL order (values
+// in both precisions), and the slots (up to 3 planes).
 struct DevPlan {
   Tile* tiles = nullptr;
   int32_t ntiles = 0;
-  Sub* subs = nullptr;
-  int32_t* trp = nullptr;
-  int32_t* tsp = nullptr;
-  CombItem* comb = nullptr;
-  int32_t ncomb = 0;
-  int32_t* col = nullptr;
+  Chunk* chunks = nullptr;
+  int32_t* segslot = nullptr;
+  int32_t* rowslot = nullptr;
+  uint16_t* col16 = nullptr;
+  int32_t* col32 = nullptr;
   double* val64 = nullptr;
   float* val32 = nullptr;
-  void* part = nullptr;  // partial sums: up to 3 planes of npart values (double-sized)
-  int64_t npart = 0;
+  void* slots = nullptr;  // double-sized: 3 planes of nslot values
+  int64_t nslot = 0;
+  int32_t nrows = 0;
   int32_t max_wlen = 0;  // largest staged window, in columns
-  std::vector<int32_t> perm;  // host copy of the plan order (until the values are placed)
+  std::vector<int32_t> src;  // host copy of the SELL order (until the values are placed)
 };
 
 struct LearnedState;  // learned-preconditioner data of a solver (learned.hip)
@@ -149,11 +152,10 @@ struct qpg_solver {
   }
 
   // ----------------------------------------------------------------- launches
-  // SpMV launches (k_spmv, then k_combine for multi-range blocks); the returned count is the
-  // number of workgroup partials a finalize must combine.
+  // SpMV launches (k_spmv, then k_combine); the returned count is the number of workgroup
+  // partials a finalize must combine.
   template <typename T, class Op>
-  int spmv(const DevPlan& pl, const int32_t* csr_col, const T* csr_val, bool split, const Op& op,
-           const int32_t* gate) {
+  int spmv(const DevPlan& pl, int nsplit, int planes, const Op& op, const int32_t* gate) {
     using G = typename Gathered<Op, T>::type;
     const size_t shmem = (size_t)pl.max_wlen * sizeof(G);
     static size_t lds_allowed = 0;  // per instantiation: raise the dynamic LDS limit once
@@ -162,25 +164,22 @@ struct qpg_solver {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
       lds_allowed = shmem;
     }
-    const int32_t* col = pl.col ? pl.col : csr_col;
-    const T* val = csr_val;
-    if (pl.col) val = std::is_same<T, double>::value ? (const T*)pl.val64 : (const T*)pl.val32;
-    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kBlock), shmem, stream, pl.tiles, pl.subs,
-                       pl.trp, split ? pl.tsp : nullptr, col, val, op, static_cast<T*>(pl.part), pl.npart,
-                       rb.partials, gate);
-    if (pl.ncomb > 0)
-      hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb,
-                         (const T*)static_cast<T*>(pl.part), pl.npart, split ? (Op::NV == 2 ? 3 : 2) : 1, op,
-                         rb.partials + (size_t)pl.ntiles * kMaxSlots, gate);
-    return pl.ntiles + pl.ncomb;
+    const T* val = std::is_same<T, double>::value ? (const T*)pl.val64 : (const T*)pl.val32;
+    hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles, pl.chunks,
+                       pl.segslot, pl.col16, pl.col32, val, nsplit, op, static_cast<T*>(pl.slots), pl.nslot,
+                       planes, gate);
+    const int ncomb = std::max(1, (pl.nrows + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_combine<T, Op>), dim3(ncomb), dim3(kBlock), 0, stream, pl.nrows, pl.rowslot,
+                       (const T*)static_cast<T*>(pl.slots), pl.nslot, planes, op, rb.partials, gate);
+    return ncomb;
   }
   template <typename T, class Op>
   int spmv_A(const Op& op, const int32_t* gate = nullptr) {
-    return spmv<T>(plan_a, a_col, P<T>().a_val, false, op, gate);
+    return spmv<T>(plan_a, INT32_MAX, 1, op, gate);
   }
   template <typename T, class Op>
   int spmv_B(const Op& op, const int32_t* gate = nullptr) {
-    return spmv<T>(plan_b, b_col, P<T>().b_val, true, op, gate);
+    return spmv<T>(plan_b, n, Op::NV == 2 ? 3 : 2, op, gate);
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
   template <class Op>
@@ -256,9 +255,8 @@ struct qpg_solver {
   template <typename T>
   void pairs(double rho) {
     Prec<T>& V = P<T>();
-    if (m > 0)
-      hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(m)), dim3(kBlock), 0, stream, m, V.vw,
-                         (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho);
+    hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(n + m)), dim3(kBlock), 0, stream, n, m, V.gp,
+                         (const T*)V.xt, (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho);
   }
 
   template <typename T>
@@ -278,7 +276,7 @@ struct qpg_solver {
 
   int solve();
   void build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
-                  int32_t nrows, int32_t ncols, int32_t nsplit);
+                  int32_t nrows, int32_t ncols);
   template <typename T>
   void place_values(DevPlan& pl, const std::vector<double>& csr_val);
   void alloc_prec64(const HostProblem& H);

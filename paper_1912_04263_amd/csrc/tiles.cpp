@@ -1,22 +1,20 @@
-// SpMV work-list construction (host): row blocks, column ranges, LDS gather windows, and the
-// entry order the SpMV kernel streams.
+// SpMV work-list construction (host): row blocks, column ranges, LDS gather windows, segments,
+// and the SELL order of the entries that the SpMV kernel streams.
 //
 // Rows are grouped into runs of similar length. For each run, a histogram of its column indices
 // over fixed windows of wcap columns decides the layout:
 //   * multi-range, when at least two windows each hold ≥ kMinSeg entries per row on average and
 //     together at least half of the run's entries: the columns are cut at those windows, and each
-//     (row block, range) workgroup stages its window in LDS. The block's entries are reordered
-//     range by range (rows in order inside each range), so that every workgroup streams one
-//     contiguous run of entries. Partial sums per (row, range) cost one value per row and range,
-//     hence the kMinSeg floor;
-//   * single-range otherwise: consecutive rows in CSR order with one optional window, either the
-//     block's whole column span when it fits, or the run's densest wcap-wide window when that
-//     holds at least half of the block's entries.
-// A window is staged only if it holds at least one entry per 16 of its elements, so that staging
-// never reads more than the gathers it replaces. Each workgroup's rows are then packed into
-// sub-runs of at most kSubCap entries (a longer row is a sub-run of its own), the unit that the
-// kernel loads through LDS.
+//     (row block, range) gets a tile that stages its window in LDS. Each range costs every row one
+//     slot at least, hence the kMinSeg floor;
+//   * single-range otherwise: one windowed tile per row block, the window being either the block's
+//     whole column span when it fits, or the run's densest wcap-wide window when that holds at
+//     least half of the block's entries.
+// A window is staged only if it holds at least one entry per 16 of its columns, so that staging
+// never reads more than the gathers it replaces. Entries outside every staged window go to tiles
+// without a window, of about plain_nnz entries each.
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <vector>
 
@@ -29,6 +27,7 @@ namespace {
 constexpr int kMinSeg = 16;         // entries per row and range for a multi-range layout
 constexpr int64_t kMinTiles = 512;  // workgroups a launch should have (two per compute unit)
 constexpr int64_t kMinTileNnz = 1024;
+constexpr int kLanes = 64;
 
 int32_t log2_exact(int32_t v) {
   int32_t l = 0;
@@ -36,65 +35,35 @@ int32_t log2_exact(int32_t v) {
   return l;
 }
 
-// Append the row structure of one workgroup: rows r0.. with the given (start, end, split)
-// entry positions in the plan's order, and its sub-runs.
-void add_tile(TilePlan& plan, int32_t r0, const std::vector<int32_t>& st, const std::vector<int32_t>& en,
-              const std::vector<int32_t>& sp, bool has_split, int32_t wlo, int32_t wlen, int32_t part) {
-  const int32_t R = (int32_t)st.size();
-  Tile t{};
-  t.r0 = r0;
-  t.nrow = R;
-  t.tr = (int32_t)plan.trp.size();
-  t.wlo = wlo;
-  t.wlen = wlen;
-  t.part = part;
-  t.sub0 = (int32_t)plan.subs.size();
-  for (int32_t i = 0; i < R; ++i) plan.trp.push_back(st[i]);
-  plan.trp.push_back(R > 0 ? en[R - 1] : 0);
-  if (has_split) {
-    for (int32_t i = 0; i < R; ++i) plan.tsp.push_back(sp[i]);
-    plan.tsp.push_back(0);
-  }
-  int32_t i = 0;
-  while (i < R) {
-    const int32_t len = en[i] - st[i];
-    if (len > kSubCap) {
-      plan.subs.push_back({i, i + 1, st[i], en[i]});
-      ++i;
-      continue;
-    }
-    int32_t i1 = i, acc = 0;
-    while (i1 < R && en[i1] - st[i1] <= kSubCap && acc + (en[i1] - st[i1]) <= kSubCap && i1 - i < kSubCap) {
-      acc += en[i1] - st[i1];
-      ++i1;
-    }
-    plan.subs.push_back({i, i1, st[i], en[i1 - 1]});
-    i = i1;
-  }
-  t.nsub = (int32_t)plan.subs.size() - t.sub0;
-  plan.tiles.push_back(t);
-  if (wlen > 0) plan.max_wlen = std::max(plan.max_wlen, wlen);
-}
+struct Seg {
+  int32_t start, len, slot;
+};
 
 }  // namespace
 
 TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col, int32_t nrows,
-                    int32_t ncols, int32_t nsplit, const TileParams& tp) {
+                    int32_t ncols, const TileParams& tp) {
   TilePlan plan;
+  plan.rowslot.assign((size_t)std::max(nrows, 0) + 1, 0);
   if (nrows <= 0) return plan;
-  const bool has_split = nsplit < ncols;
   const int32_t wcap = tp.wcap;
-  // smaller workgroups on small matrices, so that the launch still has ~kMinTiles of them
+  // smaller tiles on small matrices, so that the launch still has ~kMinTiles of them
   const int64_t nnz_all = (int64_t)rowptr[nrows] - rowptr[0];
   const int32_t tile_nnz = (int32_t)std::max<int64_t>(kMinTileNnz, std::min<int64_t>(tp.tile_nnz, nnz_all / kMinTiles));
   const int32_t plain_nnz = (int32_t)std::max<int64_t>(kMinTileNnz, std::min<int64_t>(tp.plain_nnz, nnz_all / kMinTiles));
+  // segment length: short segments on small matrices, so that a lane's serial chain stays short
+  int32_t seg_max = kSegMax;
+  while (seg_max > 16 && (int64_t)seg_max * kLanes * kMinTiles > nnz_all) seg_max >>= 1;
+  // chunks per tile: one per wavefront of the workgroup, unless the matrix is too small for that
+  const int32_t tile_chunks =
+      nnz_all >= kMinTiles * (kSpmvBlock / kLanes) * kLanes * seg_max / 2 ? kSpmvBlock / kLanes : 1;
   const int32_t sh = log2_exact(wcap);
   const int32_t fsh = std::max(0, sh - 3);  // eight fine bins per window
   const int64_t nwin = ((int64_t)ncols + wcap - 1) >> sh;
   const int64_t nfine = ((int64_t)ncols + (1 << fsh) - 1) >> fsh;
   std::vector<int64_t> cnt(std::max<int64_t>(nwin, 1), 0), fine(std::max<int64_t>(nfine, 1), 0);
   std::vector<int64_t> touched_w, touched_f;
-  std::vector<int32_t> st, en, sp;
+
   // first entry of row r at or after column c
   auto seek = [&](int32_t r, int64_t c) {
     const int32_t* first = col.data() + rowptr[r];
@@ -102,6 +71,112 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
     return (int32_t)(std::lower_bound(first, last, (int32_t)std::min<int64_t>(c, INT32_MAX)) - col.data());
   };
 
+  // One tile: segments sorted by length (longest first; ties in slot order), packed into chunks
+  // of 64 lanes in SELL order. Padding repeats the lane's last column with a zero value.
+  auto add_tile = [&](std::vector<Seg>& segs, int32_t wlo, int32_t wlen) {
+    if (segs.empty()) return;
+    std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
+    const bool win = wlen > 0;
+    Tile t{};
+    t.chunk0 = (int32_t)plan.chunks.size();
+    t.wlo = wlo;
+    t.wlen = wlen;
+    for (size_t c0 = 0; c0 < segs.size(); c0 += kLanes) {
+      const int32_t nseg = (int32_t)std::min<size_t>(kLanes, segs.size() - c0);
+      Chunk ch{};
+      ch.base = (int32_t)plan.src.size();
+      ch.cbase = (int32_t)(win ? plan.col16.size() : plan.col32.size());
+      ch.steps = segs[c0].len;
+      ch.seg0 = (int32_t)plan.segslot.size();
+      for (int32_t j = 0; j < kLanes; ++j) plan.segslot.push_back(j < nseg ? segs[c0 + j].slot : -1);
+      for (int32_t s = 0; s < ch.steps; ++s)
+        for (int32_t j = 0; j < kLanes; ++j) {
+          int32_t k = -1, c = win ? wlo : 0;
+          if (j < nseg) {
+            const Seg& g = segs[c0 + j];
+            if (s < g.len) k = g.start + s;
+            if (g.len > 0) c = col[s < g.len ? g.start + s : g.start + g.len - 1];
+          }
+          plan.src.push_back(k);
+          if (win)
+            plan.col16.push_back((uint16_t)(c - wlo));
+          else
+            plan.col32.push_back(c);
+        }
+      plan.chunks.push_back(ch);
+    }
+    t.nchunk = (int32_t)plan.chunks.size() - t.chunk0;
+    plan.tiles.push_back(t);
+    if (win) plan.max_wlen = std::max(plan.max_wlen, wlen);
+  };
+
+  std::vector<Seg> plain;  // segments waiting for a tile without a window
+  int64_t plain_entries = 0;
+  // all of them (at the end), or whole chunks' worth once there are enough entries
+  auto flush_plain = [&](bool all) {
+    if (!all && (plain_entries < plain_nnz || plain.size() < (size_t)(tile_chunks * kLanes))) return;
+    const size_t take = all ? plain.size() : plain.size() / kLanes * kLanes;
+    std::vector<Seg> t(plain.begin(), plain.begin() + take);
+    plain.erase(plain.begin(), plain.begin() + take);
+    add_tile(t, 0, 0);
+    plain_entries = 0;
+    for (const Seg& g : plain) plain_entries += g.len;
+  };
+  // segments of [a, e) with consecutive slots from *next
+  auto cut_segs = [&](std::vector<Seg>& out, int32_t a, int32_t e, int32_t* next) {
+    for (int32_t s = a; s < e; s += seg_max) out.push_back({s, std::min(seg_max, e - s), (*next)++});
+  };
+  auto pieces = [&](int32_t a, int32_t e) { return (e - a + seg_max - 1) / seg_max; };
+
+  // Row block [b0, b1) with ranges cut at cut[0..K] and windows (wlen 0: none): for each row and
+  // range, the entries left of the window, inside it, and right of it, in column order.
+  std::vector<int32_t> bnd;
+  std::vector<std::vector<Seg>> wsegs;
+  auto add_block = [&](int32_t b0, int32_t b1, const std::vector<int64_t>& cut, const std::vector<int32_t>& wlo,
+                       const std::vector<int32_t>& wlen) {
+    const int32_t K = (int32_t)cut.size() - 1, Rb = b1 - b0;
+    const int32_t stride = 3 * K + 1;
+    bnd.assign((size_t)Rb * stride, 0);
+    for (int32_t i = 0; i < Rb; ++i) {
+      const int32_t r = b0 + i;
+      int32_t* B = &bnd[(size_t)i * stride];
+      int32_t np = 0;
+      for (int32_t j = 0; j < K; ++j) {
+        const int32_t a = j == 0 ? rowptr[r] : seek(r, cut[j]);
+        const int32_t e = j == K - 1 ? rowptr[r + 1] : seek(r, cut[j + 1]);
+        const int32_t ia = wlen[j] > 0 ? std::max(a, seek(r, wlo[j])) : e;
+        const int32_t ie = wlen[j] > 0 ? std::min(e, seek(r, (int64_t)wlo[j] + wlen[j])) : e;
+        B[3 * j] = a;
+        B[3 * j + 1] = ia;
+        B[3 * j + 2] = ie;
+        B[3 * j + 3] = e;
+        np += pieces(a, ia) + pieces(ia, ie) + pieces(ie, e);
+      }
+      plan.rowslot[r + 1] = plan.rowslot[r] + np;
+    }
+    wsegs.assign(K, {});
+    for (int32_t i = 0; i < Rb; ++i) {
+      const int32_t* B = &bnd[(size_t)i * stride];
+      int32_t next = plan.rowslot[b0 + i];
+      for (int32_t j = 0; j < K; ++j) {
+        const size_t before = plain.size();
+        cut_segs(plain, B[3 * j], B[3 * j + 1], &next);
+        cut_segs(wsegs[j], B[3 * j + 1], B[3 * j + 2], &next);
+        cut_segs(plain, B[3 * j + 2], B[3 * j + 3], &next);
+        for (size_t q = before; q < plain.size(); ++q) plain_entries += plain[q].len;
+      }
+    }
+    for (int32_t j = 0; j < K; ++j) add_tile(wsegs[j], wlo[j], wlen[j]);
+    flush_plain(false);
+  };
+
+  // rows per block: about `target` entries, and at least one full chunk of segments
+  auto block_rows = [&](int64_t target, double seg_entries) {
+    const int64_t spr = std::max<int64_t>(1, (int64_t)std::ceil(seg_entries / seg_max));  // segments per row
+    int64_t R = std::max<int64_t>((int64_t)(target / std::max(seg_entries, 1.0)), tile_chunks * kLanes / spr);
+    R = (R * spr + kLanes - 1) / kLanes * kLanes / spr;  // whole chunks
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(tp.max_rows, R));
+  };
   auto len = [&](int32_t r) { return rowptr[r + 1] - rowptr[r]; };
   int32_t g0 = 0;
   while (g0 < nrows) {
@@ -150,93 +225,69 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
     touched_w.clear();
     touched_f.clear();
 
-    const bool fits32 = plan.n_part + (int64_t)S.size() * rows_g < INT32_MAX;
-    if (S.size() >= 2 && 2 * covS >= nnz_g && fits32) {
-      // ---- multi-range blocks, entries reordered range by range
-      if (plan.perm.empty()) {
-        plan.perm.resize(nnz_all);
-        for (int64_t k = 0; k < nnz_all; ++k) plan.perm[k] = (int32_t)(rowptr[0] + k);
-      }
+    if (S.size() >= 2 && 2 * covS >= nnz_g) {
+      // ---- multi-range blocks
       const int32_t K = (int32_t)S.size();
       std::vector<int64_t> cut(K + 1);
       cut[0] = 0;
       for (int32_t j = 1; j < K; ++j) cut[j] = S[j] << sh;
       cut[K] = ncols;
       const double aseg = (double)covS / (double)(rows_g * K);
-      const int32_t R = (int32_t)std::max<int64_t>(
-          1, std::min<int64_t>(tp.max_rows, (int64_t)(tile_nnz / std::max(aseg, 1.0))));
+      const int32_t R = block_rows(tile_nnz, aseg);
       for (int32_t b0 = g0; b0 < g1; b0 += R) {
         const int32_t b1 = std::min(g1, b0 + R), Rb = b1 - b0;
-        const int64_t part_base = plan.n_part;
-        int32_t pos = rowptr[b0];  // next position in the plan's order
+        std::vector<int32_t> wlo(K, 0), wlen(K, 0);
         for (int32_t j = 0; j < K; ++j) {
-          st.clear();
-          en.clear();
-          sp.clear();
-          for (int32_t r = b0; r < b1; ++r) {
-            const int32_t a = j == 0 ? rowptr[r] : seek(r, cut[j]);
-            const int32_t e = j == K - 1 ? rowptr[r + 1] : seek(r, cut[j + 1]);
-            const int32_t s = has_split ? std::min(std::max(seek(r, nsplit), a), e) : e;
-            st.push_back(pos);
-            sp.push_back(pos + (s - a));
-            for (int32_t k = a; k < e; ++k) plan.perm[pos++ - rowptr[0]] = k;
-            en.push_back(pos);
-          }
-          const int32_t wlo = (int32_t)(S[j] << sh);
-          const int32_t wlen = (int32_t)std::min<int64_t>(wcap, (int64_t)ncols - wlo);
+          const int32_t w0 = (int32_t)(S[j] << sh);
+          const int32_t wl = (int32_t)std::min<int64_t>(wcap, (int64_t)ncols - w0);
           // entries of this block in the window ≈ its share of the run's count
-          const bool stage = cntS[j] * Rb / rows_g * 16 >= wlen;
-          add_tile(plan, b0, st, en, sp, has_split, stage ? wlo : 0, stage ? wlen : 0,
-                   (int32_t)(part_base + (int64_t)j * Rb));
+          if (cntS[j] * Rb / rows_g * 16 >= wl) {
+            wlo[j] = w0;
+            wlen[j] = wl;
+          }
         }
-        for (int32_t r = b0; r < b1; r += kBlock)
-          plan.comb.push_back({r, std::min(b1, r + kBlock), K, (int32_t)(part_base + (r - b0)), Rb, 0, 0, 0});
-        plan.n_part += (int64_t)K * Rb;
+        add_block(b0, b1, cut, wlo, wlen);
       }
     } else {
-      // ---- single-range blocks (CSR order)
+      // ---- single-range blocks
       const bool window_run = 2 * best >= nnz_g;
       const int32_t target = window_run ? tile_nnz : plain_nnz;
-      const int32_t R = (int32_t)std::max<int64_t>(
-          1, std::min<int64_t>(tp.max_rows, (int64_t)(target / std::max(avg, 1.0))));
+      const int32_t R = block_rows(target, avg);
       const int64_t run_lo = best_lo, run_hi = std::min<int64_t>(best_lo + wcap, ncols);
+      const std::vector<int64_t> cut = {0, (int64_t)ncols};
       for (int32_t b0 = g0; b0 < g1; b0 += R) {
         const int32_t b1 = std::min(g1, b0 + R);
         const int64_t nb = (int64_t)rowptr[b1] - rowptr[b0];
         int32_t cmin = ncols, cmax = -1;
         int64_t in_run = 0;
-        st.clear();
-        en.clear();
-        sp.clear();
         for (int32_t r = b0; r < b1; ++r) {
           const int32_t a = rowptr[r], e = rowptr[r + 1];
-          st.push_back(a);
-          en.push_back(e);
-          if (has_split) sp.push_back(seek(r, nsplit));
           if (a == e) continue;
           cmin = std::min(cmin, col[a]);
           cmax = std::max(cmax, col[e - 1]);
           if (window_run) in_run += seek(r, run_hi) - seek(r, run_lo);
         }
-        int32_t wlo = 0, wlen = 0;
+        std::vector<int32_t> wlo(1, 0), wlen(1, 0);
         if (cmax >= 0 && (int64_t)cmax - cmin + 1 <= wcap) {
           if (nb * 16 >= (int64_t)cmax - cmin + 1) {
-            wlo = cmin;
-            wlen = cmax - cmin + 1;
+            wlo[0] = cmin;
+            wlen[0] = cmax - cmin + 1;
           }
         } else if (window_run && 2 * in_run >= nb) {
           const int32_t a = (int32_t)std::max<int64_t>(run_lo, cmin);
           const int32_t e = (int32_t)std::min<int64_t>(run_hi, (int64_t)cmax + 1);
           if (e > a && in_run * 16 >= e - a) {
-            wlo = a;
-            wlen = e - a;
+            wlo[0] = a;
+            wlen[0] = e - a;
           }
         }
-        add_tile(plan, b0, st, en, sp, has_split, wlo, wlen, -1);
+        add_block(b0, b1, cut, wlo, wlen);
       }
     }
     g0 = g1;
   }
+  flush_plain(true);
+  plan.nslot = plan.rowslot[nrows];
   return plan;
 }
 
