@@ -245,10 +245,12 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(const Tile* __restrict__ ti
   op.side();
 }
 
-// Row sums from the slots (fixed order: the row's segments in column order), then the epilogue.
-// One thread per row; reduction partials per workgroup for k_finalize.
+// Row sums from the slots, then the epilogue. 2^lg lanes per row: lane l adds slots l, l + L, …
+// of the row in order, then a fixed shuffle tree combines the lanes (deterministic). Reduction
+// partials per workgroup for k_finalize.
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_combine(int nrows, const int32_t* __restrict__ rowslot,
+__global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__ items,
+                                                    const int32_t* __restrict__ rowslot,
                                                     const T* __restrict__ slots, int64_t pstride,
                                                     int planes, Op op, double* __restrict__ partials,
                                                     const int32_t* __restrict__ gate) {
@@ -257,19 +259,28 @@ __global__ __launch_bounds__(kBlock) void k_combine(int nrows, const int32_t* __
   double red[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  if (r < nrows) {
+  const CombItem c = items[blockIdx.x];
+  const int lg = c.lg, L = 1 << lg, groups = kBlock >> lg;
+  const int g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
+  for (int r = c.r0 + g; r < c.r1; r += groups) {
     T s1 = T(0), s2 = T(0), s3 = T(0);
     const int q1 = rowslot[r + 1];
-    for (int q = rowslot[r]; q < q1; ++q) {
+#pragma unroll 4
+    for (int q = rowslot[r] + lane; q < q1; q += L) {
       s1 += slots[q];
       if (planes > 1) s2 += slots[pstride + q];
       if (planes > 2) s3 += slots[2 * pstride + q];
     }
-    op.epilogue(r, s1, s2, s3, red);
+    if (L > 1) {
+      s1 = wave_sum(s1, L);
+      if (planes > 1) s2 = wave_sum(s2, L);
+      if (planes > 2) s3 = wave_sum(s3, L);
+    }
+    if (lane == 0) op.epilogue(r, s1, s2, s3, red);
   }
   if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }
+
 // ------------------------------------------------------------------------------- SpMV epilogues
 
 #define QPG_NO_SIDE \
@@ -487,8 +498,8 @@ struct OpUpdate {
       }
     }
   }
-  __device__ void side() const {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+  __device__ void side() const {  // any workgroup size
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
       const T xti = xt[i];
       x[i] = alpha * xti + (T(1) - alpha) * x[i];
       gp[i] = pair_t<T>{xti, T(0)};

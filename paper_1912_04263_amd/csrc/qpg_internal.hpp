@@ -58,7 +58,7 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = 
 // epilogue.
 
 constexpr int kSegMax = 256;   // entries of one segment at most
-constexpr int kSpmvBlock = 256; // threads per SpMV workgroup (one chunk at a time per wavefront)
+constexpr int kSpmvBlock = 512; // threads per SpMV workgroup (one chunk at a time per wavefront)
 constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most; ≤ 65536)
 
 struct Chunk {
@@ -73,8 +73,14 @@ struct Tile {
   int32_t chunk0, nchunk, wlo, wlen;
 };
 
+// k_combine work: rows [r0, r1), 2^lg lanes per row (rows with many slots share them out).
+struct CombItem {
+  int32_t r0, r1, lg, pad;
+};
+
 struct TilePlan {
   std::vector<Tile> tiles;
+  std::vector<CombItem> comb;
   std::vector<Chunk> chunks;
   std::vector<int32_t> segslot;  // per segment (64 per chunk, −1 for an empty lane): output slot
   std::vector<int32_t> rowslot;  // nrows + 1: the slots of row r are [rowslot[r], rowslot[r + 1])

@@ -458,6 +458,9 @@ void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr,
                 s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows};
   TilePlan t = make_tiles(rowptr, col, nrows, ncols, tp);
   if (t.tiles.empty()) t.tiles.push_back(Tile{0, 0, 0, 0});
+  if (t.comb.empty()) t.comb.push_back(CombItem{0, 0, 0, 0});
+  pl.ncomb = (int32_t)t.comb.size();
+  pl.comb = upload(t.comb);
   pl.ntiles = (int32_t)t.tiles.size();
   pl.tiles = upload(t.tiles);
   pl.chunks = upload(t.chunks);
@@ -591,7 +594,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->build_plan(h->plan_a, H.a_ptr, H.a_col, H.m, H.n);
     h->build_plan(h->plan_b, H.b_ptr, H.b_col, H.n, H.n + H.m);
     int maxgrid = std::max(1024, std::max(h->na_items, h->nb_items));
-    maxgrid = std::max(maxgrid, (std::max(H.n, H.m) + kBlock - 1) / kBlock);
+    maxgrid = std::max(maxgrid, std::max(h->plan_a.ncomb, h->plan_b.ncomb));
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
     h->st = h->alloc<DevState>(1);
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream));

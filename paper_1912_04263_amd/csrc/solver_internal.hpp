@@ -61,6 +61,8 @@ struct DevPlan {
   Chunk* chunks = nullptr;
   int32_t* segslot = nullptr;
   int32_t* rowslot = nullptr;
+  CombItem* comb = nullptr;
+  int32_t ncomb = 0;
   uint16_t* col16 = nullptr;
   int32_t* col32 = nullptr;
   double* val64 = nullptr;
@@ -168,10 +170,9 @@ struct qpg_solver {
     hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles, pl.chunks,
                        pl.segslot, pl.col16, pl.col32, val, nsplit, op, static_cast<T*>(pl.slots), pl.nslot,
                        planes, gate);
-    const int ncomb = std::max(1, (pl.nrows + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_combine<T, Op>), dim3(ncomb), dim3(kBlock), 0, stream, pl.nrows, pl.rowslot,
+    hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
                        (const T*)static_cast<T*>(pl.slots), pl.nslot, planes, op, rb.partials, gate);
-    return ncomb;
+    return pl.ncomb;
   }
   template <typename T, class Op>
   int spmv_A(const Op& op, const int32_t* gate = nullptr) {

@@ -54,9 +54,11 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   // segment length: short segments on small matrices, so that a lane's serial chain stays short
   int32_t seg_max = kSegMax;
   while (seg_max > 16 && (int64_t)seg_max * kLanes * kMinTiles > nnz_all) seg_max >>= 1;
-  // chunks per tile: one per wavefront of the workgroup, unless the matrix is too small for that
-  const int32_t tile_chunks =
-      nnz_all >= kMinTiles * (kSpmvBlock / kLanes) * kLanes * seg_max / 2 ? kSpmvBlock / kLanes : 1;
+  // chunks per tile: up to one per wavefront of the workgroup, fewer when the matrix has too few
+  // chunks for kMinTiles tiles of that size
+  const double seg_est = std::min<double>(seg_max, std::max(1.0, (double)nnz_all / nrows));
+  const int32_t tile_chunks = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>(kSpmvBlock / kLanes, (int64_t)(nnz_all / (kLanes * seg_est)) / kMinTiles));
   const int32_t sh = log2_exact(wcap);
   const int32_t fsh = std::max(0, sh - 3);  // eight fine bins per window
   const int64_t nwin = ((int64_t)ncols + wcap - 1) >> sh;
@@ -205,17 +207,26 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
     std::sort(S.begin(), S.end());
     // densest wcap-wide window on the fine grid
     std::sort(touched_f.begin(), touched_f.end());
-    int64_t best = 0, best_lo = 0;
+    int64_t best = 0, best_lo = 0, best_hi = 0;
     {
       int64_t run = 0;
-      size_t tail = 0;
+      size_t tail = 0, bt = 0, bh = 0;
       for (size_t h = 0; h < touched_f.size(); ++h) {
         run += fine[touched_f[h]];
         while (touched_f[h] - touched_f[tail] >= 8) run -= fine[touched_f[tail++]];
         if (run > best) {
           best = run;
-          best_lo = touched_f[tail] << fsh;
+          bt = tail;
+          bh = h;
         }
+      }
+      // trim sparse fine bins off both ends (they keep at most 1% of the window's entries)
+      int64_t drop = 0;
+      while (bt < bh && drop + fine[touched_f[bt]] <= best / 100) drop += fine[touched_f[bt++]];
+      while (bh > bt && drop + fine[touched_f[bh]] <= best / 100) drop += fine[touched_f[bh--]];
+      if (!touched_f.empty()) {
+        best_lo = touched_f[bt] << fsh;
+        best_hi = std::min<int64_t>((touched_f[bh] + 1) << fsh, ncols);
       }
     }
     std::vector<int64_t> cntS(S.size());
@@ -253,7 +264,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
       const bool window_run = 2 * best >= nnz_g;
       const int32_t target = window_run ? tile_nnz : plain_nnz;
       const int32_t R = block_rows(target, avg);
-      const int64_t run_lo = best_lo, run_hi = std::min<int64_t>(best_lo + wcap, ncols);
+      const int64_t run_lo = best_lo, run_hi = best_hi;
       const std::vector<int64_t> cut = {0, (int64_t)ncols};
       for (int32_t b0 = g0; b0 < g1; b0 += R) {
         const int32_t b1 = std::min(g1, b0 + R);
@@ -288,6 +299,23 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   }
   flush_plain(true);
   plan.nslot = plan.rowslot[nrows];
+  // combine work: lanes per row ≈ a quarter of its slots (1..64); a workgroup of kBlock threads
+  // takes up to four passes of rows with the same lane count
+  int32_t r = 0;
+  while (r < nrows) {
+    auto lg_of = [&](int32_t q) {
+      const int32_t ns = plan.rowslot[q + 1] - plan.rowslot[q];
+      int32_t lg = 0;
+      while (lg < 6 && (4 << lg) < ns) ++lg;
+      return lg;
+    };
+    const int32_t lg = lg_of(r);
+    const int32_t cap = 4 * (kBlock >> lg);
+    int32_t r1 = r + 1;
+    while (r1 < nrows && r1 - r < cap && lg_of(r1) == lg) ++r1;
+    plan.comb.push_back({r, r1, lg, 0});
+    r = r1;
+  }
   return plan;
 }
 

@@ -102,6 +102,13 @@ int main(int argc, char** argv) {
       if (covered[k] != 1) FAIL("entry %ld covered %d times", k, covered[k]);
     for (long q = 0; q < p.nslot; ++q)
       if (!slotset[q]) FAIL("slot %ld never written", q);
+    std::vector<int> combined(nrows, 0);
+    for (const CombItem& c : p.comb) {
+      if (c.lg < 0 || c.lg > 6 || c.r0 < 0 || c.r1 > nrows || c.r0 >= c.r1) FAIL("combine item");
+      for (int r = c.r0; r < c.r1; ++r) combined[r]++;
+    }
+    for (int r = 0; r < nrows; ++r)
+      if (combined[r] != 1) FAIL("row %d combined %d times", r, combined[r]);
     double err = 0, scale = 0;
     for (int r = 0; r < nrows; ++r) {
       double s1 = 0, s2 = 0;
@@ -113,9 +120,9 @@ int main(int argc, char** argv) {
       scale = std::max(scale, std::fabs(ref1[r]) + std::fabs(ref2[r]));
     }
     if (err > 1e-12 * std::max(scale, 1.0)) FAIL("row sums off by %g", err);
-    std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld\n", wcap,
+    std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d\n", wcap,
                 p.tiles.size(), windowed, p.chunks.size(), 100.0 * padding / std::max<size_t>(p.src.size(), 1),
-                100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot);
+                100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen);
   }
   return 0;
 }

@@ -96,7 +96,18 @@ def test_initial_network_reproduces_jacobi_on_device():
                              precond_trial=0)
     il = lrn.solve()
     assert il.precond_used == "learned"
-    assert abs(il.iter - ib.iter) <= 10 and abs(il.pcg_iter_total - ib.pcg_iter_total) <= 0.05 * ib.pcg_iter_total
+    # the same preconditioner up to float32 rounding of softplus(g)/K_ii: the iterates drift apart
+    # only through rounding, so the counts agree to a few percent
+    assert abs(il.iter - ib.iter) <= 0.05 * ib.iter
+    assert abs(il.pcg_iter_total - ib.pcg_iter_total) <= 0.05 * ib.pcg_iter_total
+    base.close()
+    lrn.close()
+    # the answers agree once both runs stop where the method has converged (at 1e-5 the stopping
+    # point itself is ≈1e-2 off in x on portfolio instances)
+    base = qpg.Solver.from_qp(p, eps_abs=1e-7, eps_rel=1e-7, max_iter=20000)
+    lrn = qpg.Solver.from_qp(p, eps_abs=1e-7, eps_rel=1e-7, max_iter=20000, precond="learned",
+                             precond_weights=w, precond_trial=0)
+    assert base.solve().status == "solved" and lrn.solve().status == "solved"
     assert np.max(np.abs(lrn.x() - base.x())) <= 1e-4 * np.max(np.abs(base.x()))
     base.close()
     lrn.close()
