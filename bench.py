@@ -35,6 +35,20 @@ def spmv_b_bytes(n, m, nnz_b, s):
     return nnz_b * (s + 4) + 4 * (n + 1) + 4 * n + (n + m) * s + n * s
 
 
+def spmv_b_stream_bytes(n, m, nnz_b, s):
+    """Algorithmic bytes of the stream kernel of that pass alone (segment sums of [P̄ | Āᵀ][p; w]):
+    matrix values and 32-bit column indices once, the gathered vectors p (n) and w (m) once."""
+    return nnz_b * (s + 4) + (n + m) * s
+
+
+def stream_bytes_moved(layout, s):
+    """Bytes the stream kernel actually reads and writes in its layout: values and 16-bit column
+    offsets in windowed tiles, values and 32-bit columns elsewhere (padding included), chunk
+    descriptors and slot numbers, the two planes of segment sums written."""
+    return (layout["windowed_positions"] * (s + 2) + layout["plain_positions"] * (s + 4)
+            + layout["chunks"] * (16 + 64 * 4) + layout["slots"] * 2 * s)
+
+
 def spmv_a_bytes(n, m, nnz_a, s):
     """w = ρ̄Āp: Ā values and indices once, row pointers, p gathered once, w written once."""
     return nnz_a * (s + 4) + 4 * (m + 1) + n * s + m * s
@@ -63,7 +77,7 @@ def csrc_digest():
 def measured_traffic(workload, precision):
     """HBM bytes per launch of the dominant kernel from the committed counter runs, or None when
     there is no measurement for this workload/precision or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"spmv_B_Kp_{workload}_{precision}.traffic.json")
+    path = os.path.join(ROOT, "profiles", f"spmv_B_stream_{workload}_{precision}.traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -166,20 +180,33 @@ def main():
     nnz_a = p.meta["nnz_A"]
     nnz_b = p.meta["nnz_P_full"] + nnz_a
     kernels = {}
-    for kid, name, nbytes in ((qpg.QPG_KERNEL_SPMV_B, "spmv_B_Kp", spmv_b_bytes(n, m, nnz_b, sz)),
-                              (qpg.QPG_KERNEL_SPMV_A, "spmv_A_w", spmv_a_bytes(n, m, nnz_a, sz)),
-                              (qpg.QPG_KERNEL_PCG_UPDATE, "pcg_update", pcg_update_bytes(n, sz)),
-                              (qpg.QPG_KERNEL_PCG_DIR, "pcg_dir", pcg_dir_bytes(n, sz))):
+    pcg_steps = ((qpg.QPG_KERNEL_SPMV_B, "spmv_B_Kp", spmv_b_bytes(n, m, nnz_b, sz)),
+             (qpg.QPG_KERNEL_SPMV_A, "spmv_A_w", spmv_a_bytes(n, m, nnz_a, sz)),
+             (qpg.QPG_KERNEL_PCG_UPDATE, "pcg_update", pcg_update_bytes(n, sz)),
+             (qpg.QPG_KERNEL_PCG_DIR, "pcg_dir", pcg_dir_bytes(n, sz)))
+    for kid, name, nbytes in pcg_steps:
         us = s.time_kernel(kid, args.kernel_reps, prec_id)
         kernels[name] = {"avg_us": us, "bytes": nbytes, "GBs": nbytes / us / 1e3}
     pcg_bytes = sum(k["bytes"] for k in kernels.values())
     pcg_us = sum(k["avg_us"] for k in kernels.values())
-    dom = kernels["spmv_B_Kp"]
+    # the dominant kernel: the stream kernel of the B pass, timed alone
+    layout_b = s.spmv_layout(1)
+    us = s.time_kernel(qpg.QPG_KERNEL_SPMV_B_STREAM, args.kernel_reps, prec_id)
+    nbytes = spmv_b_stream_bytes(n, m, nnz_b, sz)
+    moved = stream_bytes_moved(layout_b, sz)
+    kernels["spmv_B_stream"] = {"avg_us": us, "bytes": nbytes, "GBs": nbytes / us / 1e3,
+                                "bytes_moved": moved, "GBs_moved": moved / us / 1e3, "layout": layout_b}
+    us_a = s.time_kernel(qpg.QPG_KERNEL_SPMV_A_STREAM, args.kernel_reps, prec_id)
+    kernels["spmv_A_stream"] = {"avg_us": us_a, "layout": s.spmv_layout(0)}
+    dom = kernels["spmv_B_stream"]
+    prec_tag = "float" if args.precision == "mixed" else "double"
     roofline = {"bound": "hbm", "achieved": dom["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dom["GBs"] / HBM_PEAK_GBS,
                 "traffic": measured_traffic(args.workload, args.precision),
-                "kernel": "k_spmv<OpKp> (Kp = P̄p + σp + Āᵀw, pᵀKp)", "bytes_per_launch": dom["bytes"],
-                "avg_us": dom["avg_us"],
+                "kernel": f"k_spmv<{prec_tag}, OpKp<{prec_tag}>> (segment sums of [P̄ | Āᵀ][p; w])",
+                "bytes_per_launch": dom["bytes"], "avg_us": dom["avg_us"],
+                "bytes_moved_per_launch": moved, "achieved_moved": dom["GBs_moved"],
+                "pass_B": kernels["spmv_B_Kp"],
                 "pcg_iteration": {"bytes": pcg_bytes, "kernel_us": pcg_us, "GBs": pcg_bytes / pcg_us / 1e3}}
     s.close()
 

@@ -177,20 +177,31 @@ int qpg_pcg(qpg_solver* h, int32_t precision, const double* b, const double* x0,
  * (Section 6.3.1–6.3.2). qpg_solve restarts from settings.rho. */
 int qpg_set_rho(qpg_solver* h, double rho);
 
-/* Average device duration, in microseconds, of `reps` back-to-back launches of one kernel of the
+/* Average device duration, in microseconds, of `reps` back-to-back launches of one step of the
  * PCG iteration (Algorithm 3 with the matrix-free K-matvec of Section 6.3), timed with HIP events
  * on the solver's stream, in the launch configuration the solve uses, on the current device
- * vectors (their contents are overwritten). Kernels:
- *   QPG_KERNEL_SPMV_A      w = ρ̄Āp                               (m rows of Ā)
- *   QPG_KERNEL_SPMV_B      Kp = P̄p + σp + Āᵀw, κ = pᵀKp, α         (n rows of [P̄ | Āᵀ])
- *   QPG_KERNEL_PCG_UPDATE  x̃ += αp, r += αKp, rᵀM⁻¹r, ‖r‖∞, β     (n)
- *   QPG_KERNEL_PCG_DIR     p = −M⁻¹r + βp                          (n)
+ * vectors (their contents are overwritten). Steps:
+ *   QPG_KERNEL_SPMV_A         w = ρ̄Āp (stream + combine kernels)       (m rows of Ā)
+ *   QPG_KERNEL_SPMV_B         Kp = P̄p + σp + Āᵀw, κ = pᵀKp, α (both)  (n rows of [P̄ | Āᵀ])
+ *   QPG_KERNEL_PCG_UPDATE     x̃ += αp, r += αKp, rᵀM⁻¹r, ‖r‖∞, β     (n)
+ *   QPG_KERNEL_PCG_DIR        p = −M⁻¹r + βp                          (n)
+ *   QPG_KERNEL_SPMV_A_STREAM  the stream kernel of SPMV_A alone (segment sums of Ā p)
+ *   QPG_KERNEL_SPMV_B_STREAM  the stream kernel of SPMV_B alone (segment sums of [P̄ | Āᵀ][p; w])
  * reps ≥ 1; precision as in qpg_apply. */
 #define QPG_KERNEL_SPMV_A 0
 #define QPG_KERNEL_SPMV_B 1
 #define QPG_KERNEL_PCG_UPDATE 2
 #define QPG_KERNEL_PCG_DIR 3
+#define QPG_KERNEL_SPMV_A_STREAM 4
+#define QPG_KERNEL_SPMV_B_STREAM 5
 int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t reps, double* avg_us);
+
+/* Layout of the SpMV work list of one matrix (0: Ā, 1: B = [P̄ | Āᵀ]), for measurement: out[0]
+ * matrix entries; out[1] stored positions in tiles with an LDS window (values + 16-bit column
+ * offsets; padding included); out[2] stored positions in the other tiles (values + 32-bit
+ * columns); out[3] workgroups (tiles); out[4] tiles with a window; out[5] columns staged in LDS
+ * per launch (sum over tiles); out[6] segment slots; out[7] segment chunks. */
+int qpg_spmv_layout(const qpg_solver* h, int32_t matrix, int64_t out[8]);
 
 /* K_ii = diag(P̄)_i + σ + ρ̄‖Ā_i‖² of the scaled reduced KKT matrix (Section 6.3.1), n values. */
 int qpg_get_kdiag(const qpg_solver* h, double rho, double* kdiag);

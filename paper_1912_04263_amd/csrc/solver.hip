@@ -423,6 +423,12 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
       case QPG_KERNEL_SPMV_B:
         h->spmv_B<T>(OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, h->n, h->st});
         break;
+      case QPG_KERNEL_SPMV_A_STREAM:
+        h->spmv<T>(h->plan_a, INT32_MAX, 1, OpScaled<T>{V.p, V.w, (T)h->rho_cur}, nullptr, false);
+        break;
+      case QPG_KERNEL_SPMV_B_STREAM:
+        h->spmv<T>(h->plan_b, h->n, 2, OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, h->n, h->st}, nullptr, false);
+        break;
       case QPG_KERNEL_PCG_UPDATE:
         hipLaunchKernelGGL((k_pcg_update<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.xt,
                            V.r, V.p, V.kp, V.dinv, (const DevState*)h->st, h->rb.partials,
@@ -472,6 +478,14 @@ void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr,
   pl.nrows = nrows;
   pl.slots = alloc<double>(3 * (size_t)std::max<int64_t>(t.nslot, 1));
   pl.max_wlen = t.max_wlen;
+  int64_t staged = 0, wtiles = 0;
+  for (const Tile& x : t.tiles) {
+    staged += x.wlen;
+    wtiles += x.wlen > 0;
+  }
+  const int64_t layout[8] = {(int64_t)rowptr[nrows] - rowptr[0], (int64_t)t.col16.size(), (int64_t)t.col32.size(),
+                             (int64_t)t.tiles.size(), wtiles, staged, t.nslot, (int64_t)t.chunks.size()};
+  std::copy(layout, layout + 8, pl.layout);
   HIPCHK(hipStreamSynchronize(stream));  // t's host arrays go out of scope
   pl.src = std::move(t.src);
 }
@@ -492,7 +506,7 @@ void qpg_solver::place_values(DevPlan& pl, const std::vector<double>& csr_val) {
 extern "C" {
 
 int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t reps, double* avg_us) {
-  if (!h || !avg_us || reps < 1 || kernel < 0 || kernel > QPG_KERNEL_PCG_DIR) return QPG_ERR_ARG;
+  if (!h || !avg_us || reps < 1 || kernel < 0 || kernel > QPG_KERNEL_SPMV_B_STREAM) return QPG_ERR_ARG;
   try {
     HIPCHK(hipSetDevice(h->device));
     if (precision == QPG_FP64) return time_kernel_impl<double>(h, kernel, reps, avg_us);
@@ -502,6 +516,13 @@ int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t re
   } catch (const HipError& e) {
     return device_error(h, e);
   }
+}
+
+int qpg_spmv_layout(const qpg_solver* h, int32_t matrix, int64_t out[8]) {
+  if (!h || !out || (matrix != 0 && matrix != 1)) return QPG_ERR_ARG;
+  const DevPlan& pl = matrix == 0 ? h->plan_a : h->plan_b;
+  std::copy(pl.layout, pl.layout + 8, out);
+  return QPG_OK;
 }
 
 int qpg_default_settings(qpg_settings* s) {

@@ -71,6 +71,7 @@ struct DevPlan {
   int64_t nslot = 0;
   int32_t nrows = 0;
   int32_t max_wlen = 0;  // largest staged window, in columns
+  int64_t layout[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see qpg_spmv_layout
   std::vector<int32_t> src;  // host copy of the SELL order (until the values are placed)
 };
 
@@ -157,7 +158,8 @@ struct qpg_solver {
   // SpMV launches (k_spmv, then k_combine); the returned count is the number of workgroup
   // partials a finalize must combine.
   template <typename T, class Op>
-  int spmv(const DevPlan& pl, int nsplit, int planes, const Op& op, const int32_t* gate) {
+  int spmv(const DevPlan& pl, int nsplit, int planes, const Op& op, const int32_t* gate,
+           bool combine = true) {
     using G = typename Gathered<Op, T>::type;
     const size_t shmem = (size_t)pl.max_wlen * sizeof(G);
     static size_t lds_allowed = 0;  // per instantiation: raise the dynamic LDS limit once
@@ -170,6 +172,7 @@ struct qpg_solver {
     hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles, pl.chunks,
                        pl.segslot, pl.col16, pl.col32, val, nsplit, op, static_cast<T*>(pl.slots), pl.nslot,
                        planes, gate);
+    if (!combine) return 0;
     hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
                        (const T*)static_cast<T*>(pl.slots), pl.nslot, planes, op, rb.partials, gate);
     return pl.ncomb;

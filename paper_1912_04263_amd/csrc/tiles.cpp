@@ -300,7 +300,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   flush_plain(true);
   plan.nslot = plan.rowslot[nrows];
   // combine work: lanes per row ≈ a quarter of its slots (1..64); a workgroup of kBlock threads
-  // takes up to four passes of rows with the same lane count
+  // takes one pass of rows with the same lane count (more workgroups, shorter dependency chains)
   int32_t r = 0;
   while (r < nrows) {
     auto lg_of = [&](int32_t q) {
@@ -310,7 +310,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
       return lg;
     };
     const int32_t lg = lg_of(r);
-    const int32_t cap = 4 * (kBlock >> lg);
+    const int32_t cap = kBlock >> lg;
     int32_t r1 = r + 1;
     while (r1 < nrows && r1 - r < cap && lg_of(r1) == lg) ++r1;
     plan.comb.push_back({r, r1, lg, 0});

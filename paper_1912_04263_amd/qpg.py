@@ -24,6 +24,7 @@ QPG_PRECOND_JACOBI, QPG_PRECOND_LEARNED = 0, 1
 QPG_NET_NPARAMS = 16705
 QPG_OP_A, QPG_OP_AT, QPG_OP_P, QPG_OP_K = 0, 1, 2, 3
 QPG_KERNEL_SPMV_A, QPG_KERNEL_SPMV_B, QPG_KERNEL_PCG_UPDATE, QPG_KERNEL_PCG_DIR = 0, 1, 2, 3
+QPG_KERNEL_SPMV_A_STREAM, QPG_KERNEL_SPMV_B_STREAM = 4, 5
 STATUS = {0: "unsolved", 1: "solved", 2: "max_iter_reached", 3: "numerical_error"}
 
 
@@ -79,6 +80,7 @@ SIGNATURES = {
                           _PI, _PD]),
     "qpg_set_rho": (C.c_int, [C.c_void_p, C.c_double]),
     "qpg_time_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _PD]),
+    "qpg_spmv_layout": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     "qpg_cleanup": (C.c_int, [C.c_void_p]),
     "qpg_get_kdiag": (C.c_int, [C.c_void_p, C.c_double, _PD]),
     "qpg_hutchinson": (C.c_int, [C.c_void_p, _PB, C.c_int32, C.c_double, C.c_double, C.c_int32, _PD]),
@@ -268,6 +270,15 @@ class Solver:
         us = C.c_double()
         self._check(lib().qpg_time_kernel(self._h, kernel, precision, reps, C.byref(us)))
         return us.value
+
+    def spmv_layout(self, matrix: int) -> dict:
+        """Work-list layout of Ā (0) or B (1): entries, stored positions with/without an LDS
+        window, tiles, windowed tiles, staged window columns, slots, chunks."""
+        out = (C.c_int64 * 8)()
+        self._check(lib().qpg_spmv_layout(self._h, matrix, out))
+        keys = ("entries", "windowed_positions", "plain_positions", "tiles", "windowed_tiles",
+                "staged_columns", "slots", "chunks")
+        return dict(zip(keys, (int(v) for v in out)))
 
     def kdiag(self, rho: float):
         out = np.empty(self.n)
