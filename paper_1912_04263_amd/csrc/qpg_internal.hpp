@@ -58,7 +58,7 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = 
 // epilogue.
 
 constexpr int kSegMax = 256;   // entries of one segment at most
-constexpr int kSpmvBlock = 512; // threads per SpMV workgroup (one chunk at a time per wavefront)
+constexpr int kSpmvBlock = 1024; // threads per SpMV workgroup (one chunk at a time per wavefront)
 constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most; ≤ 65536)
 
 struct Chunk {

@@ -299,20 +299,23 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   }
   flush_plain(true);
   plan.nslot = plan.rowslot[nrows];
-  // combine work: lanes per row ≈ a quarter of its slots (1..64); a workgroup of kBlock threads
-  // takes one pass of rows with the same lane count (more workgroups, shorter dependency chains)
+  // combine work: lanes per row ≈ a quarter of the row's slots (1..64), the largest over the
+  // rows of one workgroup; a workgroup of kBlock threads takes one pass of consecutive rows
+  auto lg_of = [&](int32_t q) {
+    const int32_t ns = plan.rowslot[q + 1] - plan.rowslot[q];
+    int32_t lg = 0;
+    while (lg < 6 && (4 << lg) < ns) ++lg;
+    return lg;
+  };
   int32_t r = 0;
   while (r < nrows) {
-    auto lg_of = [&](int32_t q) {
-      const int32_t ns = plan.rowslot[q + 1] - plan.rowslot[q];
-      int32_t lg = 0;
-      while (lg < 6 && (4 << lg) < ns) ++lg;
-      return lg;
-    };
-    const int32_t lg = lg_of(r);
-    const int32_t cap = kBlock >> lg;
-    int32_t r1 = r + 1;
-    while (r1 < nrows && r1 - r < cap && lg_of(r1) == lg) ++r1;
+    int32_t lg = lg_of(r), r1 = r + 1;
+    while (r1 < nrows) {
+      const int32_t l2 = std::max(lg, lg_of(r1));
+      if (r1 + 1 - r > (kBlock >> l2)) break;
+      lg = l2;
+      ++r1;
+    }
     plan.comb.push_back({r, r1, lg, 0});
     r = r1;
   }
