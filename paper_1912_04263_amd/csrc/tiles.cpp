@@ -12,7 +12,9 @@
 //     least half of the block's entries.
 // A window is staged only if it holds at least one entry per 16 of its columns, so that staging
 // never reads more than the gathers it replaces. Entries outside every staged window go to tiles
-// without a window, of about plain_nnz entries each.
+// without a window, of about plain_nnz entries each. Runs whose rows are too sparse for any
+// window but spread over several 2^17-column ranges (≥ kMinSeg entries per row in each) are cut
+// at those ranges too, and their tiles are issued range by range (L2 locality of the gathers).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -28,6 +30,10 @@ constexpr int kMinSeg = 16;         // entries per row and range for a multi-ran
 constexpr int64_t kMinTiles = 512;  // workgroups a launch should have (two per compute unit)
 constexpr int64_t kMinTileNnz = 1024;
 constexpr int kLanes = 64;
+// Column ranges of 2^17 entries (1 MB of FP64) for rows too sparse for LDS windows: their tiles
+// are issued range by range, so that the workgroups in flight gather from one range that the L2
+// caches hold, instead of from all of the vector.
+constexpr int kL2Shift = 17;
 
 int32_t log2_exact(int32_t v) {
   int32_t l = 0;
@@ -65,6 +71,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   const int64_t nfine = ((int64_t)ncols + (1 << fsh) - 1) >> fsh;
   std::vector<int64_t> cnt(std::max<int64_t>(nwin, 1), 0), fine(std::max<int64_t>(nfine, 1), 0);
   std::vector<int64_t> touched_w, touched_f;
+  std::vector<int64_t> cnt2(std::max<int64_t>(((int64_t)ncols >> kL2Shift) + 1, 1), 0), touched_2;
 
   // first entry of row r at or after column c
   auto seek = [&](int32_t r, int64_t c) {
@@ -135,7 +142,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   std::vector<int32_t> bnd;
   std::vector<std::vector<Seg>> wsegs;
   auto add_block = [&](int32_t b0, int32_t b1, const std::vector<int64_t>& cut, const std::vector<int32_t>& wlo,
-                       const std::vector<int32_t>& wlen) {
+                       const std::vector<int32_t>& wlen, std::vector<std::vector<Seg>>* by_range = nullptr) {
     const int32_t K = (int32_t)cut.size() - 1, Rb = b1 - b0;
     const int32_t stride = 3 * K + 1;
     bnd.assign((size_t)Rb * stride, 0);
@@ -161,11 +168,13 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
       const int32_t* B = &bnd[(size_t)i * stride];
       int32_t next = plan.rowslot[b0 + i];
       for (int32_t j = 0; j < K; ++j) {
-        const size_t before = plain.size();
-        cut_segs(plain, B[3 * j], B[3 * j + 1], &next);
+        std::vector<Seg>& out = by_range ? (*by_range)[j] : plain;
+        const size_t before = out.size();
+        cut_segs(out, B[3 * j], B[3 * j + 1], &next);
         cut_segs(wsegs[j], B[3 * j + 1], B[3 * j + 2], &next);
-        cut_segs(plain, B[3 * j + 2], B[3 * j + 3], &next);
-        for (size_t q = before; q < plain.size(); ++q) plain_entries += plain[q].len;
+        cut_segs(out, B[3 * j + 2], B[3 * j + 3], &next);
+        if (!by_range)
+          for (size_t q = before; q < plain.size(); ++q) plain_entries += plain[q].len;
       }
     }
     for (int32_t j = 0; j < K; ++j) add_tile(wsegs[j], wlo[j], wlen[j]);
@@ -196,7 +205,18 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
       const int32_t c = col[k];
       if (cnt[c >> sh]++ == 0) touched_w.push_back(c >> sh);
       if (fine[c >> fsh]++ == 0) touched_f.push_back(c >> fsh);
+      if (cnt2[c >> kL2Shift]++ == 0) touched_2.push_back(c >> kL2Shift);
     }
+    std::vector<int64_t> S2;  // L2-sized column ranges holding kMinSeg entries per row
+    int64_t covS2 = 0;
+    for (int64_t w : touched_2)
+      if (cnt2[w] >= kMinSeg * rows_g) {
+        S2.push_back(w);
+        covS2 += cnt2[w];
+      }
+    std::sort(S2.begin(), S2.end());
+    for (int64_t w : touched_2) cnt2[w] = 0;
+    touched_2.clear();
     std::vector<int64_t> S;  // qualifying windows (sorted)
     int64_t covS = 0;
     for (int64_t w : touched_w)
@@ -258,6 +278,30 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
           }
         }
         add_block(b0, b1, cut, wlo, wlen);
+      }
+    } else if (S2.size() >= 2 && 2 * covS2 >= nnz_g && 2 * best < nnz_g) {
+      // ---- multi-range blocks without windows, tiles issued range by range
+      const int32_t K = (int32_t)S2.size();
+      std::vector<int64_t> cut(K + 1);
+      cut[0] = 0;
+      for (int32_t j = 1; j < K; ++j) cut[j] = S2[j] << kL2Shift;
+      cut[K] = ncols;
+      const int32_t R = block_rows(plain_nnz, (double)covS2 / (double)(rows_g * K));
+      std::vector<std::vector<Seg>> by_range(K);
+      const std::vector<int32_t> none(K, 0);
+      for (int32_t b0 = g0; b0 < g1; b0 += R) add_block(b0, std::min(g1, b0 + R), cut, none, none, &by_range);
+      for (int32_t j = 0; j < K; ++j) {
+        std::vector<Seg>& v = by_range[j];
+        size_t i = 0;
+        while (i < v.size()) {
+          // about plain_nnz entries, in whole chunks
+          size_t e = i;
+          int64_t ent = 0;
+          while (e < v.size() && (ent < plain_nnz || (e - i) % kLanes != 0)) ent += v[e++].len;
+          std::vector<Seg> t(v.begin() + i, v.begin() + e);
+          add_tile(t, 0, 0);
+          i = e;
+        }
       }
     } else {
       // ---- single-range blocks

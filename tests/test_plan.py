@@ -99,3 +99,12 @@ def test_small_work_units_on_a_random_matrix(exe, tmp_path):
     rng = np.random.default_rng(3)
     M = sp.random(3000, 50000, density=2e-3, random_state=rng, format="csr")
     run(exe, tmp_path, M, nsplit=20000, tile_nnz=1024, plain_nnz=1024, wcap=2048)
+
+
+def test_sparse_wide_rows_take_the_l2_range_layout(exe, tmp_path):
+    # 100 entries per row over 400,000 columns: too sparse for an LDS window (≈ 2 per 8192
+    # columns) but ≈ 33 per 2^17-column range, so the rows are cut at those ranges
+    rng = np.random.default_rng(4)
+    M = sp.random(3000, 400000, density=100 / 400000, random_state=rng, format="csr")
+    st = stats(run(exe, tmp_path, M, nsplit=50000))
+    assert st["windowed"] == 0 and st["slots"] >= 3 * 3000
