@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqpg.so")
-SOURCES = ["solver.hip", "learned.hip", "host_prep.cpp", "tiles.cpp"]
+SOURCES = ["solver.hip", "learned.hip", "host_prep.cpp", "tiles.cpp", "host_parallel.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -1,9 +1,11 @@
 // Host-side preparation: input validation, CSC → CSR conversions, modified Ruiz
 // equilibration (Algorithm 2) and the SpMV work schedule.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <limits>
+#include <thread>
 
 #include "qpg_internal.hpp"
 
@@ -11,7 +13,44 @@ namespace qpg {
 
 namespace {
 
-// Structural checks of a CSC matrix; `upper` additionally requires row ≤ column.
+// The first structural error of column j of a CSC matrix (0 if none); `upper` additionally
+// requires row ≤ column.
+int column_error(const qpg_csc* M, int32_t j, int32_t nrows, bool upper, const char* name, std::string* msg) {
+  char buf[256];
+  const int32_t a = M->colptr[j], b = M->colptr[j + 1];
+  if (b < a) {
+    *msg = std::string(name) + ": colptr not monotone";
+    return QPG_ERR_ARG;
+  }
+  for (int32_t k = a; k < b; ++k) {
+    const int32_t i = M->rowidx[k];
+    if (i < 0 || i >= nrows) {
+      std::snprintf(buf, sizeof(buf), "%s: row index %d out of range in column %d", name, (int)i, (int)j);
+      *msg = buf;
+      return QPG_ERR_ARG;
+    }
+    if (k > a && i <= M->rowidx[k - 1]) {
+      std::snprintf(buf, sizeof(buf), "%s: row indices of column %d not strictly increasing", name, (int)j);
+      *msg = buf;
+      return QPG_ERR_ARG;
+    }
+    if (upper && i > j) {
+      std::snprintf(buf, sizeof(buf), "%s: entry (%d,%d) below the diagonal", name, (int)i, (int)j);
+      *msg = buf;
+      return QPG_ERR_ARG;
+    }
+  }
+  return QPG_OK;
+}
+
+void atomic_min(std::atomic<int64_t>& a, int64_t v) {
+  int64_t cur = a.load();
+  while (v < cur && !a.compare_exchange_weak(cur, v)) {
+  }
+}
+
+// Structural checks of a CSC matrix (columns checked in parallel; the first failing column is
+// reported, as a serial scan would).
 int check_csc(const qpg_csc* M, int32_t nrows, int32_t ncols, bool upper, const char* name,
               std::string* msg) {
   char buf[256];
@@ -29,41 +68,89 @@ int check_csc(const qpg_csc* M, int32_t nrows, int32_t ncols, bool upper, const 
     *msg = std::string(name) + ": colptr must start at 0 and end at nnz";
     return QPG_ERR_ARG;
   }
-  for (int32_t j = 0; j < ncols; ++j) {
-    int32_t a = M->colptr[j], b = M->colptr[j + 1];
-    if (b < a) {
+  // monotone colptr first, so that every column range below is inside [0, nnz]
+  for (int32_t j = 0; j < ncols; ++j)
+    if (M->colptr[j + 1] < M->colptr[j]) {
       *msg = std::string(name) + ": colptr not monotone";
       return QPG_ERR_ARG;
     }
-    for (int32_t k = a; k < b; ++k) {
-      int32_t i = M->rowidx[k];
-      if (i < 0 || i >= nrows) {
-        std::snprintf(buf, sizeof(buf), "%s: row index %d out of range in column %d", name, (int)i,
-                      (int)j);
-        *msg = buf;
-        return QPG_ERR_ARG;
+  std::atomic<int64_t> bad{INT64_MAX};
+  parallel_chunks(ncols, 4096, [&](int64_t, int64_t lo, int64_t hi) {
+    std::string m2;
+    for (int64_t j = lo; j < hi; ++j)
+      if (column_error(M, (int32_t)j, nrows, upper, name, &m2)) {
+        atomic_min(bad, j);
+        return;
       }
-      if (k > a && i <= M->rowidx[k - 1]) {
-        std::snprintf(buf, sizeof(buf), "%s: row indices of column %d not strictly increasing",
-                      name, (int)j);
-        *msg = buf;
-        return QPG_ERR_ARG;
+  });
+  if (bad.load() != INT64_MAX) return column_error(M, (int32_t)bad.load(), nrows, upper, name, msg);
+  std::atomic<int64_t> nonfinite{INT64_MAX};
+  parallel_chunks(M->nnz, 1 << 20, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t k = lo; k < hi; ++k)
+      if (!std::isfinite(M->val[k])) {
+        atomic_min(nonfinite, k);
+        return;
       }
-      if (upper && i > j) {
-        std::snprintf(buf, sizeof(buf), "%s: entry (%d,%d) below the diagonal", name, (int)i,
-                      (int)j);
-        *msg = buf;
-        return QPG_ERR_ARG;
-      }
-    }
-  }
-  for (int32_t k = 0; k < M->nnz; ++k) {
-    if (!std::isfinite(M->val[k])) {
-      *msg = std::string(name) + ": non-finite value";
-      return QPG_ERR_DATA;
-    }
+  });
+  if (nonfinite.load() != INT64_MAX) {
+    *msg = std::string(name) + ": non-finite value";
+    return QPG_ERR_DATA;
   }
   return QPG_OK;
+}
+
+// Builds a CSR matrix (nrows rows) from entries produced column by column: emit(j, put) calls
+// put(row, column, value) for the entries of column j in order. Rows come out in the order a
+// serial pass over the columns would produce. The columns are cut into parts of about equal work
+// (work[j] = number of entries column j emits, as a prefix array); each part counts its entries
+// per row, the counts give each part its own write position in every row, and a second pass
+// writes them. The result does not depend on the number of parts.
+template <class Emit>
+void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& work, Emit emit,
+                     std::vector<int32_t>& ptr, hvec<int32_t>& col, hvec<double>& val) {
+  const int64_t total = work[ncols];
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int T = total < (1 << 18) ? 1 : std::min(16, hw);
+  std::vector<int32_t> cut(T + 1);
+  for (int t = 0; t <= T; ++t)
+    cut[t] = (int32_t)(std::lower_bound(work.begin(), work.end(), total * t / T) - work.begin());
+  cut[0] = 0;
+  cut[T] = ncols;
+  std::vector<std::vector<int32_t>> pos(T);
+  parallel_chunks(T, 1, [&](int64_t t, int64_t, int64_t) {
+    auto& c = pos[t];
+    c.assign(nrows, 0);
+    for (int32_t j = cut[t]; j < cut[t + 1]; ++j) emit(j, [&](int32_t r, int32_t, double) { c[r]++; });
+  });
+  ptr.assign((size_t)nrows + 1, 0);
+  parallel_chunks(nrows, 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      int32_t s = 0;
+      for (int t = 0; t < T; ++t) s += pos[t][i];
+      ptr[i + 1] = s;
+    }
+  });
+  for (int32_t i = 0; i < nrows; ++i) ptr[i + 1] += ptr[i];
+  parallel_chunks(nrows, 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      int32_t o = ptr[i];
+      for (int t = 0; t < T; ++t) {
+        const int32_t c = pos[t][i];
+        pos[t][i] = o;
+        o += c;
+      }
+    }
+  });
+  col.resize(ptr[nrows]);
+  val.resize(ptr[nrows]);
+  parallel_chunks(T, 1, [&](int64_t t, int64_t, int64_t) {
+    auto& o = pos[t];
+    for (int32_t j = cut[t]; j < cut[t + 1]; ++j)
+      emit(j, [&](int32_t r, int32_t c, double v) {
+        col[o[r]] = c;
+        val[o[r]++] = v;
+      });
+  });
 }
 
 double guard_norm(double v) {
@@ -173,11 +260,17 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
     }
   }
   // full P has at most 2·nnz(triu) entries; B holds full P and Aᵀ
-  int64_t nnzP_full = 0;
-  for (int32_t j = 0; j < n; ++j)
-    for (int32_t k = Pt->colptr[j]; k < Pt->colptr[j + 1]; ++k)
-      nnzP_full += (Pt->rowidx[k] == j) ? 1 : 2;
-  if (nnzP_full + (int64_t)A->nnz > std::numeric_limits<int32_t>::max()) {
+  std::vector<int64_t> p_work((size_t)n + 1, 0), a_work((size_t)n + 1);
+  parallel_chunks(n, 1 << 14, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t j = lo; j < hi; ++j) {
+      int64_t e = 0;
+      for (int32_t k = Pt->colptr[j]; k < Pt->colptr[j + 1]; ++k) e += (Pt->rowidx[k] == j) ? 1 : 2;
+      p_work[j + 1] = e;
+    }
+  });
+  for (int32_t j = 0; j < n; ++j) p_work[j + 1] += p_work[j];
+  for (int32_t j = 0; j <= n; ++j) a_work[j] = A->colptr[j];
+  if (p_work[n] + (int64_t)A->nnz > std::numeric_limits<int32_t>::max()) {
     *msg = "nnz(P) + nnz(A) overflows int32";
     return QPG_ERR_SIZE;
   }
@@ -189,48 +282,54 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
   // ---- full P in CSR from its upper triangle in CSC (Section 6.2). Visiting the triangle's
   // columns in order emits, for row i, first the entries (i, k < i) and the diagonal (from
   // column i), then (i, j > i) from later columns: each row comes out sorted.
-  std::vector<int32_t> p_ptr(n + 1, 0);
-  for (int32_t j = 0; j < n; ++j)
-    for (int32_t k = Pt->colptr[j]; k < Pt->colptr[j + 1]; ++k) {
-      int32_t i = Pt->rowidx[k];
-      p_ptr[i + 1]++;
-      if (i != j) p_ptr[j + 1]++;
-    }
-  for (int32_t i = 0; i < n; ++i) p_ptr[i + 1] += p_ptr[i];
-  std::vector<int32_t> p_col(p_ptr[n]);
-  std::vector<double> p_val(p_ptr[n]);
-  {
-    std::vector<int32_t> next(p_ptr.begin(), p_ptr.end() - 1);
-    for (int32_t j = 0; j < n; ++j)
-      for (int32_t k = Pt->colptr[j]; k < Pt->colptr[j + 1]; ++k) {
-        int32_t i = Pt->rowidx[k];
-        double v = Pt->val[k];
-        if (i != j) {
-          p_col[next[j]] = i;
-          p_val[next[j]++] = v;  // (j, i), i < j: lower part of row j
+  std::vector<int32_t> p_ptr;
+  hvec<int32_t> p_col;
+  hvec<double> p_val;
+  columns_to_rows(
+      n, n, p_work,
+      [&](int32_t j, auto&& put) {
+        for (int32_t k = Pt->colptr[j]; k < Pt->colptr[j + 1]; ++k) {
+          const int32_t i = Pt->rowidx[k];
+          const double v = Pt->val[k];
+          if (i != j) put(j, i, v);  // (j, i), i < j: lower part of row j
+          put(i, j, v);              // (i, j), i ≤ j
         }
-        p_col[next[i]] = j;
-        p_val[next[i]++] = v;  // (i, j), i ≤ j
+      },
+      p_ptr, p_col, p_val);
+  // ---- A in CSR (visiting the CSC columns in order keeps each row's columns sorted)
+  columns_to_rows(
+      n, m, a_work,
+      [&](int32_t j, auto&& put) {
+        for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k) put(A->rowidx[k], j, A->val[k]);
+      },
+      H.a_ptr, H.a_col, H.a_val);
+  // ---- B = [P | Aᵀ]: row i is row i of the full P, then column i of A (CSC of A = CSR of Aᵀ)
+  constexpr int64_t kRows = 1 << 13;  // rows or columns per parallel chunk
+  H.b_ptr.assign(n + 1, 0);
+  H.b_split.resize(n);
+  for (int32_t i = 0; i < n; ++i)
+    H.b_ptr[i + 1] = H.b_ptr[i] + (p_ptr[i + 1] - p_ptr[i]) + (A->colptr[i + 1] - A->colptr[i]);
+  H.b_col.resize(H.b_ptr[n]);
+  H.b_val.resize(H.b_ptr[n]);
+  parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      int32_t o = H.b_ptr[i];
+      for (int32_t k = p_ptr[i]; k < p_ptr[i + 1]; ++k, ++o) {
+        H.b_col[o] = p_col[k];
+        H.b_val[o] = p_val[k];
       }
-  }
-  // ---- A in CSR (counting sort over the CSC columns keeps each row's columns sorted)
-  H.a_ptr.assign(m + 1, 0);
-  for (int32_t k = 0; k < A->nnz; ++k) H.a_ptr[A->rowidx[k] + 1]++;
-  for (int32_t i = 0; i < m; ++i) H.a_ptr[i + 1] += H.a_ptr[i];
-  H.a_col.resize(A->nnz);
-  std::vector<double> a_raw(A->nnz);
-  {
-    std::vector<int32_t> next(H.a_ptr.begin(), H.a_ptr.end() - 1);
-    for (int32_t j = 0; j < n; ++j)
-      for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k) {
-        int32_t i = A->rowidx[k];
-        H.a_col[next[i]] = j;
-        a_raw[next[i]++] = A->val[k];
+      H.b_split[i] = o;
+      for (int32_t k = A->colptr[i]; k < A->colptr[i + 1]; ++k, ++o) {
+        H.b_col[o] = n + A->rowidx[k];
+        H.b_val[o] = A->val[k];
       }
-  }
-  std::vector<double> at_raw(A->val, A->val + A->nnz);  // CSC of A = CSR of Aᵀ
+    }
+  });
+  hvec<int32_t>().swap(p_col);
+  hvec<double>().swap(p_val);
 
-  // ---- modified Ruiz equilibration (Algorithm 2), applied incrementally to the working copies.
+  // ---- modified Ruiz equilibration (Algorithm 2), applied incrementally to Ā (CSR) and to B,
+  // whose left part is P̄ and right part Āᵀ.
   // Readings: P̄ ← c·DPD (so that P̄ = cDPD holds after every pass); stop after a pass whose δ
   // satisfies ‖1 − δ‖∞ ≤ 1e-3, at most scaling_iters passes; norms below 1e-4 count as 1 and
   // are capped at 1e4 (also for the denominator of γ).
@@ -242,55 +341,75 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
   double c = 1.0;
   H.scaling_passes = 0;
   std::vector<double> dD(n), dE(m), nx(n), nz(m);
+  // largest value over chunked per-index results (max is exact, so the order does not matter)
+  auto chunk_max = [](int64_t len, const std::function<double(int64_t)>& f) {
+    const int64_t nc = (len + kRows - 1) / kRows;
+    std::vector<double> part((size_t)std::max<int64_t>(nc, 1), 0.0);
+    parallel_chunks(len, kRows, [&](int64_t ci, int64_t lo, int64_t hi) {
+      double mx = 0.0;
+      for (int64_t i = lo; i < hi; ++i) mx = std::max(mx, f(i));
+      part[ci] = mx;
+    });
+    return *std::max_element(part.begin(), part.end());
+  };
+  // per-row ∞-norms of B's entries [k0(r), k1(r)) into out
+  auto row_max = [&](std::vector<double>& out, int64_t rows, const std::function<int32_t(int64_t)>& k0,
+                     const std::function<int32_t(int64_t)>& k1, const hvec<double>& v) {
+    parallel_chunks(rows, kRows, [&](int64_t, int64_t lo, int64_t hi) {
+      for (int64_t r = lo; r < hi; ++r) {
+        double mx = 0.0;
+        for (int32_t k = k0(r), e = k1(r); k < e; ++k) mx = std::max(mx, std::fabs(v[k]));
+        out[r] = mx;
+      }
+    });
+  };
+  auto b_row0 = [&](int64_t i) { return H.b_ptr[i]; };
+  auto b_row1 = [&](int64_t i) { return H.b_ptr[i + 1]; };
+  auto b_mid = [&](int64_t i) { return H.b_split[i]; };
   for (int32_t pass = 0; pass < s->scaling_iters; ++pass) {
     H.scaling_passes++;
-    // column ∞-norms of M = [P̄ Āᵀ; Ā 0]: column j ≤ n is column j of P̄ (= row j) and of Ā
-    for (int32_t j = 0; j < n; ++j) {
-      double mx = 0.0;
-      for (int32_t k = p_ptr[j]; k < p_ptr[j + 1]; ++k) mx = std::max(mx, std::fabs(p_val[k]));
-      for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k)
-        mx = std::max(mx, std::fabs(at_raw[k]));
-      nx[j] = mx;
-    }
-    for (int32_t i = 0; i < m; ++i) {
-      double mx = 0.0;
-      for (int32_t k = H.a_ptr[i]; k < H.a_ptr[i + 1]; ++k) mx = std::max(mx, std::fabs(a_raw[k]));
-      nz[i] = mx;
-    }
-    double dev = 0.0;
-    for (int32_t j = 0; j < n; ++j) {
-      dD[j] = 1.0 / std::sqrt(guard_norm(nx[j]));
-      dev = std::max(dev, std::fabs(1.0 - dD[j]));
-      D[j] *= dD[j];
-    }
-    for (int32_t i = 0; i < m; ++i) {
-      dE[i] = 1.0 / std::sqrt(guard_norm(nz[i]));
-      dev = std::max(dev, std::fabs(1.0 - dE[i]));
-      E[i] *= dE[i];
-    }
-    for (int32_t i = 0; i < n; ++i)
-      for (int32_t k = p_ptr[i]; k < p_ptr[i + 1]; ++k) p_val[k] = (p_val[k] * dD[i]) * dD[p_col[k]];
-    for (int32_t i = 0; i < m; ++i)
-      for (int32_t k = H.a_ptr[i]; k < H.a_ptr[i + 1]; ++k)
-        a_raw[k] = (a_raw[k] * dE[i]) * dD[H.a_col[k]];
-    for (int32_t j = 0; j < n; ++j)
-      for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k)
-        at_raw[k] = (at_raw[k] * dE[A->rowidx[k]]) * dD[j];
-    double qmax = 0.0;
-    for (int32_t j = 0; j < n; ++j) {
+    // column ∞-norms of M = [P̄ Āᵀ; Ā 0]: column j ≤ n is column j of P̄ and of Ā = row j of B;
+    // column n + i is row i of Ā
+    row_max(nx, n, b_row0, b_row1, H.b_val);
+    row_max(nz, m, [&](int64_t i) { return H.a_ptr[i]; }, [&](int64_t i) { return H.a_ptr[i + 1]; }, H.a_val);
+    const double dev = std::max(chunk_max(n,
+                                          [&](int64_t j) {
+                                            dD[j] = 1.0 / std::sqrt(guard_norm(nx[j]));
+                                            D[j] *= dD[j];
+                                            return std::fabs(1.0 - dD[j]);
+                                          }),
+                                chunk_max(m, [&](int64_t i) {
+                                  dE[i] = 1.0 / std::sqrt(guard_norm(nz[i]));
+                                  E[i] *= dE[i];
+                                  return std::fabs(1.0 - dE[i]);
+                                }));
+    parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i) {
+        int32_t k = H.b_ptr[i];
+        for (; k < H.b_split[i]; ++k) H.b_val[k] = (H.b_val[k] * dD[i]) * dD[H.b_col[k]];
+        for (; k < H.b_ptr[i + 1]; ++k) H.b_val[k] = (H.b_val[k] * dE[H.b_col[k] - n]) * dD[i];
+      }
+    });
+    parallel_chunks(m, kRows, [&](int64_t, int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i)
+        for (int32_t k = H.a_ptr[i]; k < H.a_ptr[i + 1]; ++k)
+          H.a_val[k] = (H.a_val[k] * dE[i]) * dD[H.a_col[k]];
+    });
+    const double qmax = chunk_max(n, [&](int64_t j) {
       H.qb[j] *= dD[j];
-      qmax = std::max(qmax, std::fabs(H.qb[j]));
-    }
-    // cost scaling γ = 1 / max(mean_j ‖P̄_j‖∞, ‖q̄‖∞)
+      return std::fabs(H.qb[j]);
+    });
+    // cost scaling γ = 1 / max(mean_j ‖P̄_j‖∞, ‖q̄‖∞); the column norms in parallel, their sum
+    // in index order
+    row_max(nx, n, b_row0, b_mid, H.b_val);
     double mean = 0.0;
-    for (int32_t j = 0; j < n; ++j) {
-      double mx = 0.0;
-      for (int32_t k = p_ptr[j]; k < p_ptr[j + 1]; ++k) mx = std::max(mx, std::fabs(p_val[k]));
-      mean += mx;
-    }
+    for (int32_t j = 0; j < n; ++j) mean += nx[j];
     mean /= (double)n;
-    double gamma = 1.0 / guard_norm(std::max(mean, qmax));
-    for (auto& v : p_val) v *= gamma;
+    const double gamma = 1.0 / guard_norm(std::max(mean, qmax));
+    parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i)
+        for (int32_t k = H.b_ptr[i]; k < H.b_split[i]; ++k) H.b_val[k] *= gamma;
+    });
     for (auto& v : H.qb) v *= gamma;
     c *= gamma;
     if (dev <= 1e-3) break;
@@ -306,32 +425,18 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
     H.ub[i] = E[i] * ui;
   }
 
-  // ---- B = [P̄ | Āᵀ]
-  H.b_ptr.assign(n + 1, 0);
-  H.b_split.resize(n);
-  for (int32_t i = 0; i < n; ++i)
-    H.b_ptr[i + 1] = H.b_ptr[i] + (p_ptr[i + 1] - p_ptr[i]) + (A->colptr[i + 1] - A->colptr[i]);
-  H.b_col.resize(H.b_ptr[n]);
-  H.b_val.resize(H.b_ptr[n]);
+  // ---- diag(P̄) and the squared column norms of Ā (Section 6.3.1) from the rows of B
   H.diagP.assign(n, 0.0);
   H.colsq.assign(n, 0.0);
-  for (int32_t i = 0; i < n; ++i) {
-    int32_t o = H.b_ptr[i];
-    for (int32_t k = p_ptr[i]; k < p_ptr[i + 1]; ++k, ++o) {
-      H.b_col[o] = p_col[k];
-      H.b_val[o] = p_val[k];
-      if (p_col[k] == i) H.diagP[i] = p_val[k];
+  parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      for (int32_t k = H.b_ptr[i]; k < H.b_split[i]; ++k)
+        if (H.b_col[k] == i) H.diagP[i] = H.b_val[k];
+      double sq = 0.0;
+      for (int32_t k = H.b_split[i]; k < H.b_ptr[i + 1]; ++k) sq += H.b_val[k] * H.b_val[k];
+      H.colsq[i] = sq;
     }
-    H.b_split[i] = o;
-    double sq = 0.0;
-    for (int32_t k = A->colptr[i]; k < A->colptr[i + 1]; ++k, ++o) {
-      H.b_col[o] = n + A->rowidx[k];
-      H.b_val[o] = at_raw[k];
-      sq += at_raw[k] * at_raw[k];
-    }
-    H.colsq[i] = sq;
-  }
-  H.a_val = std::move(a_raw);
+  });
   double qn = 0.0;
   for (int32_t i = 0; i < n; ++i) qn = std::max(qn, std::fabs(q[i]));
   H.q_norm_unscaled = qn;

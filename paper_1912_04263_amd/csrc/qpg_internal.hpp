@@ -2,12 +2,40 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
+#include <memory>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/qpg.h"
 
 namespace qpg {
+
+// Allocator whose resize() leaves new elements default-initialised (for plain numbers: not
+// written), so that nnz-sized host arrays are first touched by the threads that fill them rather
+// than zeroed by one thread beforehand.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) noexcept {}
+  template <class U>
+  void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+    ::new ((void*)p) U;
+  }
+  template <class U, class... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using hvec = std::vector<T, NoInit<T>>;
 
 constexpr double kInf = 1e20;       // |bound| ≥ kInf is infinite
 constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64)
@@ -84,9 +112,9 @@ struct TilePlan {
   std::vector<Chunk> chunks;
   std::vector<int32_t> segslot;  // per segment (64 per chunk, −1 for an empty lane): output slot
   std::vector<int32_t> rowslot;  // nrows + 1: the slots of row r are [rowslot[r], rowslot[r + 1])
-  std::vector<int32_t> src;      // per SELL value position: CSR index, −1 for padding
-  std::vector<uint16_t> col16;   // column offsets of windowed tiles (SELL order)
-  std::vector<int32_t> col32;    // columns of the other tiles (SELL order)
+  hvec<int32_t> src;             // per SELL value position: CSR index, −1 for padding
+  hvec<uint16_t> col16;          // column offsets of windowed tiles (SELL order)
+  hvec<int32_t> col32;           // columns of the other tiles (SELL order)
   int64_t nslot = 0;
   int32_t max_wlen = 0;          // largest staged window (columns)
 };
@@ -98,20 +126,29 @@ struct TileParams {
   int32_t max_rows;   // rows per block at most
 };
 
-// nrows × ncols CSR matrix with sorted column indices in each row.
-TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col, int32_t nrows,
-                    int32_t ncols, const TileParams& tp);
+// nrows × ncols CSR matrix (row pointers rowptr[0..nrows], column indices col[rowptr[0] ..
+// rowptr[nrows]), sorted within each row).
+TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows, int32_t ncols,
+                    const TileParams& tp);
+
+// ---- host parallelism for setup
+// f(c, lo, hi) for the chunks [c·chunk, min(n, (c+1)·chunk)) of [0, n), on up to 16 threads.
+// The chunking does not depend on the thread count, so results that combine per-chunk partials
+// in chunk order are the same on every machine.
+void parallel_chunks(int64_t n, int64_t chunk, const std::function<void(int64_t, int64_t, int64_t)>& f);
 
 // The problem after validation, format conversion and Ruiz equilibration, all on the host.
 struct HostProblem {
   int32_t n = 0, m = 0;
   // Ā in CSR (m rows, n columns)
-  std::vector<int32_t> a_ptr, a_col;
-  std::vector<double> a_val;
+  std::vector<int32_t> a_ptr;
+  hvec<int32_t> a_col;
+  hvec<double> a_val;
   // B = [P̄ | Āᵀ] in CSR (n rows, n + m columns): row i holds row i of the full P̄ (columns
   // 0..n−1) followed by row i of Āᵀ (columns n + j); b_split[i] is where the Āᵀ part starts.
-  std::vector<int32_t> b_ptr, b_split, b_col;
-  std::vector<double> b_val;
+  std::vector<int32_t> b_ptr, b_split;
+  hvec<int32_t> b_col;
+  hvec<double> b_val;
   std::vector<double> qb, lb, ub;      // q̄ = cDq, l̄ = El, ū = Eu (bounds clamped to ±kInf first)
   std::vector<double> D, E;            // Ruiz factors
   double c = 1.0;

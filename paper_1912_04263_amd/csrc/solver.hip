@@ -1,6 +1,8 @@
 // Solver object and C ABI: device memory, SpMV schedules, the ADMM loop of Algorithm 1 with the
 // inexact reduced-KKT PCG step of Section 6.3, termination (Section 3.1), the PCG tolerance
 // rule (Section 6.3.3) and the ρ̄ update (Section 3.4, 6.3.2).
+#include <new>
+
 #include "solver_internal.hpp"
 
 using namespace qpg;
@@ -458,8 +460,8 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
 
 }  // namespace
 
-void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr,
-                            const std::vector<int32_t>& col, int32_t nrows, int32_t ncols) {
+void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows,
+                            int32_t ncols) {
   TileParams tp{win_cols, s.spmv_tile_nnz > 0 ? s.spmv_tile_nnz : kTileNnz,
                 s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows};
   TilePlan t = make_tiles(rowptr, col, nrows, ncols, tp);
@@ -492,9 +494,11 @@ void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr,
 
 // Values in the plan's SELL order (zero in the padding).
 template <typename T>
-void qpg_solver::place_values(DevPlan& pl, const std::vector<double>& csr_val) {
-  std::vector<T> v(pl.src.size());
-  for (size_t k = 0; k < v.size(); ++k) v[k] = pl.src[k] >= 0 ? (T)csr_val[pl.src[k]] : T(0);
+void qpg_solver::place_values(DevPlan& pl, const hvec<double>& csr_val) {
+  hvec<T> v(pl.src.size());
+  parallel_chunks((int64_t)v.size(), 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
+    for (int64_t k = lo; k < hi; ++k) v[k] = pl.src[k] >= 0 ? (T)csr_val[pl.src[k]] : T(0);
+  });
   T* d = upload(v);
   HIPCHK(hipStreamSynchronize(stream));
   if (std::is_same<T, double>::value)
@@ -566,7 +570,13 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
   auto t0 = std::chrono::steady_clock::now();
   HostProblem H;
   std::string msg;
-  int rc = prepare(P_triu, q, A, l, u, settings, &H, &msg);
+  int rc;
+  try {
+    rc = prepare(P_triu, q, A, l, u, settings, &H, &msg);
+  } catch (const std::bad_alloc&) {
+    rc = QPG_ERR_OOM;
+    msg = "host allocation failed";
+  }
   if (rc) {
     g_setup_error = msg;
     return rc;
@@ -612,8 +622,8 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     while (h->win_cols > 1024 &&
            (size_t)h->win_cols * sizeof(double2) + 1024 > (size_t)lds_max)
       h->win_cols >>= 1;
-    h->build_plan(h->plan_a, H.a_ptr, H.a_col, H.m, H.n);
-    h->build_plan(h->plan_b, H.b_ptr, H.b_col, H.n, H.n + H.m);
+    h->build_plan(h->plan_a, H.a_ptr, H.a_col.data(), H.m, H.n);
+    h->build_plan(h->plan_b, H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
     int maxgrid = std::max(1024, std::max(h->na_items, h->nb_items));
     maxgrid = std::max(maxgrid, std::max(h->plan_a.ncomb, h->plan_b.ncomb));
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
@@ -625,10 +635,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->alloc_prec64(H);
     if (settings->precision == QPG_MIXED) h->alloc_prec32(H);
     for (DevPlan* pl : {&h->plan_a, &h->plan_b}) {
-      const std::vector<double>& v = pl == &h->plan_a ? H.a_val : H.b_val;
+      const hvec<double>& v = pl == &h->plan_a ? H.a_val : H.b_val;
       h->place_values<double>(*pl, v);
       if (settings->precision == QPG_MIXED) h->place_values<float>(*pl, v);
-      pl->src = std::vector<int32_t>();
+      hvec<int32_t>().swap(pl->src);
     }
     for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);
     for (double* v : {h->p64.z, h->p64.y, h->p64.w, h->p64.zt, h->p64.ax}) h->fill(v, h->m, 0.0);
@@ -661,6 +671,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     int code = device_error(nullptr, e);
     delete h;
     return code;
+  } catch (const std::bad_alloc&) {
+    g_setup_error = "host allocation failed";
+    delete h;
+    return QPG_ERR_OOM;
   }
   h->info.scaling_passes = h->scaling_passes;
   h->info.setup_time = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

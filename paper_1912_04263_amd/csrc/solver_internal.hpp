@@ -72,7 +72,7 @@ struct DevPlan {
   int32_t nrows = 0;
   int32_t max_wlen = 0;  // largest staged window, in columns
   int64_t layout[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see qpg_spmv_layout
-  std::vector<int32_t> src;  // host copy of the SELL order (until the values are placed)
+  qpg::hvec<int32_t> src;  // host copy of the SELL order (until the values are placed)
 };
 
 struct LearnedState;  // learned-preconditioner data of a solver (learned.hip)
@@ -127,15 +127,18 @@ struct qpg_solver {
     allocs.push_back(ptr);
     return static_cast<T*>(ptr);
   }
-  template <typename T>
-  T* upload(const std::vector<T>& h) {
+  template <typename T, class A>
+  T* upload(const std::vector<T, A>& h) {
     T* d = alloc<T>(h.size());
     if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream));
     return d;
   }
-  template <typename T, typename S>
-  T* upload_as(const std::vector<S>& h) {
-    std::vector<T> t(h.begin(), h.end());
+  template <typename T, typename S, class A>
+  T* upload_as(const std::vector<S, A>& h) {
+    qpg::hvec<T> t(h.size());
+    qpg::parallel_chunks((int64_t)h.size(), 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
+      for (int64_t k = lo; k < hi; ++k) t[k] = (T)h[k];
+    });
     T* d = upload(t);
     HIPCHK(hipStreamSynchronize(stream));  // t goes out of scope
     return d;
@@ -279,10 +282,10 @@ struct qpg_solver {
   int admm(int k_start, double& rho, double& eps_pcg, int& status, int& fallback_request);
 
   int solve();
-  void build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col,
+  void build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const int32_t* col,
                   int32_t nrows, int32_t ncols);
   template <typename T>
-  void place_values(DevPlan& pl, const std::vector<double>& csr_val);
+  void place_values(DevPlan& pl, const qpg::hvec<double>& csr_val);
   void alloc_prec64(const HostProblem& H);
   void alloc_prec32(const HostProblem& H);
 };

@@ -45,10 +45,37 @@ struct Seg {
   int32_t start, len, slot;
 };
 
+// Column counts over windows (w), eighth-windows (f) and 2^kL2Shift ranges (l2), with the lists
+// of the bins that are non-zero (so that clearing costs what was touched).
+struct Hist {
+  std::vector<int64_t> w, f, l2, tw, tf, t2;
+  Hist(int64_t nw, int64_t nf, int64_t n2) : w(nw, 0), f(nf, 0), l2(n2, 0) {}
+  static void bump(std::vector<int64_t>& cnt, std::vector<int64_t>& touched, int64_t b, int64_t by) {
+    if (cnt[b] == 0) touched.push_back(b);
+    cnt[b] += by;
+  }
+  void add(int32_t c, int32_t sh, int32_t fsh) {
+    bump(w, tw, c >> sh, 1);
+    bump(f, tf, c >> fsh, 1);
+    bump(l2, t2, c >> kL2Shift, 1);
+  }
+  // adds o's counts and clears o
+  void merge(Hist& o) {
+    for (int64_t b : o.tw) bump(w, tw, b, o.w[b]), o.w[b] = 0;
+    for (int64_t b : o.tf) bump(f, tf, b, o.f[b]), o.f[b] = 0;
+    for (int64_t b : o.t2) bump(l2, t2, b, o.l2[b]), o.l2[b] = 0;
+    o.tw.clear();
+    o.tf.clear();
+    o.t2.clear();
+  }
+};
+constexpr int64_t kParHist = 1 << 20;  // runs with more entries are counted in parallel
+constexpr int kHistParts = 16;
+
 }  // namespace
 
-TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_t>& col, int32_t nrows,
-                    int32_t ncols, const TileParams& tp) {
+TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows, int32_t ncols,
+                    const TileParams& tp) {
   TilePlan plan;
   plan.rowslot.assign((size_t)std::max(nrows, 0) + 1, 0);
   if (nrows <= 0) return plan;
@@ -69,19 +96,25 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   const int32_t fsh = std::max(0, sh - 3);  // eight fine bins per window
   const int64_t nwin = ((int64_t)ncols + wcap - 1) >> sh;
   const int64_t nfine = ((int64_t)ncols + (1 << fsh) - 1) >> fsh;
-  std::vector<int64_t> cnt(std::max<int64_t>(nwin, 1), 0), fine(std::max<int64_t>(nfine, 1), 0);
-  std::vector<int64_t> touched_w, touched_f;
-  std::vector<int64_t> cnt2(std::max<int64_t>(((int64_t)ncols >> kL2Shift) + 1, 1), 0), touched_2;
+  Hist hist(std::max<int64_t>(nwin, 1), std::max<int64_t>(nfine, 1),
+            std::max<int64_t>(((int64_t)ncols >> kL2Shift) + 1, 1));
+  std::vector<int64_t>&cnt = hist.w, &fine = hist.f, &cnt2 = hist.l2;
+  std::vector<int64_t>&touched_w = hist.tw, &touched_f = hist.tf, &touched_2 = hist.t2;
+  std::vector<Hist> part;  // per-part histograms of long runs
 
   // first entry of row r at or after column c
   auto seek = [&](int32_t r, int64_t c) {
-    const int32_t* first = col.data() + rowptr[r];
-    const int32_t* last = col.data() + rowptr[r + 1];
-    return (int32_t)(std::lower_bound(first, last, (int32_t)std::min<int64_t>(c, INT32_MAX)) - col.data());
+    const int32_t* first = col + rowptr[r];
+    const int32_t* last = col + rowptr[r + 1];
+    return (int32_t)(std::lower_bound(first, last, (int32_t)std::min<int64_t>(c, INT32_MAX)) - col);
   };
 
   // One tile: segments sorted by length (longest first; ties in slot order), packed into chunks
-  // of 64 lanes in SELL order. Padding repeats the lane's last column with a zero value.
+  // of 64 lanes in SELL order. Only the chunk structure is built here (the lanes' segments in
+  // `lanes`, the array offsets from running counts); the entries are written afterwards, chunk
+  // by chunk in parallel.
+  std::vector<Seg> lanes;  // 64 per chunk; len −1 for an empty lane
+  int64_t n_src = 0, n_c16 = 0, n_c32 = 0;
   auto add_tile = [&](std::vector<Seg>& segs, int32_t wlo, int32_t wlen) {
     if (segs.empty()) return;
     std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
@@ -93,25 +126,13 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
     for (size_t c0 = 0; c0 < segs.size(); c0 += kLanes) {
       const int32_t nseg = (int32_t)std::min<size_t>(kLanes, segs.size() - c0);
       Chunk ch{};
-      ch.base = (int32_t)plan.src.size();
-      ch.cbase = (int32_t)(win ? plan.col16.size() : plan.col32.size());
+      ch.base = (int32_t)n_src;
+      ch.cbase = (int32_t)(win ? n_c16 : n_c32);
       ch.steps = segs[c0].len;
-      ch.seg0 = (int32_t)plan.segslot.size();
-      for (int32_t j = 0; j < kLanes; ++j) plan.segslot.push_back(j < nseg ? segs[c0 + j].slot : -1);
-      for (int32_t s = 0; s < ch.steps; ++s)
-        for (int32_t j = 0; j < kLanes; ++j) {
-          int32_t k = -1, c = win ? wlo : 0;
-          if (j < nseg) {
-            const Seg& g = segs[c0 + j];
-            if (s < g.len) k = g.start + s;
-            if (g.len > 0) c = col[s < g.len ? g.start + s : g.start + g.len - 1];
-          }
-          plan.src.push_back(k);
-          if (win)
-            plan.col16.push_back((uint16_t)(c - wlo));
-          else
-            plan.col32.push_back(c);
-        }
+      ch.seg0 = (int32_t)lanes.size();
+      for (int32_t j = 0; j < kLanes; ++j) lanes.push_back(j < nseg ? segs[c0 + j] : Seg{0, -1, -1});
+      n_src += (int64_t)ch.steps * kLanes;
+      (win ? n_c16 : n_c32) += (int64_t)ch.steps * kLanes;
       plan.chunks.push_back(ch);
     }
     t.nchunk = (int32_t)plan.chunks.size() - t.chunk0;
@@ -200,12 +221,16 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
     const int64_t nnz_g = (int64_t)rowptr[g1] - rowptr[g0];
     const double avg = (double)nnz_g / (double)rows_g;
 
-    // ---- column histogram of the run
-    for (int64_t k = rowptr[g0]; k < rowptr[g1]; ++k) {
-      const int32_t c = col[k];
-      if (cnt[c >> sh]++ == 0) touched_w.push_back(c >> sh);
-      if (fine[c >> fsh]++ == 0) touched_f.push_back(c >> fsh);
-      if (cnt2[c >> kL2Shift]++ == 0) touched_2.push_back(c >> kL2Shift);
+    // ---- column histogram of the run (a long run in parts, counted in parallel and merged)
+    if (nnz_g < kParHist) {
+      for (int64_t k = rowptr[g0]; k < rowptr[g1]; ++k) hist.add(col[k], sh, fsh);
+    } else {
+      if (part.empty()) part.assign(kHistParts, Hist(cnt.size(), fine.size(), cnt2.size()));
+      parallel_chunks(kHistParts, 1, [&](int64_t t, int64_t, int64_t) {
+        const int64_t k0 = rowptr[g0] + nnz_g * t / kHistParts, k1 = rowptr[g0] + nnz_g * (t + 1) / kHistParts;
+        for (int64_t k = k0; k < k1; ++k) part[t].add(col[k], sh, fsh);
+      });
+      for (Hist& h : part) hist.merge(h);
     }
     std::vector<int64_t> S2;  // L2-sized column ranges holding kMinSeg entries per row
     int64_t covS2 = 0;
@@ -343,6 +368,35 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const std::vector<int32_
   }
   flush_plain(true);
   plan.nslot = plan.rowslot[nrows];
+  // ---- the entries in SELL order. Padding repeats the lane's last column with a zero value.
+  plan.segslot.resize(lanes.size());
+  plan.src.resize((size_t)n_src);
+  plan.col16.resize((size_t)n_c16);
+  plan.col32.resize((size_t)n_c32);
+  parallel_chunks((int64_t)plan.tiles.size(), 8, [&](int64_t, int64_t t0, int64_t t1) {
+    for (int64_t ti = t0; ti < t1; ++ti) {
+      const Tile& t = plan.tiles[ti];
+      const bool win = t.wlen > 0;
+      for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci) {
+        const Chunk& ch = plan.chunks[ci];
+        const Seg* g = &lanes[ch.seg0];
+        int32_t* src = &plan.src[ch.base];
+        for (int32_t j = 0; j < kLanes; ++j) plan.segslot[ch.seg0 + j] = g[j].slot;
+        for (int32_t q = 0; q < ch.steps; ++q) {
+          for (int32_t j = 0; j < kLanes; ++j) {
+            const int32_t len = g[j].len;
+            const int32_t k = q < len ? g[j].start + q : -1;
+            const int32_t c = len > 0 ? col[q < len ? g[j].start + q : g[j].start + len - 1] : (win ? t.wlo : 0);
+            src[(size_t)q * kLanes + j] = k;
+            if (win)
+              plan.col16[(size_t)ch.cbase + (size_t)q * kLanes + j] = (uint16_t)(c - t.wlo);
+            else
+              plan.col32[(size_t)ch.cbase + (size_t)q * kLanes + j] = c;
+          }
+        }
+      }
+    }
+  });
   // combine work: lanes per row ≈ a quarter of the row's slots (1..64), the largest over the
   // rows of one workgroup; a workgroup of kBlock threads takes one pass of consecutive rows
   auto lg_of = [&](int32_t q) {

@@ -46,7 +46,7 @@ int main(int argc, char** argv) {
   for (int r = 0; r < nrows; ++r)
     for (int k = rp[r]; k < rp[r + 1]; ++k) (col[k] < nsplit ? ref1 : ref2)[r] += val[k] * x[col[k]];
   for (int wcap = wcap0; wcap <= 2 * wcap0; wcap *= 2) {
-    const TilePlan p = make_tiles(rp, col, nrows, ncols, TileParams{wcap, tile_nnz, plain_nnz, kTileMaxRows});
+    const TilePlan p = make_tiles(rp, col.data(), nrows, ncols, TileParams{wcap, tile_nnz, plain_nnz, kTileMaxRows});
     if ((int)p.rowslot.size() != nrows + 1 || p.rowslot[0] != 0 || p.rowslot[nrows] != p.nslot) FAIL("row slots");
     for (int r = 0; r < nrows; ++r)
       if (p.rowslot[r + 1] < p.rowslot[r]) FAIL("row slots decrease");

@@ -23,7 +23,8 @@ CSRC = os.path.join(ROOT, "paper_1912_04263_amd", "csrc")
 def checker(tmpdir):
     exe = os.path.join(tmpdir, "plan_check")
     subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "native", "plan_check.cpp"),
-                    os.path.join(CSRC, "tiles.cpp"), "-o", exe], check=True)
+                    os.path.join(CSRC, "tiles.cpp"), os.path.join(CSRC, "host_parallel.cpp"), "-lpthread", "-o", exe],
+                   check=True)
     return exe
 
 
