@@ -6,7 +6,9 @@ Each iteration, on the Ruiz-scaled problem (Algorithm 2):
   3. x ← αx̃ + (1−α)x
   4. z ← Π_[l̄,ū](αz̃ + (1−α)z + R⁻¹y)
   5. y ← y + R(αz̃ + (1−α)z − z_new)
-and stops when the unscaled residuals meet the relative test of Section 3.1.
+and stops when the unscaled residuals meet the relative test of Section 3.1, or when the
+iterate differences δx = x^k − x^{k−1}, δy = y^k − y^{k−1} certify infeasibility (Section 3,
+Section 3.1; ``infeasibility``).
 
 ``linsys="pcg"`` replaces the direct solve by the route of Section 6.3: R = ρ̄I, the reduced
 system (eq. kkt_red_sc) solved with Algorithm 3 (``oracle.pcg``) to a tight relative tolerance,
@@ -45,6 +47,46 @@ RHO_MIN, RHO_MAX = 1e-6, 1e6
 INF = 1e20
 
 
+def infeasibility(dx, dy, P_full, q, A, l, u, eps_pinf, eps_dinf, tiny=1e-30):
+    """Infeasibility tests of Section 3.1 on the unscaled differences dx (n) and dy (m).
+
+    Primal (certificate conditions of Section 2.1, Aᵀȳ = 0 and lᵀȳ₋ + uᵀȳ₊ < 0): dy is first
+    projected so that no term of the support function is infinite (dy_i ≤ 0 where u_i = +∞,
+    dy_i ≥ 0 where l_i = −∞); then ‖Aᵀdy‖∞ ≤ ε_pinf‖dy‖∞ and lᵀdy₋ + uᵀdy₊ < −ε_pinf‖dy‖∞,
+    the infinite bounds contributing nothing.
+    Dual (conditions Px̄ = 0, qᵀx̄ < 0 and the sign pattern of Ax̄): ‖P dx‖∞ ≤ ε_dinf‖dx‖∞,
+    qᵀdx < −ε_dinf‖dx‖∞, and (A dx)_i within ±ε_dinf‖dx‖∞ for finite l_i and u_i, ≥ −ε_dinf‖dx‖∞
+    for u_i = +∞, ≤ ε_dinf‖dx‖∞ for l_i = −∞.
+    The tests are the paper's, with every tolerance relative to ‖δ‖∞ (the paper's are absolute;
+    normalising makes them independent of how fast the iterates diverge). A test whose tolerance
+    is 0 is skipped. Returns (status, certificate normalised to ‖·‖∞ = 1) or None.
+    """
+    l_inf = l <= -INF
+    u_inf = u >= INF
+    if eps_pinf > 0 and dy.size:
+        d = np.where(u_inf, np.minimum(dy, 0.0), dy)
+        d = np.where(l_inf, np.maximum(d, 0.0), d)
+        nrm = float(np.max(np.abs(d)))
+        if nrm > tiny:
+            atd = A.T @ d
+            support = float(np.sum(np.where(u_inf, 0.0, u) * np.maximum(d, 0.0))
+                            + np.sum(np.where(l_inf, 0.0, l) * np.minimum(d, 0.0)))
+            if float(np.max(np.abs(atd))) <= eps_pinf * nrm and support < -eps_pinf * nrm:
+                return "primal_infeasible", d / nrm
+    if eps_dinf > 0:
+        nrm = float(np.max(np.abs(dx)))
+        if nrm > tiny:
+            tol = eps_dinf * nrm
+            if float(np.max(np.abs(P_full @ dx))) <= tol and float(q @ dx) < -tol:
+                adx = A @ dx
+                ok = np.where(l_inf & u_inf, True,
+                              np.where(u_inf, adx >= -tol,
+                                       np.where(l_inf, adx <= tol, np.abs(adx) <= tol)))
+                if bool(np.all(ok)):
+                    return "dual_infeasible", dx / nrm
+    return None
+
+
 @dataclasses.dataclass
 class AdmmResult:
     x: np.ndarray
@@ -61,6 +103,7 @@ class AdmmResult:
     scaling: tuple
     factor_time: float = 0.0
     iter_time: float = 0.0
+    certificate: np.ndarray | None = None  # normalised δy (primal) or δx (dual infeasibility)
 
 
 def kkt_matrix(Pb, Ab, sigma, rvec):
@@ -141,7 +184,7 @@ def rho_vector(l, u, rho_bar, mode):
 def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, eps_rel=1e-9,
           max_iter=20000, scaling_iters=10, r_mode="scalar", adaptive_rho=True, rho_interval=100,
           check_every=1, record=0, x0=None, z0=None, y0=None, linsys="direct",
-          pcg_tol=1e-12) -> AdmmResult:
+          pcg_tol=1e-12, eps_pinf=1e-4, eps_dinf=1e-4) -> AdmmResult:
     import time
 
     P_full = sp.csr_matrix(P_full, dtype=np.float64)
@@ -183,7 +226,9 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
     it = 0
     pr = dr = np.inf
     t1 = time.perf_counter()
+    cert = None
     for it in range(1, max_iter + 1):
+        x_prev, y_prev = x, y
         x, z, y = admm_step(kkt, qb, lb, ub, rvec, sigma, alpha, x, z, y)
         if it <= record:
             trace.append((D * x, z / E, E * y / c))
@@ -206,6 +251,12 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
         eps_d = eps_abs + eps_rel * max(nPx, nAty, nq)
         if pr <= eps_p and dr <= eps_d:
             status = "solved"
+            break
+        # unscaled differences: δx = D δx̄, δy = E δȳ / c
+        found = infeasibility(D * (x - x_prev), E * (y - y_prev) / c, P_full, q, A, l, u,
+                              eps_pinf, eps_dinf)
+        if found is not None:
+            status, cert = found
             break
         if adaptive_rho and it - last_update >= rho_interval:
             num = float(np.max(np.abs(rp_s))) / max(float(np.max(np.abs(Ax))) if m else 0.0,
@@ -230,4 +281,4 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
     zs = z / E
     obj = 0.5 * float(xs @ (P_full @ xs)) + float(q @ xs)
     return AdmmResult(xs, ys, zs, obj, it, status, pr, dr, rho_bar, rho_updates, trace,
-                      (D, E, c), factor_time, iter_time)
+                      (D, E, c), factor_time, iter_time, cert)

@@ -175,6 +175,48 @@ def svm_qp(n_points: int, n_feat: int, dens: float, seed: int, lam: float = 1.0)
     return _finish("svm", P, q, A, l, u, dict(seed=seed, n_points=N, n_feat=n, dens=dens, lam=lam))
 
 
+def primal_infeasible_qp(n: int, m: int, dens: float, seed: int) -> QP:
+    """Random class whose longest row a of A is moved to the end and doubled under disjoint
+    bounds, a·x ∈ [1, 2] (row m − 1) and a·x ∈ [3, 4] (row m), so that no x is feasible; every
+    fourth other row has u = +∞. With m < n the rows of A other than the copy are independent
+    (almost surely), so Aᵀy = 0 (Section 2.1) forces y onto the two copies:
+    y ∝ e_{m−1} − e_m, the only certificate direction."""
+    base = random_qp(n, m, dens, dens, seed)
+    A = sp.csr_matrix(base.A)
+    r = int(np.argmax(np.diff(A.indptr)))  # the longest row (non-empty)
+    rest = np.delete(np.arange(m), r)
+    A2 = sp.vstack([A[rest], A[r], A[r]]).tocsr()
+    l = np.concatenate([base.l[rest], [1.0, 3.0]])
+    u = np.concatenate([base.u[rest], [2.0, 4.0]])
+    u[:m - 1:4] = np.inf
+    return _finish("primal_infeasible", base.P_full(), base.q, A2, l, u,
+                   dict(seed=seed, dens=dens, rows=(m - 1, m)))
+
+
+def dual_infeasible_qp(n: int, m: int, dens: float, seed: int) -> QP:
+    """Random class in which variable j (drawn) appears neither in P nor in A, except in one last
+    row x_j ≥ 0 (u = +∞), and has q_j = −1: the objective decreases without bound along e_j
+    (Pe_j = 0, qᵀe_j < 0, Ae_j ≥ 0 on that row), and P is positive definite on the other
+    variables, so e_j is the only certificate direction (Section 2.1)."""
+    base = random_qp(n, m, dens, dens, seed)
+    rng = np.random.default_rng(seed + 1)
+    j = int(rng.integers(n))
+    keep = np.ones(n)
+    keep[j] = 0.0
+    Dk = sp.diags(keep)
+    P = (Dk @ base.P_full() @ Dk).tocsr()
+    P.eliminate_zeros()
+    A = (sp.csr_matrix(base.A) @ Dk).tocsr()
+    A.eliminate_zeros()
+    ej = sp.csr_matrix(([1.0], ([0], [j])), shape=(1, n))
+    A2 = sp.vstack([A, ej]).tocsr()
+    q = base.q.copy()
+    q[j] = -1.0
+    l = np.concatenate([base.l, [0.0]])
+    u = np.concatenate([base.u, [np.inf]])
+    return _finish("dual_infeasible", P, q, A2, l, u, dict(seed=seed, dens=dens, var=j))
+
+
 # The five benchmark workloads and their scaled-down parity variants.
 # Instance j of workload i uses seed 1000·i + j.
 WORKLOADS = {

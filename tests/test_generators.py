@@ -56,3 +56,18 @@ def test_svm_labels_and_means():
     # rows are diag(b)·Ad, whose entries then all have mean +1/n_feat
     assert Ad.data.mean() == pytest.approx(1.0 / 100, rel=0.1)
     assert np.all(p.u[:N] == -1.0) and np.all(p.l[N:] == 0.0)
+
+
+def test_infeasible_generators_structure():
+    p = pr.primal_infeasible_qp(60, 40, 0.15, 7)
+    i, j = p.meta["rows"]
+    A = p.A.tocsr()
+    assert (A[i] != A[j]).nnz == 0 and A[i].nnz > 0
+    assert (p.l[i], p.u[i], p.l[j], p.u[j]) == (1.0, 2.0, 3.0, 4.0)
+    assert np.linalg.matrix_rank(A.toarray()) == p.m - 1  # independent rows apart from the copy
+    d = pr.dual_infeasible_qp(60, 80, 0.15, 8)
+    v = d.meta["var"]
+    assert d.P_full()[:, v].nnz == 0 and d.q[v] == -1.0
+    col = d.A.tocsc()[:, v]
+    assert col.nnz == 1 and col.indices[0] == d.m - 1 and d.l[-1] == 0.0 and d.u[-1] == np.inf
+    assert np.linalg.eigvalsh(np.delete(np.delete(d.P_full().toarray(), v, 0), v, 1)).min() > 0

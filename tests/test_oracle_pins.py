@@ -386,3 +386,75 @@ def test_bruteforce_pin_has_teeth(monkeypatch, kind):
     with np.errstate(all="ignore"):
         r = _solve(P, q, A, l, u, max_iter=3000)
     assert not np.all(np.abs(r.x - xb) <= 1e-7 * (1 + np.abs(xb).max()))
+
+
+# ---------------------------------------------------------------- infeasibility (Section 3.1)
+def test_primal_infeasible_closed_form():
+    # x ≥ 1 and x ≤ 0: Aᵀȳ = 0 and lᵀȳ₋ + uᵀȳ₊ < 0 leave only ȳ ∝ (−1, 1) (Section 2.1)
+    r = _solve(np.zeros((1, 1)), np.array([0.0]), np.array([[1.0], [1.0]]),
+               np.array([1.0, -np.inf]), np.array([np.inf, 0.0]))
+    assert r.status == "primal_infeasible"
+    np.testing.assert_allclose(r.certificate, [-1.0, 1.0], atol=1e-3)
+
+
+def test_primal_infeasible_contradicting_equalities():
+    # x₁ + x₂ = 1 and x₁ + x₂ = 2: ȳ ∝ (1, −1), support 1 − 2 < 0
+    r = _solve(np.eye(2), np.zeros(2), np.array([[1.0, 1.0], [1.0, 1.0]]), np.array([1.0, 2.0]),
+               np.array([1.0, 2.0]))
+    assert r.status == "primal_infeasible"
+    np.testing.assert_allclose(r.certificate, [1.0, -1.0], atol=1e-3)
+
+
+def test_dual_infeasible_closed_form():
+    # min ½x₁² − x₂ s.t. x₂ ≥ 0: Px̄ = 0 and qᵀx̄ < 0 leave only x̄ ∝ (0, 1)
+    r = _solve(np.diag([1.0, 0.0]), np.array([0.0, -1.0]), np.array([[0.0, 1.0]]),
+               np.array([0.0]), np.array([np.inf]))
+    assert r.status == "dual_infeasible"
+    np.testing.assert_allclose(r.certificate, [0.0, 1.0], atol=1e-3)
+
+
+def test_dual_infeasible_lp_with_equality():
+    # min −x₁ − x₂ s.t. x₁ − x₂ = 0, x ≥ 0: unbounded along (1, 1) (equality row stays at 0)
+    A = np.array([[1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])
+    r = _solve(np.zeros((2, 2)), np.array([-1.0, -1.0]), A, np.array([0.0, 0.0, 0.0]),
+               np.array([0.0, np.inf, np.inf]))
+    assert r.status == "dual_infeasible"
+    np.testing.assert_allclose(r.certificate, [1.0, 1.0], atol=1e-3)
+
+
+def test_feasible_lp_is_not_flagged():
+    # min x s.t. x ≥ 0 (P = 0): bounded, solution 0
+    r = _solve(np.zeros((1, 1)), np.array([1.0]), np.array([[1.0]]), np.array([0.0]), np.array([np.inf]),
+               eps_abs=1e-9, eps_rel=1e-9)
+    assert r.status == "solved"
+    assert abs(r.x[0]) < 1e-7
+
+
+@pytest.mark.parametrize("kind", ["primal", "dual"])
+def test_generated_infeasible_instances(kind):
+    from paper_1912_04263_amd import problems as pr
+    qp = (pr.primal_infeasible_qp(60, 40, 0.15, 7) if kind == "primal"
+          else pr.dual_infeasible_qp(60, 80, 0.15, 8))
+    r = _solve(qp.P_full(), qp.q, qp.A, qp.l, qp.u, check_every=5, max_iter=5000)
+    assert r.status == kind + "_infeasible"
+    if kind == "primal":
+        want = np.zeros(qp.m)
+        want[list(qp.meta["rows"])] = [1.0, -1.0]
+    else:
+        want = np.zeros(qp.n)
+        want[qp.meta["var"]] = 1.0
+    np.testing.assert_allclose(r.certificate, want, atol=1e-2)
+
+
+@pytest.mark.parametrize("kind", ["primal", "dual"])
+def test_infeasibility_pin_has_teeth(monkeypatch, kind):
+    # differences taken the wrong way round (x^{k−1} − x^k) must break the pins
+    orig = admm.infeasibility
+
+    def flipped(dx, dy, *a, **k):
+        return orig(-dx, -dy, *a, **k)
+
+    monkeypatch.setattr(admm, "infeasibility", flipped)
+    pin = test_primal_infeasible_closed_form if kind == "primal" else test_dual_infeasible_closed_form
+    with pytest.raises(AssertionError):
+        pin()
