@@ -172,7 +172,8 @@ def main():
     last = infos[-1] if infos else s.info()
     admm_iters = sum(i.iter for i in infos)
     log(f"[bench] {args.precision}/{args.precond}: {last.status} in {last.iter} ADMM / {last.pcg_iter_total} PCG "
-        f"iterations, solve {elapsed / steps * 1e3:.2f} ms, setup {setup_s:.2f} s, obj {last.obj_val:.10g}")
+        f"iterations ({last.infeas_checks} infeasibility checks), solve {elapsed / steps * 1e3:.2f} ms, "
+        f"setup {setup_s:.2f} s, obj {last.obj_val:.10g}")
 
     prec_id = qpg.QPG_MIXED if args.precision == "mixed" else qpg.QPG_FP64
     sz = 4 if args.precision == "mixed" else 8
@@ -219,14 +220,15 @@ def main():
             last2 = inf2[-1]
             v = {"precision": prec, "precond": pc, "tts_ms": el2 / len(inf2) * 1e3,
                  "admm_iter_per_s": sum(i.iter for i in inf2) / el2, "admm_iters": last2.iter,
-                 "pcg_iters": last2.pcg_iter_total, "status": last2.status, "obj": last2.obj_val,
+                 "pcg_iters": last2.pcg_iter_total, "infeas_checks": last2.infeas_checks,
+                 "status": last2.status, "obj": last2.obj_val,
                  "precision_used": last2.precision_used, "precond_used": last2.precond_used,
                  "precond_trials_won": [last2.precond_learned_chosen, last2.precond_trials],
                  "setup_s": su2,
                  "obj_rel_diff_vs_main": abs(last2.obj_val - last.obj_val) / max(1.0, abs(last.obj_val))}
             variants.append(v)
             log(f"[bench] {prec}/{pc}: {v['status']} tts {v['tts_ms']:.2f} ms, {v['admm_iters']} ADMM / "
-                f"{v['pcg_iters']} PCG, obj {v['obj']:.10g}")
+                f"{v['pcg_iters']} PCG, {v['infeas_checks']} infeasibility checks, obj {v['obj']:.10g}")
             s2.close()
 
     ref = None
@@ -268,6 +270,7 @@ def main():
         "status": last.status,
         "admm_iters": last.iter,
         "pcg_iters": last.pcg_iter_total,
+        "infeas_checks": last.infeas_checks,
         "obj": last.obj_val,
         "kernels": kernels,
         "roofline": roofline,

@@ -42,6 +42,8 @@ extern "C" {
 #define QPG_SOLVED 1
 #define QPG_MAX_ITER_REACHED 2
 #define QPG_NUMERICAL_ERROR 3 /* PCG breakdown (pᵀKp ≤ 0 or NaN) in every precision */
+#define QPG_PRIMAL_INFEASIBLE 4 /* δy certifies Aᵀȳ = 0, lᵀȳ₋ + uᵀȳ₊ < 0 (Section 2.1, 3.1) */
+#define QPG_DUAL_INFEASIBLE 5   /* δx certifies Px̄ = 0, qᵀx̄ < 0, sign pattern of Ax̄ (Section 2.1, 3.1) */
 
 /* Arithmetic of the iteration. */
 #define QPG_FP64 0  /* matrices, vectors and reductions in double */
@@ -101,6 +103,10 @@ typedef struct {
   int32_t spmv_tile_nnz;  /* SpMV work-list granularity: matrix entries per workgroup when it stages
                              a gather window in LDS; default 32768, 0 = default */
   int32_t spmv_plain_nnz; /* the same for workgroups without a window; default 8192, 0 = default */
+  double eps_prim_inf;    /* ε_pinf of the primal infeasibility test (Section 3.1), relative to
+                             ‖δy‖∞; default 1e-4; 0 disables the test */
+  double eps_dual_inf;    /* ε_dinf of the dual infeasibility test, relative to ‖δx‖∞; default
+                             1e-4; 0 disables it (both 0: no infeasibility passes at all) */
 } qpg_settings;
 
 typedef struct {
@@ -122,6 +128,8 @@ typedef struct {
   int32_t precond_trials;  /* learned-vs-Jacobi trials run in the last solve */
   int32_t precond_learned_chosen; /* trials won by the learned preconditioner */
   int32_t precond_switches; /* runtime switches from learned to Jacobi (capped or broken-down PCG) */
+  int32_t infeas_checks;   /* checks that ran the infeasibility passes: those after two checks in a
+                              row without a 1% gain in the worse normalised residual */
 } qpg_info;
 
 typedef struct qpg_solver qpg_solver;
@@ -139,9 +147,22 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
 
 /* Run Algorithm 1 from x = z = y = 0, x̃ = 0 and the initial ρ̄ until the unscaled residuals meet
  * eps_prim = eps_abs + eps_rel·max(‖Ax‖∞, ‖z‖∞), eps_dual = eps_abs + eps_rel·max(‖Px‖∞, ‖Aᵀy‖∞,
- * ‖q‖∞) (Section 3.1, checked every check_every iterations) or max_iter is reached. The status
- * is in qpg_info; reaching max_iter is not an error. */
+ * ‖q‖∞) (Section 3.1, checked every check_every iterations), or the differences of the checked
+ * step certify primal or dual infeasibility (Section 3.1; tested, with two extra SpMV passes, at
+ * the checks that follow two checks in a row without a 1% gain in the worse normalised residual),
+ * or max_iter is reached. After ten such checks the PCG tolerance is divided by 10 at every second
+ * check (a stall guard, not in the paper: infeasible problems keep the residuals, and with them
+ * the tolerance of Section 6.3.3, large). The status is in qpg_info; reaching max_iter or
+ * detecting infeasibility is not an error. */
 int qpg_solve(qpg_solver* h);
+
+/* Infeasibility certificate of the last solve (status QPG_PRIMAL_INFEASIBLE or
+ * QPG_DUAL_INFEASIBLE): the unscaled iterate differences δx = x^k − x^{k−1} (n) and δy =
+ * y^k − y^{k−1} (m) of the step that passed the test (Section 3), δy projected so that its
+ * support function lᵀδy₋ + uᵀδy₊ has no infinite term, each divided by its ∞-norm. δy is the
+ * certificate of primal infeasibility, δx that of dual infeasibility. Either pointer may be NULL.
+ * QPG_ERR_STATE when the last solve did not end infeasible. */
+int qpg_get_certificate(const qpg_solver* h, double* dx, double* dy);
 
 /* Copy the unscaled iterates of the last solve: x (n), y (m), z (m). */
 int qpg_get_x(const qpg_solver* h, double* x);

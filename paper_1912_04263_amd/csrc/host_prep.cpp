@@ -177,7 +177,8 @@ int validate_settings(const qpg_settings* s, std::string* msg) {
             (s->precond == QPG_PRECOND_JACOBI ||
              (s->precond == QPG_PRECOND_LEARNED && s->precond_weights != nullptr)) &&
             (s->precond_trial == 0 || s->precond_trial == 1) && s->device >= 0 &&
-            s->spmv_tile_nnz >= 0 && s->spmv_plain_nnz >= 0;
+            s->spmv_tile_nnz >= 0 && s->spmv_plain_nnz >= 0 && s->eps_prim_inf >= 0 &&
+            s->eps_dual_inf >= 0 && std::isfinite(s->eps_prim_inf) && std::isfinite(s->eps_dual_inf);
   if (!ok) {
     *msg = "settings: value out of range";
     return QPG_ERR_ARG;

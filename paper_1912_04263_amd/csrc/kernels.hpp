@@ -37,7 +37,7 @@ struct DevState {
   int32_t maxit;      // PCG iteration cap
   uint32_t pad1;
   uint32_t pad2;
-  double norms[16];   // residual-check outputs (see OpRPrim / OpRDual)
+  double norms[24];   // residual-check outputs (OpRPrim / OpRDual: 0..13, OpInfeasA/B: 16..22)
 };
 
 struct RedBuf {
@@ -453,6 +453,8 @@ struct OpKp {
 //   side task: x ← αx̃ + (1−α)x, and the pairs (x̃, 0).
 // With CHECK, the primal residual r̄_p = Āx − z⁺ and its norms are reduced as well:
 // slots ‖r̄_p‖, ‖E⁻¹r̄_p‖, ‖Āx‖, ‖E⁻¹Āx‖, ‖z‖, ‖E⁻¹z‖ → norms[0..5].
+// With dxy set, the iterate differences of this step, δx̄ = x⁺ − x (n) and δȳ = y⁺ − y (m), are
+// written to it for the infeasibility tests (Section 3).
 template <typename T, bool CHECK>
 struct OpUpdate {
   QPG_ONE_PRODUCT
@@ -471,6 +473,7 @@ struct OpUpdate {
   T alpha, rho, rho_inv;
   int n;
   DevState* st;
+  T* dxy;  // null, or n + m differences (δx̄, δȳ)
   __device__ T gather(int c) const { return xt[c]; }
   __device__ void epilogue(int i, T s1, T, T, double* red) const {
     const T zi = z[i], yi = y[i];
@@ -479,6 +482,7 @@ struct OpUpdate {
     zn = zn < lb[i] ? lb[i] : zn;
     zn = zn > ub[i] ? ub[i] : zn;
     const T yn = yi + rho * (v - zn);
+    if (dxy) dxy[n + i] = yn - yi;
     y[i] = yn;
     z[i] = zn;
     zt[i] = s1;
@@ -500,8 +504,10 @@ struct OpUpdate {
   }
   __device__ void side() const {  // any workgroup size
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-      const T xti = xt[i];
-      x[i] = alpha * xti + (T(1) - alpha) * x[i];
+      const T xti = xt[i], xi = x[i];
+      const T xn = alpha * xti + (T(1) - alpha) * xi;
+      x[i] = xn;
+      if (dxy) dxy[i] = xn - xi;
       gp[i] = pair_t<T>{xti, T(0)};
     }
   }
@@ -567,6 +573,74 @@ struct OpRDual {
   }
   __device__ void operator()(const double* t) const {
     for (int s = 0; s < 8; ++s) st->norms[6 + s] = t[s];
+  }
+};
+
+// Infeasibility tests (Section 3.1) on the differences δx̄, δȳ of the last ADMM step, in two
+// passes. Bounds with |l_i|, |u_i| ≥ kInf/2 (unscaled) are infinite.
+// Pass 1 over the rows of Ā, gathering δx̄: with v = E⁻¹(Āδx̄) = Aδx,
+//   norms[16] = max_i of v's violation of the sign pattern: |v_i| where l_i and u_i are finite,
+//               max(−v_i, 0) where only u_i = +∞, max(v_i, 0) where only l_i = −∞, 0 where both;
+// and δȳ is projected so that the support function has no infinite term (δȳ_i ≤ 0 where
+// u_i = +∞, ≥ 0 where l_i = −∞) and written back, then
+//   norms[17] = ‖Eδȳ‖∞,  norms[18] = ūᵀ(δȳ)₊ + l̄ᵀ(δȳ)₋ (the infinite terms being zero).
+// With δy = Eδȳ/c the unscaled tests read ‖Aᵀδy‖ ≤ ε‖δy‖ and uᵀδy₊ + lᵀδy₋ < −ε‖δy‖; c cancels.
+template <typename T>
+struct OpInfeasA {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 3;
+  static constexpr unsigned MAXMASK = 0x3u;
+  T* dxy;
+  const T* lb;
+  const T* ub;
+  const double* einv;
+  int n;
+  DevState* st;
+  __device__ T gather(int c) const { return dxy[c]; }
+  __device__ void epilogue(int i, T s1, T, T, double* red) const {
+    const double e = einv[i];
+    const double lo = (double)lb[i], up = (double)ub[i];
+    const bool linf = lo * e <= -0.5 * kInf, uinf = up * e >= 0.5 * kInf;
+    const double v = (double)s1 * e;
+    const double viol = linf ? (uinf ? 0.0 : nmax(v, 0.0)) : (uinf ? nmax(-v, 0.0) : fabs(v));
+    T d = dxy[n + i];
+    if (uinf) d = d < T(0) ? d : T(0);
+    if (linf) d = d > T(0) ? d : T(0);
+    dxy[n + i] = d;
+    const double dd = (double)d;
+    red[0] = nmax(red[0], viol);
+    red[1] = nmax(red[1], fabs(dd / e));
+    red[2] += (dd > 0.0 ? up * dd : 0.0) + (dd < 0.0 ? lo * dd : 0.0);
+  }
+  __device__ void operator()(const double* t) const {
+    for (int s = 0; s < 3; ++s) st->norms[16 + s] = t[s];
+  }
+};
+
+// Pass 2 over B = [P̄ | Āᵀ], gathering [δx̄; projected δȳ]:
+//   norms[19] = ‖D⁻¹P̄δx̄‖∞ = c‖Pδx‖∞,  norms[20] = ‖D⁻¹Āᵀδȳ‖∞ = ‖Aᵀ(Eδȳ)‖∞,
+//   norms[21] = ‖Dδx̄‖∞ = ‖δx‖∞,        norms[22] = q̄ᵀδx̄ = c·qᵀδx.
+template <typename T>
+struct OpInfeasB {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 4;
+  static constexpr unsigned MAXMASK = 0x7u;
+  const T* dxy;
+  const T* qb;
+  const double* dinv_scale;
+  DevState* st;
+  __device__ T gather(int c) const { return dxy[c]; }
+  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+    const double d = dinv_scale[i], dx = (double)dxy[i];
+    red[0] = nmax(red[0], fabs((double)s1 * d));
+    red[1] = nmax(red[1], fabs((double)s2 * d));
+    red[2] = nmax(red[2], fabs(dx / d));
+    red[3] += (double)qb[i] * dx;
+  }
+  __device__ void operator()(const double* t) const {
+    for (int s = 0; s < 4; ++s) st->norms[19 + s] = t[s];
   }
 };
 

@@ -31,6 +31,7 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.zt = alloc<double>(m);
   V.ax = alloc<double>(m);
   V.gp = alloc<double2>((size_t)n + m);
+  V.dxy = alloc<double>((size_t)n + m);
   V.ready = true;
 }
 
@@ -53,7 +54,40 @@ void qpg_solver::alloc_prec32(const HostProblem& H) {
   V.z = alloc<float>(m);
   V.zt = alloc<float>(m);
   V.gp = alloc<float2>((size_t)n + m);
+  V.dxy = alloc<float>((size_t)n + m);
   V.ready = true;
+}
+
+// Infeasibility tests of Section 3.1 on the norms of OpInfeasA / OpInfeasB, every tolerance
+// relative to the ∞-norm of the difference tested (see the oracle's reading): primal first.
+int qpg_solver::infeasibility_status() const {
+  const double* nm = st_host->norms;
+  const double tiny = 1e-30;
+  const double ny = nm[17];
+  if (s.eps_prim_inf > 0 && ny > tiny && nm[20] <= s.eps_prim_inf * ny && nm[18] < -s.eps_prim_inf * ny)
+    return QPG_PRIMAL_INFEASIBLE;
+  const double nx = nm[21], tol = s.eps_dual_inf * nx;
+  if (s.eps_dual_inf > 0 && nx > tiny && nm[19] / c <= tol && nm[22] / c < -tol && nm[16] <= tol)
+    return QPG_DUAL_INFEASIBLE;
+  return QPG_UNSOLVED;
+}
+
+// The certificate directions: δx = Dδx̄ and δy ∝ Eδȳ, each scaled to ‖·‖∞ = 1.
+template <typename T>
+void qpg_solver::keep_certificate() {
+  std::vector<T> d((size_t)n + m);
+  HIPCHK(hipMemcpyAsync(d.data(), P<T>().dxy, d.size() * sizeof(T), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  cert_x.assign(n, 0.0);
+  cert_y.assign(m, 0.0);
+  double nx = 0.0, ny = 0.0;
+  for (int i = 0; i < n; ++i) nx = std::max(nx, std::fabs(cert_x[i] = D[i] * (double)d[i]));
+  for (int i = 0; i < m; ++i) ny = std::max(ny, std::fabs(cert_y[i] = E[i] * (double)d[n + i]));
+  if (nx > 0)
+    for (double& v : cert_x) v /= nx;
+  if (ny > 0)
+    for (double& v : cert_y) v /= ny;
+  cert_valid = true;
 }
 
 // ADMM iterations k_start.. in precision T. Returns the last iteration index. status is set
@@ -70,6 +104,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // hit the cap, ends with a smaller residual); a capped learned solve falls back to Jacobi.
   // A new trial is run only when ρ̄ has moved by more than a factor 2 since the last one, and
   // trials stop for the rest of the solve after the learned diagonal has lost two in a row.
+  const bool infeas = s.eps_prim_inf > 0 || s.eps_dual_inf > 0;
   const bool learned_ok = (s.precond == QPG_PRECOND_LEARNED);
   bool trial = learned_ok && s.precond_trial;
   bool use_learned = learned_ok && !s.precond_trial;
@@ -82,6 +117,12 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   int cap_streak = 0;
   double best_ratio = INFINITY;
   int since_best = 0;
+  double tighten = 1.0;  // stall guard on the PCG tolerance (see below)
+  // The infeasibility passes (Section 3.1) cost an Ā and a B pass per check. They run once the
+  // residuals have stopped improving (kInfeasAfter checks without a 1% gain), which is where an
+  // infeasible problem ends up; on a converging problem they would only add cost.
+  constexpr int kInfeasAfter = 2;
+  bool armed = false;
   int k = k_start;
   for (; k <= s.max_iter; ++k) {
     // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
@@ -142,13 +183,14 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     // Āx tracked (FP64) the primal residual of a check iteration comes out of the same pass
     const bool check = (k % s.check_every == 0 || k == s.max_iter);
     T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
+    T* dxy = (check && infeas && armed) ? V.dxy : nullptr;  // δx̄, δȳ of this step (Section 3.1)
     if (check && ax) {
       OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
-                           (T)rho, (T)(1.0 / rho), n, st};
+                           (T)rho, (T)(1.0 / rho), n, st, dxy};
       finalize(up, spmv_A<T>(up));
     } else {
       spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
-                                   (T)alpha, (T)rho, (T)(1.0 / rho), n, st});
+                                   (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy});
     }
     // (a9) residuals and termination every check_every iterations
     if (check) {
@@ -185,6 +227,28 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         last_precond_learned = use_learned;
         return k;
       }
+      // infeasibility certificates from the differences of this step (Section 3, 3.1)
+      if (dxy) {
+        info.infeas_checks++;
+        OpInfeasA<T> ia{V.dxy, V.lb, V.ub, escale, n, st};
+        finalize(ia, spmv_A<T>(ia));
+        OpInfeasB<T> ib{V.dxy, V.qb, dscale, st};
+        finalize(ib, spmv_B<T>(ib));
+        sync_state();
+        const int inf = infeasibility_status();
+        if (s.verbose) {
+          const double* q = st_host->norms;
+          std::fprintf(stderr, "qpg        pinf: |Atdy|/|dy| %.2e  support/|dy| %.2e   dinf: |Pdx|/|dx| %.2e  "
+                       "qdx/|dx| %.2e  Adx viol/|dx| %.2e\n", q[20] / q[17], q[18] / q[17], q[19] / c / q[21],
+                       q[22] / c / q[21], q[16] / q[21]);
+        }
+        if (inf != QPG_UNSOLVED) {
+          keep_certificate<T>();
+          status = inf;
+          last_precond_learned = use_learned;
+          return k;
+        }
+      }
       // FP32 stagnation: no 1% improvement of the worse normalised residual in 20 checks
       const double ratio = std::max(prim / std::max(eps_p, 1e-300), dual / std::max(eps_d, 1e-300));
       if (ratio < 0.99 * best_ratio) {
@@ -194,12 +258,19 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         fallback_request = 1;
         return k;
       }
+      armed = since_best >= kInfeasAfter;
       // PCG tolerance from the scaled residuals (Section 6.3.3). With the relative test
       // ‖r‖ ≤ ε‖b‖ the rule is capped at λ: a larger ε (residuals above 1/λ²) would let PCG stop
       // at zero iterations, freezing x̃ while ADMM stalls.
+      // Stall guard (not in the paper): the rule keeps ε large while the residuals stay large,
+      // which is what they do on an infeasible problem, and steps that inexact leave the
+      // differences δx̄, δȳ of Section 3 too noisy to pass its tests. After 10 checks without a
+      // 1% gain in the worse normalised residual, ε is divided by 10 at every second check.
+      if (since_best >= 10 && since_best % 2 == 0) tighten = std::max(tighten * 0.1, 1e-12);
       if (!fixed_eps) {
-        eps_pcg = std::max(s.pcg_lambda * std::sqrt(nm[0] * nm[6]), s.pcg_eps_min);
+        eps_pcg = s.pcg_lambda * std::sqrt(nm[0] * nm[6]);
         if (s.pcg_rel_test) eps_pcg = std::min(eps_pcg, s.pcg_lambda);
+        eps_pcg = std::max(eps_pcg * tighten, s.pcg_eps_min);
       }
       // ρ̄ update (Section 3.4, every rho_update_every iterations, Section 6.3.2)
       if (s.rho_update_every > 0 && k % s.rho_update_every == 0) {
@@ -233,6 +304,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
 int qpg_solver::solve() {
   auto t0 = std::chrono::steady_clock::now();
   info.status = QPG_UNSOLVED;
+  cert_valid = false;
   info.iter = 0;
   info.pcg_iter_total = 0;
   info.pcg_iter_max = 0;
@@ -241,6 +313,7 @@ int qpg_solver::solve() {
   info.precond_trials = 0;
   info.precond_learned_chosen = 0;
   info.precond_switches = 0;
+  info.infeas_checks = 0;
   info.prim_res = info.dual_res = INFINITY;
   info.obj_val = NAN;
   double rho = s.rho;
@@ -556,6 +629,8 @@ int qpg_default_settings(qpg_settings* s) {
   s->precond_trial = 1;
   s->spmv_tile_nnz = kTileNnz;
   s->spmv_plain_nnz = kPlainNnz;
+  s->eps_prim_inf = 1e-4;
+  s->eps_dual_inf = 1e-4;
   return QPG_OK;
 }
 
@@ -724,6 +799,14 @@ int qpg_get_scaling(const qpg_solver* h, double* D, double* E, double* c) {
   std::copy(h->D.begin(), h->D.end(), D);
   std::copy(h->E.begin(), h->E.end(), E);
   *c = h->c;
+  return QPG_OK;
+}
+
+int qpg_get_certificate(const qpg_solver* h, double* dx, double* dy) {
+  if (!h) return QPG_ERR_ARG;
+  if (!h->cert_valid) return QPG_ERR_STATE;
+  if (dx) std::copy(h->cert_x.begin(), h->cert_x.end(), dx);
+  if (dy) std::copy(h->cert_y.begin(), h->cert_y.end(), dy);
   return QPG_OK;
 }
 

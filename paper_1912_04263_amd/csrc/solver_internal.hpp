@@ -50,6 +50,7 @@ struct Prec {
   T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
   T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
   pair_t<T>* gp = nullptr;  // (x̃, 0) (n), then (ρ̄(z̃ − z) + y, ρ̄z − y) (m), for the right-hand side
+  T* dxy = nullptr;         // δx̄ (n), then δȳ (m): differences of the last checked ADMM step
   bool ready = false;
 };
 
@@ -107,6 +108,8 @@ struct qpg_solver {
 
   // host copies
   std::vector<double> D, E, diagP_h, colsq_h, x_out, y_out, z_out;
+  std::vector<double> cert_x, cert_y;  // normalised δx, δy of the last infeasibility check
+  bool cert_valid = false;
   double c = 1.0, q_norm = 0.0, qb_norm = 0.0;
   double rho_cur = 0.1;
   int32_t scaling_passes = 0;
@@ -280,6 +283,9 @@ struct qpg_solver {
 
   template <typename T>
   int admm(int k_start, double& rho, double& eps_pcg, int& status, int& fallback_request);
+  int infeasibility_status() const;
+  template <typename T>
+  void keep_certificate();
 
   int solve();
   void build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const int32_t* col,

@@ -19,13 +19,15 @@ LIB_PATH = os.path.join(HERE, "libqpg.so")
 QPG_OK = 0
 QPG_ERR_ARG, QPG_ERR_DATA, QPG_ERR_SIZE, QPG_ERR_DEVICE, QPG_ERR_OOM, QPG_ERR_STATE = -1, -2, -3, -4, -5, -6
 QPG_UNSOLVED, QPG_SOLVED, QPG_MAX_ITER_REACHED, QPG_NUMERICAL_ERROR = 0, 1, 2, 3
+QPG_PRIMAL_INFEASIBLE, QPG_DUAL_INFEASIBLE = 4, 5
 QPG_FP64, QPG_MIXED = 0, 1
 QPG_PRECOND_JACOBI, QPG_PRECOND_LEARNED = 0, 1
 QPG_NET_NPARAMS = 16705
 QPG_OP_A, QPG_OP_AT, QPG_OP_P, QPG_OP_K = 0, 1, 2, 3
 QPG_KERNEL_SPMV_A, QPG_KERNEL_SPMV_B, QPG_KERNEL_PCG_UPDATE, QPG_KERNEL_PCG_DIR = 0, 1, 2, 3
 QPG_KERNEL_SPMV_A_STREAM, QPG_KERNEL_SPMV_B_STREAM = 4, 5
-STATUS = {0: "unsolved", 1: "solved", 2: "max_iter_reached", 3: "numerical_error"}
+STATUS = {0: "unsolved", 1: "solved", 2: "max_iter_reached", 3: "numerical_error", 4: "primal_infeasible",
+          5: "dual_infeasible"}
 
 
 class Csc(C.Structure):
@@ -44,7 +46,8 @@ class Settings(C.Structure):
                 ("scaling_iters", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
                 ("device", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
                 ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32),
-                ("spmv_tile_nnz", C.c_int32), ("spmv_plain_nnz", C.c_int32)]
+                ("spmv_tile_nnz", C.c_int32), ("spmv_plain_nnz", C.c_int32),
+                ("eps_prim_inf", C.c_double), ("eps_dual_inf", C.c_double)]
 
 
 class Info(C.Structure):
@@ -55,7 +58,7 @@ class Info(C.Structure):
                 ("precision_used", C.c_int32), ("precond_used", C.c_int32),
                 ("fallback_events", C.c_int32), ("scaling_passes", C.c_int32),
                 ("precond_trials", C.c_int32), ("precond_learned_chosen", C.c_int32),
-                ("precond_switches", C.c_int32)]
+                ("precond_switches", C.c_int32), ("infeas_checks", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -75,6 +78,7 @@ SIGNATURES = {
     "qpg_get_z": (C.c_int, [C.c_void_p, _PD]),
     "qpg_get_info": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
     "qpg_get_scaling": (C.c_int, [C.c_void_p, _PD, _PD, _PD]),
+    "qpg_get_certificate": (C.c_int, [C.c_void_p, _PD, _PD]),
     "qpg_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _PD, _PD]),
     "qpg_pcg": (C.c_int, [C.c_void_p, C.c_int32, _PD, _PD, C.c_double, C.c_int32, C.c_int32, _PD,
                           _PI, _PD]),
@@ -167,6 +171,7 @@ class SolveInfo:
     precond_trials: int = 0
     precond_learned_chosen: int = 0
     precond_switches: int = 0
+    infeas_checks: int = 0
 
 
 class _CscArrays:
@@ -221,7 +226,7 @@ class Solver:
                          i.solve_time, "mixed" if i.precision_used == QPG_MIXED else "fp64",
                          i.fallback_events, i.scaling_passes,
                          "learned" if i.precond_used == QPG_PRECOND_LEARNED else "jacobi",
-                         i.precond_trials, i.precond_learned_chosen, i.precond_switches)
+                         i.precond_trials, i.precond_learned_chosen, i.precond_switches, i.infeas_checks)
 
     def x(self):
         out = np.empty(self.n)
@@ -237,6 +242,13 @@ class Solver:
         out = np.empty(self.m)
         self._check(lib().qpg_get_z(self._h, _dptr(out)))
         return out
+
+    def certificate(self):
+        """(δx, δy) of an infeasible last solve, each scaled to ‖·‖∞ = 1 (δy certifies primal,
+        δx dual infeasibility)."""
+        dx, dy = np.empty(self.n), np.empty(self.m)
+        self._check(lib().qpg_get_certificate(self._h, _dptr(dx), _dptr(dy)))
+        return dx, dy
 
     def scaling(self):
         D, E, c = np.empty(self.n), np.empty(self.m), C.c_double()
