@@ -54,9 +54,10 @@ def spmv_a_bytes(n, m, nnz_a, s):
     return nnz_a * (s + 4) + 4 * (m + 1) + n * s + m * s
 
 
-def pcg_update_bytes(n, s):
-    """x̃ += αp, r += αKp, rᵀM⁻¹r, ‖r‖∞: read x̃, p, r, Kp, M⁻¹; write x̃, r."""
-    return 7 * n * s
+def pcg_update_bytes(n, m, s):
+    """x̃ += αp, r += αKp, rᵀM⁻¹r, ‖r‖∞: read x̃, p, r, Kp, M⁻¹; write x̃, r. z̃ += αw/ρ̄ (the
+    tracked Āx̃): read z̃, w; write z̃."""
+    return 7 * n * s + 3 * m * s
 
 
 def pcg_dir_bytes(n, s):
@@ -183,7 +184,7 @@ def main():
     kernels = {}
     pcg_steps = ((qpg.QPG_KERNEL_SPMV_B, "spmv_B_Kp", spmv_b_bytes(n, m, nnz_b, sz)),
              (qpg.QPG_KERNEL_SPMV_A, "spmv_A_w", spmv_a_bytes(n, m, nnz_a, sz)),
-             (qpg.QPG_KERNEL_PCG_UPDATE, "pcg_update", pcg_update_bytes(n, sz)),
+             (qpg.QPG_KERNEL_PCG_UPDATE, "pcg_update", pcg_update_bytes(n, m, sz)),
              (qpg.QPG_KERNEL_PCG_DIR, "pcg_dir", pcg_dir_bytes(n, sz)))
     for kid, name, nbytes in pcg_steps:
         us = s.time_kernel(kid, args.kernel_reps, prec_id)

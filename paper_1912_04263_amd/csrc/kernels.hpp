@@ -647,6 +647,8 @@ struct OpInfeasB {
 // -------------------------------------------------------------------------------- vector kernels
 
 // PCG update (Algorithm 3): x̃ += αp; r += αKp; y = M⁻¹r (not stored); rᵀy; ‖r‖∞.
+// With zt set, z̃ = Āx̃ follows x̃: z̃ += α·Āp, with Āp = w/ρ̄ from this iteration's Ā pass, so the
+// ADMM update after PCG needs no SpMV of its own.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt,
                                                        T* __restrict__ r,
@@ -654,18 +656,34 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt
                                                        const T* __restrict__ kp,
                                                        const T* __restrict__ dinv,
                                                        const DevState* st, double* partials,
-                                                       const int32_t* __restrict__ gate) {
+                                                       const int32_t* __restrict__ gate, int m,
+                                                       T* __restrict__ zt, const T* __restrict__ w,
+                                                       T rho_inv) {
   if (gate && *gate) return;
   const T a = (T)st->alpha;
   double red[2] = {0.0, 0.0};
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    xt[i] += a * p[i];
-    const T ri = r[i] + a * kp[i];
-    r[i] = ri;
-    red[0] += (double)ri * (double)(ri * dinv[i]);
-    red[1] = nmax(red[1], fabs((double)ri));
+  const int total = zt ? (n > m ? n : m) : n;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+    if (i < n) {
+      xt[i] += a * p[i];
+      const T ri = r[i] + a * kp[i];
+      r[i] = ri;
+      red[0] += (double)ri * (double)(ri * dinv[i]);
+      red[1] = nmax(red[1], fabs((double)ri));
+    }
+    if (zt && i < m) zt[i] += a * (w[i] * rho_inv);
   }
   publish<2, 2u>(red, partials);
+}
+
+// An SpMV operation's row epilogue and side task without the SpMV: the row values s1 are given
+// (used by the ADMM update when z̃ = Āx̃ is already known).
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__ s1, Op op) {
+  double red[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < rows; i += gridDim.x * kBlock)
+    op.epilogue(i, s1[i], T(0), T(0), red);
+  op.side();
 }
 
 // β = r⁺ᵀy⁺ / rᵀy, iteration count and the stopping flag (run by k_finalize).

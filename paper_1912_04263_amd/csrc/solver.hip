@@ -133,14 +133,15 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       copy(V.b, (const T*)V.xt, n);  // the warm start, kept for the second run
       learned_dinv<T>(rho);
       finalize(rr, spmv_B<T>(rr));
-      const int it_l = pcg_loop<T>(rho, s.pcg_max_iter);
+      const int it_l = pcg_loop<T>(rho, s.pcg_max_iter, true);
       const double rn_l = st_host->rnorm;
       const bool cap_l = it_l >= s.pcg_max_iter && rn_l > st_host->thresh;
       const bool broke_l = st_host->breakdown != 0;
       copy(V.xt, (const T*)V.b, n);
+      spmv_A<T>(OpScaled<T>{V.xt, V.zt, (T)1});  // z̃ = Āx̃ of the restored warm start
       jacobi<T>(rho);
       finalize(rr, spmv_B<T>(rr));
-      it = pcg_loop<T>(rho, s.pcg_max_iter);
+      it = pcg_loop<T>(rho, s.pcg_max_iter, true);
       const bool cap_j = it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh;
       use_learned = !broke_l && ((!cap_l && it_l < it) || (cap_l && cap_j && rn_l < st_host->rnorm));
       lost_in_a_row = use_learned ? 0 : lost_in_a_row + 1;
@@ -155,7 +156,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     } else {
       finalize(rr, spmv_B<T>(rr));
       // (a3)–(a6) PCG iterations
-      it = pcg_loop<T>(rho, s.pcg_max_iter);
+      it = pcg_loop<T>(rho, s.pcg_max_iter, true);
       if (use_learned && (st_host->breakdown ||
                           (it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh))) {
         use_learned = false;  // runtime guard
@@ -184,13 +185,19 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     const bool check = (k % s.check_every == 0 || k == s.max_iter);
     T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
     T* dxy = (check && infeas && armed) ? V.dxy : nullptr;  // δx̄, δȳ of this step (Section 3.1)
+    // Between checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a
+    // vector pass; a check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
+    OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
+                           (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy};
     if (check && ax) {
       OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
                            (T)rho, (T)(1.0 / rho), n, st, dxy};
       finalize(up, spmv_A<T>(up));
+    } else if (check) {
+      spmv_A<T>(upd);
     } else {
-      spmv_A<T>(OpUpdate<T, false>{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
-                                   (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy});
+      hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(grid_for(std::max(n, m))), dim3(kBlock), 0,
+                         stream, m, (const T*)V.zt, upd);
     }
     // (a9) residuals and termination every check_every iterations
     if (check) {
@@ -507,7 +514,7 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
       case QPG_KERNEL_PCG_UPDATE:
         hipLaunchKernelGGL((k_pcg_update<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.xt,
                            V.r, V.p, V.kp, V.dinv, (const DevState*)h->st, h->rb.partials,
-                           (const int32_t*)nullptr);
+                           (const int32_t*)nullptr, h->m, V.zt, (const T*)V.w, (T)(1.0 / h->rho_cur));
         break;
       default:
         hipLaunchKernelGGL((k_pcg_dir<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.p, V.r,

@@ -218,16 +218,18 @@ struct qpg_solver {
                        colsq, s.sigma, rho);
   }
 
-  // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set.
+  // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set. With
+  // track_zt, z̃ = Āx̃ is carried along (see k_pcg_update).
   template <typename T>
-  void pcg_iteration(double rho) {
+  void pcg_iteration(double rho, bool track_zt) {
     Prec<T>& V = P<T>();
     const int32_t* gate = &st->done;
     spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho}, gate);
     OpKp<T> kp{V.p, V.w, V.kp, (T)s.sigma, n, st};
     finalize(kp, spmv_B<T>(kp, gate), gate);
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.xt, V.r, V.p,
-                       V.kp, V.dinv, (const DevState*)st, rb.partials, gate);
+                       V.kp, V.dinv, (const DevState*)st, rb.partials, gate, m,
+                       track_zt ? V.zt : (T*)nullptr, (const T*)V.w, (T)(1.0 / rho));
     finalize_fn<2, 2u>(FinPcgUpdate{st}, vgrid, gate);
     hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, V.r, V.dinv,
                        (const DevState*)st, gate);
@@ -237,12 +239,12 @@ struct qpg_solver {
   // shorter than the previous PCG solve took, so that iterations launched after convergence
   // (which exit at once) stay rare; then one iteration per host check. Returns the count.
   template <typename T>
-  int pcg_loop(double rho, int maxit) {
+  int pcg_loop(double rho, int maxit, bool track_zt = false) {
     int issued = 0;
     int batch = std::max(1, std::min(last_pcg - 1, maxit));
     for (;;) {
       int k = std::min(batch, maxit - issued);
-      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho);
+      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho, track_zt);
       issued += k;
       sync_state();
       if (st_host->done || issued >= maxit) break;

@@ -5,10 +5,13 @@ Tolerances:
   ≈ rowlen·2⁻⁵³ relative to (|M||x|)_i; the oracle sums in extended precision).
 * SpMV FP32: ≤ 1e-5 on the same scale (inputs rounded to 2⁻²⁴, accumulation in float).
 * Final answer at eps_abs = eps_rel = 1e-5: |f − f*| ≤ 1e-4·max(1, |f*|) and
-  ‖x − x*‖∞ ≤ 1e-3·‖x*‖∞ against the oracle run to 1e-9. Portfolio instances are compared at
-  eps 1e-7: the method itself (the oracle's exact-solve ADMM) stopped at 1e-5 is 3.5e-4 off in
-  objective on them, and stopped at 1e-6 it is still ≈1e-3 off in x (measured: 0.98e-3 in
-  FP64), so only a tighter stop separates implementation error from the method's own.
+  ‖x − x*‖∞ ≤ 1e-3·‖x*‖∞ against the oracle run to 1e-9; the residuals of the returned point,
+  recomputed in float64, within 1.01·eps (plus, in mixed precision, the forward error bound
+  (k + 2)·2⁻²⁴·(|M||v|)_i of the float dot products the solver's own test used). Portfolio
+  instances are compared at eps 1e-7: the method itself (the oracle's exact-solve ADMM) stopped
+  at 1e-5 is 3.5e-4 off in objective on them, and stopped at 1e-6 it is still ≈1e-3 off in x
+  (measured: 0.98e-3 in FP64), so only a tighter stop separates implementation error from the
+  method's own.
 * Iterate trace with a near-exact PCG (fixed relative tolerance 1e-13) against the oracle's
   direct KKT solves: 1e-8 relative.
 """
@@ -215,10 +218,22 @@ def test_final_answer_matches_oracle(name, precision):
         # the reported objective is the objective of the returned x
         f = o_kkt.objective(p.P_full(), p.q, x)
         assert abs(f - info.obj_val) <= 1e-6 * max(1.0, abs(f))
-        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, x, s.y(), s.z())
+        y, z = s.y(), s.z()
+        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, x, y, z)
         eps_p = eps + eps * max(rep["norms"]["Ax"], rep["norms"]["z"])
         eps_d = eps + eps * max(rep["norms"]["Px"], rep["norms"]["Aty"], rep["norms"]["q"])
-        assert rep["prim"] <= 1.01 * eps_p and rep["dual"] <= 1.01 * eps_d
+        slack_p = slack_d = 0.0
+        if precision == "mixed":
+            # the solver's own residuals are float sums of float products: the exact residual of
+            # the returned point may exceed them by the dot-product bound (k + 2)·2⁻²⁴·(|M||v|)_i
+            A = sp.csr_matrix(p.A)
+            P = sp.csr_matrix(p.P_full())
+            u = 2.0 ** -24
+            kA = np.diff(A.indptr) + 2
+            kB = np.diff(P.indptr) + np.diff(sp.csc_matrix(A).indptr) + 2
+            slack_p = float(np.max(u * kA * (abs(A) @ np.abs(x) + np.abs(z)))) if p.m else 0.0
+            slack_d = float(np.max(u * kB * (abs(P) @ np.abs(x) + abs(A).T @ np.abs(y) + np.abs(p.q))))
+        assert rep["prim"] <= 1.01 * eps_p + slack_p and rep["dual"] <= 1.01 * eps_d + slack_d
         # z and the scaled bounds are held in float in mixed precision
         box_tol = 1e-6 if precision == "mixed" else 1e-9
         assert rep["box"] <= box_tol * (1 + rep["norms"]["z"])
