@@ -116,15 +116,19 @@ __device__ __forceinline__ void publish(double (&v)[NS], double* partials) {
 }
 
 // One 1024-thread workgroup: combine `count` partials in a fixed order (thread t takes
-// workgroups t, t + 1024, …; then a fixed tree), run the scalar finalisation, and mirror the
-// device scalars into host-visible memory for the host's checks.
+// workgroups t, t + 1024, …; then a fixed tree) and run the scalar finalisation, unless the gate
+// is set; then, when `mirror` is given (only before a host read: the write crosses PCIe), copy the
+// device scalars into host-visible memory, gate or not.
 constexpr int kFinBlock = 1024;
 
 template <int NS, unsigned MAXMASK, class Fin>
 __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict__ partials, int count,
                                                         Fin fin, const int32_t* __restrict__ gate,
                                                         const DevState* st, DevState* mirror) {
-  if (gate && *gate) return;
+  if (gate && *gate) {
+    if (mirror && threadIdx.x == 0) *mirror = *st;
+    return;
+  }
   __shared__ double lds[kMaxSlots][kFinBlock / 64];
   double acc[NS];
 #pragma unroll
@@ -152,6 +156,11 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict
     fin(acc);
     if (mirror) *mirror = *st;
   }
+}
+
+template <class S>
+__global__ void k_mirror(const S* st, S* mirror) {
+  if (threadIdx.x == 0) *mirror = *st;
 }
 
 template <typename T>

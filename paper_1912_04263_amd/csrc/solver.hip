@@ -206,7 +206,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         finalize(rp, spmv_A<T>(rp));
       }
       OpRDual<T> rd{V.x, V.y, V.qb, dscale, n, st};
-      finalize(rd, spmv_B<T>(rd));
+      finalize(rd, spmv_B<T>(rd), nullptr, true);
       sync_state();
       const double* nm = st_host->norms;
       const double prim = nm[1], nAx = nm[3], nz = nm[5];
@@ -240,7 +240,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         OpInfeasA<T> ia{V.dxy, V.lb, V.ub, escale, n, st};
         finalize(ia, spmv_A<T>(ia));
         OpInfeasB<T> ib{V.dxy, V.qb, dscale, st};
-        finalize(ib, spmv_B<T>(ib));
+        finalize(ib, spmv_B<T>(ib), nullptr, true);
         sync_state();
         const int inf = infeasibility_status();
         if (s.verbose) {

@@ -193,18 +193,21 @@ struct qpg_solver {
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
   template <class Op>
-  void finalize(const Op& op, int count, const int32_t* gate = nullptr) {
+  void finalize(const Op& op, int count, const int32_t* gate = nullptr, bool mirror = false) {
     hipLaunchKernelGGL((k_finalize<Op::NS, Op::MAXMASK, Op>), dim3(1), dim3(kFinBlock), 0, stream,
-                       (const double*)rb.partials, count, op, gate, (const DevState*)st, st_mirror_dev);
+                       (const double*)rb.partials, count, op, gate, (const DevState*)st,
+                       mirror ? st_mirror_dev : nullptr);
   }
   template <int NS, unsigned MASK, class Fin>
-  void finalize_fn(const Fin& fin, int count, const int32_t* gate = nullptr) {
+  void finalize_fn(const Fin& fin, int count, const int32_t* gate = nullptr, bool mirror = false) {
     hipLaunchKernelGGL((k_finalize<NS, MASK, Fin>), dim3(1), dim3(kFinBlock), 0, stream,
-                       (const double*)rb.partials, count, fin, gate, (const DevState*)st, st_mirror_dev);
+                       (const double*)rb.partials, count, fin, gate, (const DevState*)st,
+                       mirror ? st_mirror_dev : nullptr);
   }
 
-  // Wait for the stream and read the device scalars. Every finalize kernel leaves a copy of
-  // them in mapped host memory (st_host), so no copy is queued: the host polls the stream.
+  // Wait for the stream and read the device scalars: the finalize kernel launched last before a
+  // host read leaves a copy of them in mapped host memory (st_host), so no copy is queued and the
+  // host polls the stream.
   void sync_state() {
     hipError_t e;
     while ((e = hipStreamQuery(stream)) == hipErrorNotReady) {
@@ -221,7 +224,7 @@ struct qpg_solver {
   // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set. With
   // track_zt, z̃ = Āx̃ is carried along (see k_pcg_update).
   template <typename T>
-  void pcg_iteration(double rho, bool track_zt) {
+  void pcg_iteration(double rho, bool track_zt, bool mirror) {
     Prec<T>& V = P<T>();
     const int32_t* gate = &st->done;
     spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho}, gate);
@@ -230,7 +233,7 @@ struct qpg_solver {
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.xt, V.r, V.p,
                        V.kp, V.dinv, (const DevState*)st, rb.partials, gate, m,
                        track_zt ? V.zt : (T*)nullptr, (const T*)V.w, (T)(1.0 / rho));
-    finalize_fn<2, 2u>(FinPcgUpdate{st}, vgrid, gate);
+    finalize_fn<2, 2u>(FinPcgUpdate{st}, vgrid, gate, mirror);
     hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, V.r, V.dinv,
                        (const DevState*)st, gate);
   }
@@ -244,7 +247,8 @@ struct qpg_solver {
     int batch = std::max(1, std::min(last_pcg - 1, maxit));
     for (;;) {
       int k = std::min(batch, maxit - issued);
-      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho, track_zt);
+      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho, track_zt, i == k - 1);
+      if (k == 0) hipLaunchKernelGGL(k_mirror<DevState>, dim3(1), dim3(64), 0, stream, (const DevState*)st, st_mirror_dev);
       issued += k;
       sync_state();
       if (st_host->done || issued >= maxit) break;
