@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "learned"])
     ap.add_argument("--weights", default="portfolio_h32", help="learned-preconditioner weights name")
     ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--rho-update-every", type=int, default=10,
+                    help="ρ̄ update cadence in ADMM iterations (0: constant ρ̄), for the cadence ablation")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -148,7 +150,8 @@ def main():
         precond = precond or args.precond
         extra = dict(precond="learned", precond_weights=weights) if precond == "learned" else {}
         s = qpg.Solver.from_qp(p, eps_abs=args.eps, eps_rel=args.eps, precision=precision,
-                               stream=stream, device=0, max_iter=20000, **extra)
+                               stream=stream, device=0, max_iter=20000,
+                               rho_update_every=args.rho_update_every, **extra)
         setup = s.info().setup_time
         for _ in range(warmup):
             s.solve()
@@ -265,7 +268,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "nnz_P": p.meta["nnz_P_full"], "nnz_A": nnz_a,
                    "eps_abs": args.eps, "eps_rel": args.eps, "precision": args.precision,
-                   "preconditioner": args.precond, "step": "one full solve from a cold start"},
+                   "preconditioner": args.precond, "rho_update_every": args.rho_update_every,
+                   "step": "one full solve from a cold start"},
         "tts_s": elapsed / steps if args.steps else None,
         "setup_s": setup_s,
         "status": last.status,

@@ -175,6 +175,90 @@ def svm_qp(n_points: int, n_feat: int, dens: float, seed: int, lam: float = 1.0)
     return _finish("svm", P, q, A, l, u, dict(seed=seed, n_points=N, n_feat=n, dens=dens, lam=lam))
 
 
+def control_qp(nx: int, nu: int, horizon: int, dens: float, seed: int) -> QP:
+    """Control class (Section 7.1): min x_Tᵀ Q_T x_T + Σ_{t<T} x_tᵀQx_t + u_tᵀRu_t subject to
+    x_0 = x_init, x_{t+1} = A x_t + B u_t, −x̲ ≤ x_t ≤ x̄, −u̲ ≤ u_t ≤ ū, over the stacked
+    variables (x_0, …, x_T, u_0, …, u_{T−1}).
+
+    Data: A = 0.95·I + Δ with Δ Bernoulli(dens), entries N(0, 0.03²/(nx·dens)) (spectral radius
+    of Δ about 0.03, so A is contractive); B Bernoulli(dens) N(0, 1); Q = diag(U[0, 10]) with a
+    fifth of its entries zeroed; Q_T = 10·Q + I; R = 0.1·I; x̄ = x̲ = 2 + U[0, 2];
+    ū = u̲ = 1 + U[0, 1]; x_init ~ U[−1, 1]. With A contractive, u = 0 keeps every |x_t| below
+    the bounds, so every instance is feasible. The objective has no ½, so
+    P = 2·blockdiag(Q, …, Q, Q_T, R, …, R).
+    """
+    rng = np.random.default_rng(seed)
+    T = horizon
+    Ad = (0.95 * sp.identity(nx, format="csr")
+          + sprandn(rng, nx, nx, dens, var=0.0009 / (nx * dens))).tocsr()
+    Bd = sprandn(rng, nx, nu, dens)
+    qd = rng.random(nx) * 10.0
+    qd[rng.choice(nx, nx // 5, replace=False)] = 0.0
+    Q = sp.diags(qd)
+    QT = sp.diags(10.0 * qd + 1.0)
+    R = 0.1 * sp.identity(nu)
+    P = 2.0 * sp.block_diag([Q] * T + [QT] + [R] * T, format="csr")
+    nX, nU = nx * (T + 1), nu * T
+    n = nX + nU
+    q = np.zeros(n)
+    # x_0 = x_init; x_{t+1} − A x_t − B u_t = 0
+    Ix = sp.identity(nx, format="csr")
+    Sx = sp.kron(sp.eye(T + 1, k=-1), -Ad) + sp.kron(sp.identity(T + 1), Ix)  # rows t: x_t − A x_{t−1}
+    Su = sp.kron(sp.vstack([sp.csr_matrix((1, T)), sp.identity(T)]), -Bd)      # rows t ≥ 1: − B u_{t−1}
+    Aeq = sp.hstack([Sx, Su]).tocsr()
+    xbar = 2.0 + 2.0 * rng.random(nx)
+    ubar = 1.0 + rng.random(nu)
+    x0 = 2.0 * rng.random(nx) - 1.0
+    beq = np.concatenate([x0, np.zeros(nx * T)])
+    Abox = sp.hstack([sp.csr_matrix((nx * T + nU, nx)), sp.identity(nx * T + nU)]).tocsr()
+    A = sp.vstack([Aeq, Abox], format="csc")
+    lbox = np.concatenate([np.tile(-xbar, T), np.tile(-ubar, T)])
+    ubox = np.concatenate([np.tile(xbar, T), np.tile(ubar, T)])
+    l = np.concatenate([beq, lbox])
+    u = np.concatenate([beq, ubox])
+    return _finish("control", P, q, A, l, u, dict(seed=seed, nx=nx, nu=nu, horizon=T, dens=dens))
+
+
+def equality_qp(n: int, m: int, dens_M: float, dens_A: float, seed: int) -> QP:
+    """Equality class (Section 7.1): min ½xᵀPx + qᵀx  s.t.  Ax = b, with the random class's
+    P = MMᵀ + 1e-2·I and A, q ~ N(0, 1), and b = A·x₀ for x₀ ~ N(0, 1) (consistent)."""
+    rng = np.random.default_rng(seed)
+    M = sprandn(rng, n, n, dens_M)
+    P = (M @ M.T + 1e-2 * sp.identity(n, format="csr")).tocsr()
+    A = sprandn(rng, m, n, dens_A)
+    q = rng.standard_normal(n)
+    b = A @ rng.standard_normal(n)
+    return _finish("equality", P, q, A, b, b.copy(), dict(seed=seed, dens_M=dens_M, dens_A=dens_A))
+
+
+def huber_qp(n_feat: int, m_data: int, dens: float, seed: int, M: float = 1.0) -> QP:
+    """Huber class (Section 7.1): min Σ φ_hub(a_iᵀx − b_i), φ_hub(v) = v² for |v| ≤ M and
+    M(2|v| − M) otherwise, as the QP over (x, w, r, s):
+
+        min wᵀw + 2M·1ᵀ(r + s)  s.t.  Ad·x − w − r + s = b,  r ≥ 0,  s ≥ 0
+
+    (for a residual v the inner minimum over w + r − s = v is v² when |v| ≤ M and 2M|v| − M²
+    otherwise). Data: Ad Bernoulli(dens) N(0, 1); x_true ~ N(0, 1/n_feat); b = Ad·x_true + ε with
+    ε ~ N(0, 1/4) on 95% of the points and N(0, 10²) on the other 5% (outliers)."""
+    rng = np.random.default_rng(seed)
+    Ad = sprandn(rng, m_data, n_feat, dens)
+    x_true = rng.standard_normal(n_feat) * math.sqrt(1.0 / n_feat)
+    noise = 0.5 * rng.standard_normal(m_data)
+    out = rng.random(m_data) < 0.05
+    noise[out] = 10.0 * rng.standard_normal(int(out.sum()))
+    b = Ad @ x_true + noise
+    n, m = n_feat, m_data
+    Im = sp.identity(m, format="csr")
+    P = sp.block_diag((sp.csr_matrix((n, n)), 2.0 * Im, sp.csr_matrix((2 * m, 2 * m))), format="csr")
+    q = np.concatenate([np.zeros(n + m), 2.0 * M * np.ones(2 * m)])
+    A = sp.bmat([[Ad, -Im, -Im, Im],
+                 [None, None, Im, None],
+                 [None, None, None, Im]], format="csc")
+    l = np.concatenate([b, np.zeros(2 * m)])
+    u = np.concatenate([b, np.inf * np.ones(2 * m)])
+    return _finish("huber", P, q, A, l, u, dict(seed=seed, n_feat=n, m_data=m, dens=dens, M=M))
+
+
 def primal_infeasible_qp(n: int, m: int, dens: float, seed: int) -> QP:
     """Random class whose longest row a of A is moved to the end and doubled under disjoint
     bounds, a·x ∈ [1, 2] (row m − 1) and a·x ∈ [3, 4] (row m), so that no x is feasible; every
@@ -227,6 +311,14 @@ WORKLOADS = {
     "svm_c4": lambda j=0: svm_qp(1_000_000, 10_000, 0.01, 1000 * 4 + j),
 }
 
+# The three further classes of Section 7.1 at sizes of the same order (n + m ≈ 2·10⁵–6·10⁶,
+# 10⁷–2·10⁷ entries of A); instance j uses seed 1000·i + j with i = 10, 11, 12.
+MORE = {
+    "control_large": lambda j=0: control_qp(2000, 1000, 30, 0.1, 1000 * 10 + j),
+    "equality_large": lambda j=0: equality_qp(100_000, 50_000, 4.47e-5, 4e-4, 1000 * 11 + j),
+    "huber_large": lambda j=0: huber_qp(10_000, 1_000_000, 1e-3, 1000 * 12 + j),
+}
+
 # Scaled-down variants with the same generators and per-row densities, sized so
 # that the oracle's direct solve finishes in seconds.
 SMALL = {
@@ -235,10 +327,15 @@ SMALL = {
     "random2_small": lambda j=0: random_qp(1_000, 10_000, 4.4e-3, 2e-2, 1000 * 7 + j),
     "portfolio_small": lambda j=0: portfolio_qp(2_000, 20, 0.5, 1000 * 8 + j),
     "svm_small": lambda j=0: svm_qp(4_000, 100, 0.1, 1000 * 9 + j),
+    "control_small": lambda j=0: control_qp(20, 10, 10, 0.3, 1000 * 13 + j),
+    "equality_small": lambda j=0: equality_qp(500, 250, 0.02, 0.02, 1000 * 14 + j),
+    "huber_small": lambda j=0: huber_qp(100, 2_000, 0.05, 1000 * 15 + j),
 }
 
 
 def make(name: str, j: int = 0) -> QP:
     if name in WORKLOADS:
         return WORKLOADS[name](j)
+    if name in MORE:
+        return MORE[name](j)
     return SMALL[name](j)

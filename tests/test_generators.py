@@ -71,3 +71,43 @@ def test_infeasible_generators_structure():
     col = d.A.tocsc()[:, v]
     assert col.nnz == 1 and col.indices[0] == d.m - 1 and d.l[-1] == 0.0 and d.u[-1] == np.inf
     assert np.linalg.eigvalsh(np.delete(np.delete(d.P_full().toarray(), v, 0), v, 1)).min() > 0
+
+
+def test_control_instances_are_feasible_with_zero_input():
+    p = pr.control_qp(20, 10, 10, 0.3, 5)
+    nx, nu, T = 20, 10, 10
+    A = p.A.tocsr()
+    # u = 0: propagate x with the dynamics rows themselves (x_{t+1} solves row block t + 1)
+    x = np.zeros(p.n)
+    x[:nx] = p.l[:nx]
+    Ad = -A[nx:2 * nx, :nx].toarray()  # rows x_1 − A x_0
+    for t in range(T):
+        x[(t + 1) * nx:(t + 2) * nx] = Ad @ x[t * nx:(t + 1) * nx]
+    Ax = A @ x
+    assert np.all(Ax >= p.l - 1e-12) and np.all(Ax <= p.u + 1e-12)
+    assert p.P_full().shape == (p.n, p.n) and np.all(p.P_full().diagonal() >= 0)
+
+
+def test_huber_qp_objective_is_the_huber_loss():
+    p = pr.huber_qp(30, 200, 0.2, 6)
+    n, m, M = 30, 200, p.meta["M"]
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(n)
+    A = p.A.tocsr()
+    v = A[:m, :n] @ x - p.l[:m]  # residuals a_iᵀx − b_i
+    w = np.clip(v, -M, M)
+    r = np.maximum(v - M, 0.0)
+    s = np.maximum(-v - M, 0.0)
+    z = np.concatenate([x, w, r, s])
+    Az = A @ z
+    assert np.allclose(Az[:m], p.l[:m]) and np.all(Az[m:] >= 0)
+    obj = 0.5 * z @ (p.P_full() @ z) + p.q @ z
+    huber = np.where(np.abs(v) <= M, v ** 2, M * (2 * np.abs(v) - M))
+    assert obj == pytest.approx(huber.sum(), rel=1e-12)
+
+
+def test_equality_instances_are_consistent():
+    p = pr.equality_qp(500, 250, 0.02, 0.02, 7)
+    assert np.array_equal(p.l, p.u)
+    x, *_ = np.linalg.lstsq(p.A.toarray(), p.l, rcond=None)
+    assert np.allclose(p.A @ x, p.l, atol=1e-8)
