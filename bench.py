@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--rho-update-every", type=int, default=10,
                     help="ρ̄ update cadence in ADMM iterations (0: constant ρ̄), for the cadence ablation")
+    ap.add_argument("--check-every", type=int, default=5, help="termination check cadence (ablation)")
+    ap.add_argument("--rho-vector", type=int, default=0, help="1: R = diag(ρ_i) (ablation)")
+    ap.add_argument("--pcg-eps-schedule", type=int, default=0,
+                    help="1: PCG tolerance decreasing with k instead of the residual rule (ablation)")
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -151,7 +155,9 @@ def main():
         extra = dict(precond="learned", precond_weights=weights) if precond == "learned" else {}
         s = qpg.Solver.from_qp(p, eps_abs=args.eps, eps_rel=args.eps, precision=precision,
                                stream=stream, device=0, max_iter=20000,
-                               rho_update_every=args.rho_update_every, **extra)
+                               rho_update_every=args.rho_update_every, check_every=args.check_every,
+                               rho_vector=args.rho_vector, pcg_eps_schedule=args.pcg_eps_schedule,
+                               **extra)
         setup = s.info().setup_time
         for _ in range(warmup):
             s.solve()
@@ -269,6 +275,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "nnz_P": p.meta["nnz_P_full"], "nnz_A": nnz_a,
                    "eps_abs": args.eps, "eps_rel": args.eps, "precision": args.precision,
                    "preconditioner": args.precond, "rho_update_every": args.rho_update_every,
+                   "check_every": args.check_every, "rho_vector": args.rho_vector,
+                   "pcg_eps_schedule": args.pcg_eps_schedule,
                    "step": "one full solve from a cold start"},
         "tts_s": elapsed / steps if args.steps else None,
         "setup_s": setup_s,

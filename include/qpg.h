@@ -107,6 +107,14 @@ typedef struct {
                              ‖δy‖∞; default 1e-4; 0 disables the test */
   double eps_dual_inf;    /* ε_dinf of the dual infeasibility test, relative to ‖δx‖∞; default
                              1e-4; 0 disables it (both 0: no infeasibility passes at all) */
+  int32_t rho_vector;     /* 0 (default): R = ρ̄I, the choice of Section 6.3 for the PCG step;
+                             1: OSQP's R = diag(ρ_i), ρ_i = 10³ρ̄ where l_i = u_i (eq. rho_vec),
+                             in K = P + σI + AᵀRA, its Jacobi diagonal and the ADMM updates (the
+                             ablation of Section 6.3; Jacobi preconditioner only) */
+  int32_t pcg_eps_schedule; /* 0 (default): the residual rule of Section 6.3.3 (pcg_lambda,
+                             pcg_eps_min, refreshed at every check); 1: a tolerance decreasing with
+                             the ADMM iteration k, max(pcg_lambda·(k + 1)^(−3/2), pcg_eps_min), the
+                             kind of rule Section 6.3.3 attributes to SCS (an ablation) */
 } qpg_settings;
 
 typedef struct {
@@ -179,7 +187,8 @@ int qpg_get_scaling(const qpg_solver* h, double* D, double* E, double* c);
  *   QPG_OP_AT  out(n) = Āᵀ in(m)                        (Section 6.2: Aᵀ stored in CSR)
  *   QPG_OP_P   out(n) = P̄ in(n)                         (Section 6.2: full P in CSR)
  *   QPG_OP_K   out(n) = (P̄ + σI + ρ̄ĀᵀĀ) in(n), matrix-free as w = ρ̄Āx, Px + σx + Āᵀw
- *                                                       (Section 6.3) with the current ρ̄ */
+ *                                                       (Section 6.3) with the current ρ̄
+ *                                                       (ĀᵀRĀ, w = RĀx with settings.rho_vector) */
 #define QPG_OP_A 0
 #define QPG_OP_AT 1
 #define QPG_OP_P 2

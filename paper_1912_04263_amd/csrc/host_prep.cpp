@@ -178,7 +178,9 @@ int validate_settings(const qpg_settings* s, std::string* msg) {
              (s->precond == QPG_PRECOND_LEARNED && s->precond_weights != nullptr)) &&
             (s->precond_trial == 0 || s->precond_trial == 1) && s->device >= 0 &&
             s->spmv_tile_nnz >= 0 && s->spmv_plain_nnz >= 0 && s->eps_prim_inf >= 0 &&
-            s->eps_dual_inf >= 0 && std::isfinite(s->eps_prim_inf) && std::isfinite(s->eps_dual_inf);
+            s->eps_dual_inf >= 0 && std::isfinite(s->eps_prim_inf) && std::isfinite(s->eps_dual_inf) &&
+            (s->rho_vector == 0 || (s->rho_vector == 1 && s->precond == QPG_PRECOND_JACOBI)) &&
+            (s->pcg_eps_schedule == 0 || s->pcg_eps_schedule == 1);
   if (!ok) {
     *msg = "settings: value out of range";
     return QPG_ERR_ARG;
@@ -426,16 +428,28 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
     H.ub[i] = E[i] * ui;
   }
 
-  // ---- diag(P̄) and the squared column norms of Ā (Section 6.3.1) from the rows of B
+  // ---- diag(P̄) and the squared column norms of Ā (Section 6.3.1) from the rows of B; with
+  // R = diag(ρ_i) (eq. rho_vec) also the equality rows' share of them
+  const bool rvec = s->rho_vector != 0;
+  if (rvec) {
+    H.eqrow.assign(m, 0);
+    for (int32_t i = 0; i < m; ++i) H.eqrow[i] = (l[i] == u[i]) ? 1 : 0;
+    H.colsq_eq.assign(n, 0.0);
+  }
   H.diagP.assign(n, 0.0);
   H.colsq.assign(n, 0.0);
   parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
     for (int64_t i = lo; i < hi; ++i) {
       for (int32_t k = H.b_ptr[i]; k < H.b_split[i]; ++k)
         if (H.b_col[k] == i) H.diagP[i] = H.b_val[k];
-      double sq = 0.0;
-      for (int32_t k = H.b_split[i]; k < H.b_ptr[i + 1]; ++k) sq += H.b_val[k] * H.b_val[k];
+      double sq = 0.0, sq_eq = 0.0;
+      for (int32_t k = H.b_split[i]; k < H.b_ptr[i + 1]; ++k) {
+        const double v2 = H.b_val[k] * H.b_val[k];
+        sq += v2;
+        if (rvec && H.eqrow[H.b_col[k] - n]) sq_eq += v2;
+      }
       H.colsq[i] = sq;
+      if (rvec) H.colsq_eq[i] = sq_eq;
     }
   });
   double qn = 0.0;

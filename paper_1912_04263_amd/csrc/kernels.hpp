@@ -21,6 +21,14 @@ namespace qpg {
 
 constexpr int kMaxSlots = 8;
 
+// R = diag(ρ_i) with ρ_i = 10³ρ̄ on the equality rows (eq. rho_vec) when a row flag array is
+// given; ρ̄ everywhere otherwise.
+constexpr double kRhoEq = 1e3;
+template <typename T>
+__device__ __forceinline__ T row_rho(const uint8_t* eq, int i, T rho) {
+  return (eq && eq[i]) ? T(kRhoEq) * rho : rho;
+}
+
 // Scalars of the iteration that live on the device.
 struct DevState {
   double rz;      // rᵀM⁻¹r of the current PCG iterate
@@ -299,7 +307,8 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
 #define QPG_ONE_PRODUCT \
   static constexpr int NV = 1;
 
-// out = scale · (M v)   (M = Ā, or the whole of B with v = [vp; vat])
+// out = scale · (M v)   (M = Ā, or the whole of B with v = [vp; vat]); with eq set (rows of Ā),
+// out_r = ρ_r/ρ̄ · scale · (M v)_r, i.e. w = RĀv for scale = ρ̄.
 template <typename T>
 struct OpScaled {
   QPG_NO_SIDE
@@ -310,8 +319,11 @@ struct OpScaled {
   const T* v;
   T* out;
   T scale;
+  const uint8_t* eq = nullptr;
   __device__ T gather(int c) const { return v[c]; }
-  __device__ void epilogue(int r, T s1, T s2, T, double*) const { out[r] = scale * (s1 + s2); }
+  __device__ void epilogue(int r, T s1, T s2, T, double*) const {
+    out[r] = row_rho(eq, r, scale) * (s1 + s2);
+  }
 };
 
 // B-part products: P̄ vp + Āᵀ vat (either pointer may be null: that part contributes 0)
@@ -482,20 +494,23 @@ struct OpUpdate {
   T alpha, rho, rho_inv;
   int n;
   DevState* st;
-  T* dxy;  // null, or n + m differences (δx̄, δȳ)
+  T* dxy;              // null, or n + m differences (δx̄, δȳ)
+  const uint8_t* eq;   // null (R = ρ̄I), or the equality-row flags of R = diag(ρ_i)
   __device__ T gather(int c) const { return xt[c]; }
   __device__ void epilogue(int i, T s1, T, T, double* red) const {
+    const bool e = eq && eq[i];
+    const T ri = e ? T(kRhoEq) * rho : rho, ri_inv = e ? rho_inv / T(kRhoEq) : rho_inv;
     const T zi = z[i], yi = y[i];
     const T v = alpha * s1 + (T(1) - alpha) * zi;
-    T zn = v + yi * rho_inv;
+    T zn = v + yi * ri_inv;
     zn = zn < lb[i] ? lb[i] : zn;
     zn = zn > ub[i] ? ub[i] : zn;
-    const T yn = yi + rho * (v - zn);
+    const T yn = yi + ri * (v - zn);
     if (dxy) dxy[n + i] = yn - yi;
     y[i] = yn;
     z[i] = zn;
     zt[i] = s1;
-    gp[n + i] = pair_t<T>{rho * (s1 - zn) + yn, rho * zn - yn};
+    gp[n + i] = pair_t<T>{ri * (s1 - zn) + yn, ri * zn - yn};
     if (ax) {
       const T a = alpha * s1 + (T(1) - alpha) * ax[i];
       ax[i] = a;
@@ -722,14 +737,17 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
     p[i] = -(r[i] * dinv[i]) + b * p[i];
 }
 
-// Jacobi preconditioner (Section 6.3.1): M⁻¹_ii = 1 / (diag(P̄)_i + σ + ρ̄‖Ā_i‖²).
+// Jacobi preconditioner (Section 6.3.1): M⁻¹_ii = 1 / (diag(P̄)_i + σ + ρ̄‖Ā_i‖²); with
+// R = diag(ρ_i), (ĀᵀRĀ)_ii = ρ̄(‖Ā_i‖² + (10³ − 1)·Σ_{equality rows k} Ā_ki²).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
                                                    const double* __restrict__ diagP,
                                                    const double* __restrict__ colsq, double sigma,
-                                                   double rho) {
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-    dinv[i] = (T)(1.0 / (diagP[i] + sigma + rho * colsq[i]));
+                                                   double rho, const double* __restrict__ colsq_eq) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const double c = colsq_eq ? colsq[i] + (kRhoEq - 1.0) * colsq_eq[i] : colsq[i];
+    dinv[i] = (T)(1.0 / (diagP[i] + sigma + rho * c));
+  }
 }
 
 // The pairs read by OpRhsR0: (x̃, 0) for the n P̄ columns, (ρ̄(z̃ − z) + y, ρ̄z − y) for the m
@@ -737,13 +755,15 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pairs(int n, int m, pair_t<T>* __restrict__ gp,
                                                   const T* __restrict__ xt, const T* __restrict__ zt,
-                                                  const T* __restrict__ z, const T* __restrict__ y, T rho) {
+                                                  const T* __restrict__ z, const T* __restrict__ y, T rho,
+                                                  const uint8_t* __restrict__ eq) {
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + m; i += gridDim.x * kBlock) {
     if (i < n) {
       gp[i] = pair_t<T>{xt[i], T(0)};
     } else {
       const int j = i - n;
-      gp[i] = pair_t<T>{rho * (zt[j] - z[j]) + y[j], rho * z[j] - y[j]};
+      const T r = row_rho(eq, j, rho);
+      gp[i] = pair_t<T>{r * (zt[j] - z[j]) + y[j], r * z[j] - y[j]};
     }
   }
 }

@@ -155,6 +155,8 @@ struct HostProblem {
   int32_t scaling_passes = 0;
   std::vector<double> diagP;           // diag(P̄)
   std::vector<double> colsq;           // ‖Ā_j‖₂² = (ĀᵀĀ)_jj  (Section 6.3.1)
+  std::vector<uint8_t> eqrow;          // l_i = u_i (eq. rho_vec); filled when settings.rho_vector
+  std::vector<double> colsq_eq;        // Σ over equality rows i of Ā_ij²; likewise
   double q_norm_unscaled = 0.0;        // ‖q‖∞ of the original data
 };
 

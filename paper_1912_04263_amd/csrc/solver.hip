@@ -125,6 +125,10 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   bool armed = false;
   int k = k_start;
   for (; k <= s.max_iter; ++k) {
+    // PCG tolerance as a decreasing function of k (the alternative Section 6.3.3 attributes to
+    // SCS), when chosen instead of the residual rule: ε_k = max(λ·(k + 1)^(−3/2), ε_min)
+    if (!fixed_eps && s.pcg_eps_schedule == 1)
+      eps_pcg = std::max(s.pcg_lambda * std::pow((double)k + 1.0, -1.5), s.pcg_eps_min);
     // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
     OpRhsR0<T> rr{V.x, V.xt, V.qb, V.gp, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
                   s.pcg_rel_test, eps_pcg, st};
@@ -188,12 +192,12 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     // Between checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a
     // vector pass; a check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
     OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
-                           (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy};
+                           (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
     if (check && ax) {
       OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
-                           (T)rho, (T)(1.0 / rho), n, st, dxy};
+                           (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
       finalize(up, spmv_A<T>(up));
-    } else if (check) {
+    } else if (check || eqrow) {  // with R = diag(ρ_i), z̃ is not carried through PCG
       spmv_A<T>(upd);
     } else {
       hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(grid_for(std::max(n, m))), dim3(kBlock), 0,
@@ -274,7 +278,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       // differences δx̄, δȳ of Section 3 too noisy to pass its tests. After 10 checks without a
       // 1% gain in the worse normalised residual, ε is divided by 10 at every second check.
       if (since_best >= 10 && since_best % 2 == 0) tighten = std::max(tighten * 0.1, 1e-12);
-      if (!fixed_eps) {
+      if (!fixed_eps && s.pcg_eps_schedule == 0) {
         eps_pcg = s.pcg_lambda * std::sqrt(nm[0] * nm[6]);
         if (s.pcg_rel_test) eps_pcg = std::min(eps_pcg, s.pcg_lambda);
         eps_pcg = std::max(eps_pcg * tighten, s.pcg_eps_min);
@@ -460,7 +464,7 @@ int apply_impl(qpg_solver* h, int op, const double* in, double* out) {
       break;
     case QPG_OP_K:
       to_device<T>(h, V.p, in, n);
-      h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)h->rho_cur});
+      h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)h->rho_cur, h->eqrow});
       h->spmv_B<T>(OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, n, h->st});
       from_device<T>(h, out, V.kp, n);
       break;
@@ -500,13 +504,13 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
   auto launch = [&]() {
     switch (kernel) {
       case QPG_KERNEL_SPMV_A:
-        h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)h->rho_cur});
+        h->spmv_A<T>(OpScaled<T>{V.p, V.w, (T)h->rho_cur, h->eqrow});
         break;
       case QPG_KERNEL_SPMV_B:
         h->spmv_B<T>(OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, h->n, h->st});
         break;
       case QPG_KERNEL_SPMV_A_STREAM:
-        h->spmv<T>(h->plan_a, INT32_MAX, 1, OpScaled<T>{V.p, V.w, (T)h->rho_cur}, nullptr, false);
+        h->spmv<T>(h->plan_a, INT32_MAX, 1, OpScaled<T>{V.p, V.w, (T)h->rho_cur, h->eqrow}, nullptr, false);
         break;
       case QPG_KERNEL_SPMV_B_STREAM:
         h->spmv<T>(h->plan_b, h->n, 2, OpKp<T>{V.p, V.w, V.kp, (T)h->s.sigma, h->n, h->st}, nullptr, false);
@@ -638,6 +642,8 @@ int qpg_default_settings(qpg_settings* s) {
   s->spmv_plain_nnz = kPlainNnz;
   s->eps_prim_inf = 1e-4;
   s->eps_dual_inf = 1e-4;
+  s->rho_vector = 0;
+  s->pcg_eps_schedule = 0;
   return QPG_OK;
 }
 
@@ -691,6 +697,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->b_items = h->upload(pb.items);
     h->diagP = h->upload(H.diagP);
     h->colsq = h->upload(H.colsq);
+    if (settings->rho_vector) {
+      h->eqrow = h->upload(H.eqrow);
+      h->colsq_eq = h->upload(H.colsq_eq);
+    }
     std::vector<double> dinv(H.n), einv(H.m);
     for (int i = 0; i < H.n; ++i) dinv[i] = 1.0 / H.D[i];
     for (int i = 0; i < H.m; ++i) einv[i] = 1.0 / H.E[i];

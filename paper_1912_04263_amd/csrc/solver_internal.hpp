@@ -97,6 +97,8 @@ struct qpg_solver {
   int32_t win_cols = 8192;  // LDS gather window capacity (columns)
   int32_t nnzA = 0, nnzB = 0;
   double *diagP = nullptr, *colsq = nullptr, *dscale = nullptr, *escale = nullptr;  // D⁻¹, E⁻¹
+  uint8_t* eqrow = nullptr;     // equality-row flags when R = diag(ρ_i) (eq. rho_vec), else null
+  double* colsq_eq = nullptr;   // Σ over equality rows k of Ā_ki², per column (R = diag(ρ_i) only)
   DevState* st = nullptr;
   DevState* st_host = nullptr;        // mapped pinned host memory, written by finalize kernels
   DevState* st_mirror_dev = nullptr;  // its device-side address
@@ -218,7 +220,7 @@ struct qpg_solver {
   template <typename T>
   void jacobi(double rho) {
     hipLaunchKernelGGL((k_jacobi<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, P<T>().dinv, diagP,
-                       colsq, s.sigma, rho);
+                       colsq, s.sigma, rho, (const double*)colsq_eq);
   }
 
   // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set. With
@@ -227,12 +229,12 @@ struct qpg_solver {
   void pcg_iteration(double rho, bool track_zt, bool mirror) {
     Prec<T>& V = P<T>();
     const int32_t* gate = &st->done;
-    spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho}, gate);
+    spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho, eqrow}, gate);
     OpKp<T> kp{V.p, V.w, V.kp, (T)s.sigma, n, st};
     finalize(kp, spmv_B<T>(kp, gate), gate);
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.xt, V.r, V.p,
                        V.kp, V.dinv, (const DevState*)st, rb.partials, gate, m,
-                       track_zt ? V.zt : (T*)nullptr, (const T*)V.w, (T)(1.0 / rho));
+                       (track_zt && !eqrow) ? V.zt : (T*)nullptr, (const T*)V.w, (T)(1.0 / rho));
     finalize_fn<2, 2u>(FinPcgUpdate{st}, vgrid, gate, mirror);
     hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, V.r, V.dinv,
                        (const DevState*)st, gate);
@@ -262,7 +264,7 @@ struct qpg_solver {
   template <typename T>
   int pcg_solve(double rho, int maxit) {
     Prec<T>& V = P<T>();
-    spmv_A<T>(OpScaled<T>{V.xt, V.w, (T)rho});
+    spmv_A<T>(OpScaled<T>{V.xt, V.w, (T)rho, eqrow});
     OpR0<T> r0{V.xt, V.w, V.b, V.dinv, V.r, V.p, (T)s.sigma, n, maxit, st};
     finalize(r0, spmv_B<T>(r0));
     return pcg_loop<T>(rho, maxit);
@@ -272,7 +274,8 @@ struct qpg_solver {
   void pairs(double rho) {
     Prec<T>& V = P<T>();
     hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(n + m)), dim3(kBlock), 0, stream, n, m, V.gp,
-                         (const T*)V.xt, (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho);
+                         (const T*)V.xt, (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho,
+                         (const uint8_t*)eqrow);
   }
 
   template <typename T>

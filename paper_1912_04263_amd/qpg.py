@@ -47,7 +47,8 @@ class Settings(C.Structure):
                 ("device", C.c_int32), ("stream", C.c_void_p), ("verbose", C.c_int32),
                 ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32),
                 ("spmv_tile_nnz", C.c_int32), ("spmv_plain_nnz", C.c_int32),
-                ("eps_prim_inf", C.c_double), ("eps_dual_inf", C.c_double)]
+                ("eps_prim_inf", C.c_double), ("eps_dual_inf", C.c_double), ("rho_vector", C.c_int32),
+                ("pcg_eps_schedule", C.c_int32)]
 
 
 class Info(C.Structure):

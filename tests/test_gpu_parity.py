@@ -201,6 +201,47 @@ def test_admm_iterates_match_oracle_trace(name):
                 assert np.max(np.abs(got - want)) <= 1e-8 * max(1.0, np.max(np.abs(want))), k
 
 
+@pytest.mark.parametrize("name", ["lasso_small", "huber_small", "portfolio_small"])
+def test_admm_iterates_with_vector_rho_match_oracle_trace(name):
+    """R = diag(ρ_i), ρ_i = 10³ρ̄ on equality rows (eq. rho_vec): the GPU's K, Jacobi diagonal and
+    updates against the oracle's direct solves with the same R."""
+    say("admm trace, vector rho", name)
+    p = problem(name)
+    assert np.any(p.l == p.u)
+    K = 10
+    ref = o_admm.solve(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, eps_abs=0.0, eps_rel=0.0,
+                       max_iter=K, adaptive_rho=False, record=K, r_mode="vector")
+    for k in (1, 3, 10):
+        st = qpg.default_settings(rho_update_every=0, pcg_eps_fixed=1e-13, pcg_max_iter=5000,
+                                  check_every=10000, max_iter=k, rho_vector=1)
+        with qpg.Solver.from_qp(p, settings=st) as s:
+            s.solve()
+            xk, zk, yk = ref.trace[k - 1]
+            for got, want in ((s.x(), xk), (s.z(), zk), (s.y(), yk)):
+                assert np.max(np.abs(got - want)) <= 1e-8 * max(1.0, np.max(np.abs(want))), k
+
+
+@pytest.mark.parametrize("name", ["lasso_small", "equality_small"])
+def test_vector_rho_operator_and_final_answer(name):
+    say("vector rho operator + answer", name)
+    p = problem(name)
+    ref = oracle_solution(name)
+    with qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5, max_iter=20000, rho_vector=1) as s:
+        D, E, c, Pb, Ab = scaled_data(s, p)
+        s.set_rho(0.37)
+        eq = (p.l == p.u).astype(float)
+        r = 0.37 * (1.0 + 999.0 * eq)
+        v = np.random.default_rng(7).standard_normal(s.n)
+        want = Pb @ v + 1e-6 * v + Ab.T @ (r * (Ab @ v))
+        got = s.apply(qpg.QPG_OP_K, v)
+        scale = np.abs(Pb) @ np.abs(v) + 1e-6 * np.abs(v) + abs(Ab).T @ (r * (abs(Ab) @ np.abs(v)))
+        assert np.max(np.abs(got - want) / scale) <= 1e-11
+        info = s.solve()
+        assert info.status == "solved"
+        assert abs(info.obj_val - ref.obj) <= 1e-4 * max(1.0, abs(ref.obj))
+        assert np.max(np.abs(s.x() - ref.x)) <= 1e-3 * np.max(np.abs(ref.x))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", PROBLEMS)
 def test_final_answer_matches_oracle(name, precision):
@@ -355,3 +396,17 @@ def test_full_size_sampled_spmv_and_kkt_certificate(name, eps, kw):
     if not kw:
         sampled_spmv_check(p, rows=100)
     kkt_certificate(p, eps, **kw)
+
+
+@pytest.mark.parametrize("name", ["lasso_small", "huber_small"])
+def test_pcg_tolerance_schedule_final_answer(name):
+    """The ε(k) schedule (settings.pcg_eps_schedule = 1) changes only how accurately each step is
+    solved: the final answer still matches the oracle."""
+    say("eps schedule", name)
+    p = problem(name)
+    ref = oracle_solution(name)
+    with qpg.Solver.from_qp(p, eps_abs=1e-5, eps_rel=1e-5, max_iter=20000, pcg_eps_schedule=1) as s:
+        info = s.solve()
+        assert info.status == "solved"
+        assert abs(info.obj_val - ref.obj) <= 1e-4 * max(1.0, abs(ref.obj))
+        assert np.max(np.abs(s.x() - ref.x)) <= 1e-3 * np.max(np.abs(ref.x))
