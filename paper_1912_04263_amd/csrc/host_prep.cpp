@@ -1,5 +1,5 @@
-// Host-side preparation: input validation, CSC → CSR conversions, modified Ruiz
-// equilibration (Algorithm 2) and the SpMV work schedule.
+// Host-side preparation: input validation and the CSC → CSR conversions (full P from its upper
+// triangle, A, and B = [P | Aᵀ]); the values stay unscaled (equilibration runs on the device).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -153,11 +153,6 @@ void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& w
   });
 }
 
-double guard_norm(double v) {
-  // A vanishing norm (empty column or row) leaves its scaling at 1; large norms are capped.
-  if (!(v >= 1e-4)) return 1.0;
-  return std::min(v, 1e4);
-}
 
 }  // namespace
 
@@ -331,127 +326,20 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
   hvec<int32_t>().swap(p_col);
   hvec<double>().swap(p_val);
 
-  // ---- modified Ruiz equilibration (Algorithm 2), applied incrementally to Ā (CSR) and to B,
-  // whose left part is P̄ and right part Āᵀ.
-  // Readings: P̄ ← c·DPD (so that P̄ = cDPD holds after every pass); stop after a pass whose δ
-  // satisfies ‖1 − δ‖∞ ≤ 1e-3, at most scaling_iters passes; norms below 1e-4 count as 1 and
-  // are capped at 1e4 (also for the denominator of γ).
-  std::vector<double>& D = H.D;
-  std::vector<double>& E = H.E;
-  D.assign(n, 1.0);
-  E.assign(m, 1.0);
+  // ---- q, and the bounds with infinities clamped to ±kInf (Ruiz equilibration, Algorithm 2,
+  // runs on the device on these raw values)
   H.qb.assign(q, q + n);
-  double c = 1.0;
-  H.scaling_passes = 0;
-  std::vector<double> dD(n), dE(m), nx(n), nz(m);
-  // largest value over chunked per-index results (max is exact, so the order does not matter)
-  auto chunk_max = [](int64_t len, const std::function<double(int64_t)>& f) {
-    const int64_t nc = (len + kRows - 1) / kRows;
-    std::vector<double> part((size_t)std::max<int64_t>(nc, 1), 0.0);
-    parallel_chunks(len, kRows, [&](int64_t ci, int64_t lo, int64_t hi) {
-      double mx = 0.0;
-      for (int64_t i = lo; i < hi; ++i) mx = std::max(mx, f(i));
-      part[ci] = mx;
-    });
-    return *std::max_element(part.begin(), part.end());
-  };
-  // per-row ∞-norms of B's entries [k0(r), k1(r)) into out
-  auto row_max = [&](std::vector<double>& out, int64_t rows, const std::function<int32_t(int64_t)>& k0,
-                     const std::function<int32_t(int64_t)>& k1, const hvec<double>& v) {
-    parallel_chunks(rows, kRows, [&](int64_t, int64_t lo, int64_t hi) {
-      for (int64_t r = lo; r < hi; ++r) {
-        double mx = 0.0;
-        for (int32_t k = k0(r), e = k1(r); k < e; ++k) mx = std::max(mx, std::fabs(v[k]));
-        out[r] = mx;
-      }
-    });
-  };
-  auto b_row0 = [&](int64_t i) { return H.b_ptr[i]; };
-  auto b_row1 = [&](int64_t i) { return H.b_ptr[i + 1]; };
-  auto b_mid = [&](int64_t i) { return H.b_split[i]; };
-  for (int32_t pass = 0; pass < s->scaling_iters; ++pass) {
-    H.scaling_passes++;
-    // column ∞-norms of M = [P̄ Āᵀ; Ā 0]: column j ≤ n is column j of P̄ and of Ā = row j of B;
-    // column n + i is row i of Ā
-    row_max(nx, n, b_row0, b_row1, H.b_val);
-    row_max(nz, m, [&](int64_t i) { return H.a_ptr[i]; }, [&](int64_t i) { return H.a_ptr[i + 1]; }, H.a_val);
-    const double dev = std::max(chunk_max(n,
-                                          [&](int64_t j) {
-                                            dD[j] = 1.0 / std::sqrt(guard_norm(nx[j]));
-                                            D[j] *= dD[j];
-                                            return std::fabs(1.0 - dD[j]);
-                                          }),
-                                chunk_max(m, [&](int64_t i) {
-                                  dE[i] = 1.0 / std::sqrt(guard_norm(nz[i]));
-                                  E[i] *= dE[i];
-                                  return std::fabs(1.0 - dE[i]);
-                                }));
-    parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
-      for (int64_t i = lo; i < hi; ++i) {
-        int32_t k = H.b_ptr[i];
-        for (; k < H.b_split[i]; ++k) H.b_val[k] = (H.b_val[k] * dD[i]) * dD[H.b_col[k]];
-        for (; k < H.b_ptr[i + 1]; ++k) H.b_val[k] = (H.b_val[k] * dE[H.b_col[k] - n]) * dD[i];
-      }
-    });
-    parallel_chunks(m, kRows, [&](int64_t, int64_t lo, int64_t hi) {
-      for (int64_t i = lo; i < hi; ++i)
-        for (int32_t k = H.a_ptr[i]; k < H.a_ptr[i + 1]; ++k)
-          H.a_val[k] = (H.a_val[k] * dE[i]) * dD[H.a_col[k]];
-    });
-    const double qmax = chunk_max(n, [&](int64_t j) {
-      H.qb[j] *= dD[j];
-      return std::fabs(H.qb[j]);
-    });
-    // cost scaling γ = 1 / max(mean_j ‖P̄_j‖∞, ‖q̄‖∞); the column norms in parallel, their sum
-    // in index order
-    row_max(nx, n, b_row0, b_mid, H.b_val);
-    double mean = 0.0;
-    for (int32_t j = 0; j < n; ++j) mean += nx[j];
-    mean /= (double)n;
-    const double gamma = 1.0 / guard_norm(std::max(mean, qmax));
-    parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
-      for (int64_t i = lo; i < hi; ++i)
-        for (int32_t k = H.b_ptr[i]; k < H.b_split[i]; ++k) H.b_val[k] *= gamma;
-    });
-    for (auto& v : H.qb) v *= gamma;
-    c *= gamma;
-    if (dev <= 1e-3) break;
-  }
-  H.c = c;
-
-  // ---- bounds: clamp infinities, then scale l̄ = El, ū = Eu
   H.lb.resize(m);
   H.ub.resize(m);
   for (int32_t i = 0; i < m; ++i) {
-    double li = std::max(l[i], -kInf), ui = std::min(u[i], kInf);
-    H.lb[i] = E[i] * li;
-    H.ub[i] = E[i] * ui;
+    H.lb[i] = std::max(l[i], -kInf);
+    H.ub[i] = std::min(u[i], kInf);
   }
-
-  // ---- diag(P̄) and the squared column norms of Ā (Section 6.3.1) from the rows of B; with
-  // R = diag(ρ_i) (eq. rho_vec) also the equality rows' share of them
-  const bool rvec = s->rho_vector != 0;
-  if (rvec) {
+  // equality rows, for R = diag(ρ_i) (eq. rho_vec)
+  if (s->rho_vector) {
     H.eqrow.assign(m, 0);
     for (int32_t i = 0; i < m; ++i) H.eqrow[i] = (l[i] == u[i]) ? 1 : 0;
-    H.colsq_eq.assign(n, 0.0);
   }
-  H.diagP.assign(n, 0.0);
-  H.colsq.assign(n, 0.0);
-  parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi; ++i) {
-      for (int32_t k = H.b_ptr[i]; k < H.b_split[i]; ++k)
-        if (H.b_col[k] == i) H.diagP[i] = H.b_val[k];
-      double sq = 0.0, sq_eq = 0.0;
-      for (int32_t k = H.b_split[i]; k < H.b_ptr[i + 1]; ++k) {
-        const double v2 = H.b_val[k] * H.b_val[k];
-        sq += v2;
-        if (rvec && H.eqrow[H.b_col[k] - n]) sq_eq += v2;
-      }
-      H.colsq[i] = sq;
-      if (rvec) H.colsq_eq[i] = sq_eq;
-    }
-  });
   double qn = 0.0;
   for (int32_t i = 0; i < n; ++i) qn = std::max(qn, std::fabs(q[i]));
   H.q_norm_unscaled = qn;

@@ -137,26 +137,20 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
 // in chunk order are the same on every machine.
 void parallel_chunks(int64_t n, int64_t chunk, const std::function<void(int64_t, int64_t, int64_t)>& f);
 
-// The problem after validation, format conversion and Ruiz equilibration, all on the host.
+// The problem after validation and format conversion on the host, values unscaled.
 struct HostProblem {
   int32_t n = 0, m = 0;
-  // Ā in CSR (m rows, n columns)
+  // A in CSR (m rows, n columns)
   std::vector<int32_t> a_ptr;
   hvec<int32_t> a_col;
   hvec<double> a_val;
-  // B = [P̄ | Āᵀ] in CSR (n rows, n + m columns): row i holds row i of the full P̄ (columns
-  // 0..n−1) followed by row i of Āᵀ (columns n + j); b_split[i] is where the Āᵀ part starts.
+  // B = [P | Aᵀ] in CSR (n rows, n + m columns): row i holds row i of the full P (columns
+  // 0..n−1) followed by row i of Aᵀ (columns n + j); b_split[i] is where the Aᵀ part starts.
   std::vector<int32_t> b_ptr, b_split;
   hvec<int32_t> b_col;
   hvec<double> b_val;
-  std::vector<double> qb, lb, ub;      // q̄ = cDq, l̄ = El, ū = Eu (bounds clamped to ±kInf first)
-  std::vector<double> D, E;            // Ruiz factors
-  double c = 1.0;
-  int32_t scaling_passes = 0;
-  std::vector<double> diagP;           // diag(P̄)
-  std::vector<double> colsq;           // ‖Ā_j‖₂² = (ĀᵀĀ)_jj  (Section 6.3.1)
+  std::vector<double> qb, lb, ub;      // q, and l, u clamped to ±kInf
   std::vector<uint8_t> eqrow;          // l_i = u_i (eq. rho_vec); filled when settings.rho_vector
-  std::vector<double> colsq_eq;        // Σ over equality rows i of Ā_ij²; likewise
   double q_norm_unscaled = 0.0;        // ‖q‖∞ of the original data
 };
 

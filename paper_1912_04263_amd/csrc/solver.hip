@@ -2,7 +2,9 @@
 // inexact reduced-KKT PCG step of Section 6.3, termination (Section 3.1), the PCG tolerance
 // rule (Section 6.3.3) and the ρ̄ update (Section 3.4, 6.3.2).
 #include <new>
+#include <thread>
 
+#include "ruiz.hpp"
 #include "solver_internal.hpp"
 
 using namespace qpg;
@@ -35,13 +37,22 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.ready = true;
 }
 
-void qpg_solver::alloc_prec32(const HostProblem& H) {
+// FP32 copies of the equilibrated device data (matrix values in CSR; the SELL copies are placed
+// by place_values).
+void qpg_solver::alloc_prec32() {
   Prec<float>& V = p32;
-  V.a_val = upload_as<float>(H.a_val);
-  V.b_val = upload_as<float>(H.b_val);
-  V.qb = upload_as<float>(H.qb);
-  V.lb = upload_as<float>(H.lb);
-  V.ub = upload_as<float>(H.ub);
+  auto cast = [&](const double* src, size_t count) {
+    float* d = alloc<float>(count);
+    if (count)
+      hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for((int)count)), dim3(kBlock), 0, stream, (int)count,
+                         d, src);
+    return d;
+  };
+  V.a_val = cast(p64.a_val, (size_t)nnzA);
+  V.b_val = cast(p64.b_val, (size_t)nnzB);
+  V.qb = cast(p64.qb, n);
+  V.lb = cast(p64.lb, m);
+  V.ub = cast(p64.ub, m);
   V.x = alloc<float>((size_t)n + m);
   V.y = V.x + n;
   V.xt = alloc<float>(n);
@@ -544,11 +555,14 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
 
 }  // namespace
 
-void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows,
-                            int32_t ncols) {
+TilePlan qpg_solver::plan_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows,
+                               int32_t ncols) const {
   TileParams tp{win_cols, s.spmv_tile_nnz > 0 ? s.spmv_tile_nnz : kTileNnz,
                 s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows};
-  TilePlan t = make_tiles(rowptr, col, nrows, ncols, tp);
+  return make_tiles(rowptr, col, nrows, ncols, tp);
+}
+
+void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows) {
   if (t.tiles.empty()) t.tiles.push_back(Tile{0, 0, 0, 0});
   if (t.comb.empty()) t.comb.push_back(CombItem{0, 0, 0, 0});
   pl.ncomb = (int32_t)t.comb.size();
@@ -576,19 +590,98 @@ void qpg_solver::build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, con
   pl.src = std::move(t.src);
 }
 
-// Values in the plan's SELL order (zero in the padding).
-template <typename T>
-void qpg_solver::place_values(DevPlan& pl, const hvec<double>& csr_val) {
-  hvec<T> v(pl.src.size());
-  parallel_chunks((int64_t)v.size(), 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
-    for (int64_t k = lo; k < hi; ++k) v[k] = pl.src[k] >= 0 ? (T)csr_val[pl.src[k]] : T(0);
-  });
-  T* d = upload(v);
-  HIPCHK(hipStreamSynchronize(stream));
-  if (std::is_same<T, double>::value)
-    pl.val64 = (double*)d;
-  else
-    pl.val32 = (float*)d;
+// Values in the plan's SELL order (zero in the padding), gathered on the device from the
+// equilibrated CSR values through the plan's CSR index of every SELL position; FP32 copies cast
+// from them.
+void qpg_solver::place_values(DevPlan& pl, const double* csr_val, bool fp32) {
+  const size_t count = pl.src.size();
+  int32_t* src = nullptr;
+  HIPCHK(hipMalloc((void**)&src, std::max<size_t>(count, 1) * sizeof(int32_t)));
+  try {
+    if (count) HIPCHK(hipMemcpyAsync(src, pl.src.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    pl.val64 = alloc<double>(count);
+    if (count) {
+      const int g = (int)std::min<size_t>((count + kBlock - 1) / kBlock, 65536);
+      hipLaunchKernelGGL(k_gather_values, dim3(g), dim3(kBlock), 0, stream, (int64_t)count, (const int32_t*)src,
+                         csr_val, pl.val64);
+    }
+    if (fp32) {
+      pl.val32 = alloc<float>(count);
+      if (count)
+        hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for((int)count)), dim3(kBlock), 0, stream,
+                           (int)count, pl.val32, (const double*)pl.val64);
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+  } catch (...) {
+    (void)hipFree(src);
+    throw;
+  }
+  HIPCHK(hipFree(src));
+  hvec<int32_t>().swap(pl.src);
+}
+
+// Modified Ruiz equilibration (Algorithm 2) of the uploaded raw problem, on the device (see
+// ruiz.hpp); then diag(P̄), ‖Ā_i‖², l̄ = El, ū = Eu, D⁻¹, E⁻¹. Readings: P̄ ← c·DPD (so that
+// P̄ = cDPD holds after every pass); stop after a pass whose δ satisfies ‖1 − δ‖∞ ≤ 1e-3, at most
+// scaling_iters passes; norms below 1e-4 count as 1 and are capped at 1e4 (also for the
+// denominator of γ). The host keeps D, E, c, ‖q̄‖∞, diag(P̄) and ‖Ā_i‖².
+void qpg_solver::equilibrate() {
+  Prec<double>& V = p64;
+  const size_t nm = (size_t)n + m;
+  double* work = nullptr;  // D, E, δ_D, δ_E, row norms of B and Ā, P̄ row norms
+  HIPCHK(hipMalloc((void**)&work, (3 * nm + (size_t)n + 1) * sizeof(double)));
+  double *Dd = work, *Ed = Dd + n, *dD = Ed + m, *dE = dD + n, *rB = dE + m, *rA = rB + n, *pB = rA + m;
+  try {
+    fill(Dd, (int)nm, 1.0);  // D and E
+    hipLaunchKernelGGL(k_ruiz_init, dim3(1), dim3(64), 0, stream, st);
+    auto rows_grid = [](int rows) { return std::max(1, std::min((rows + 3) / 4, 16384)); };
+    const int gB = rows_grid(n), gA = rows_grid(m), gv = grid_for((int)nm), gn = grid_for(n);
+    int passes = 0;
+    while (passes < s.scaling_iters) {
+      hipLaunchKernelGGL(k_ruiz_norms_B, dim3(gB), dim3(kBlock), 0, stream, n, (const int32_t*)b_ptr,
+                         (const int32_t*)b_split, V.b_val, (const DevState*)st, rB);
+      if (m)
+        hipLaunchKernelGGL(k_ruiz_norms_A, dim3(gA), dim3(kBlock), 0, stream, m, (const int32_t*)a_ptr,
+                           (const double*)V.a_val, rA);
+      hipLaunchKernelGGL(k_ruiz_delta, dim3(gv), dim3(kBlock), 0, stream, n, m, (const double*)rB,
+                         (const double*)rA, Dd, Ed, dD, dE, V.qb, (const DevState*)st, rb.partials);
+      finalize_fn<2, 3u>(FinRuizDelta{st}, gv);
+      hipLaunchKernelGGL(k_ruiz_scale_B, dim3(gB), dim3(kBlock), 0, stream, n, (const int32_t*)b_ptr,
+                         (const int32_t*)b_split, (const int32_t*)b_col, V.b_val, (const double*)dD,
+                         (const double*)dE, pB);
+      if (m)
+        hipLaunchKernelGGL(k_ruiz_scale_A, dim3(gA), dim3(kBlock), 0, stream, m, (const int32_t*)a_ptr,
+                           (const int32_t*)a_col, V.a_val, (const double*)dD, (const double*)dE);
+      hipLaunchKernelGGL(k_ruiz_pmean, dim3(gn), dim3(kBlock), 0, stream, n, (const double*)pB, rb.partials);
+      finalize_fn<1, 0u>(FinRuizGamma{st, n}, gn, nullptr, true);
+      sync_state();
+      ++passes;
+      if (st_host->norms[kRuizDev] <= 1e-3) break;
+    }
+    hipLaunchKernelGGL(k_ruiz_final_B, dim3(gB), dim3(kBlock), 0, stream, n, (const int32_t*)b_ptr,
+                       (const int32_t*)b_split, (const int32_t*)b_col, V.b_val, (const DevState*)st,
+                       (const uint8_t*)eqrow, diagP, colsq, colsq_eq);
+    hipLaunchKernelGGL(k_ruiz_final_vec, dim3(gv), dim3(kBlock), 0, stream, n, m, V.qb, V.lb, V.ub,
+                       (const double*)Dd, (const double*)Ed, dscale, escale, (const DevState*)st, rb.partials);
+    finalize_fn<1, 1u>(FinRuizFinal{st}, gv, nullptr, true);
+    sync_state();
+    c = st_host->norms[kRuizC];
+    qb_norm = st_host->norms[kRuizQmax];
+    scaling_passes = passes;
+    D.resize(n);
+    E.resize(m);
+    diagP_h.resize(n);
+    colsq_h.resize(n);
+    HIPCHK(hipMemcpyAsync(D.data(), Dd, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    if (m) HIPCHK(hipMemcpyAsync(E.data(), Ed, m * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(diagP_h.data(), diagP, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(colsq_h.data(), colsq, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  } catch (...) {
+    (void)hipFree(work);
+    throw;
+  }
+  HIPCHK(hipFree(work));
 }
 
 extern "C" {
@@ -681,6 +774,31 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
   h->stream = static_cast<hipStream_t>(settings->stream);
   try {
     HIPCHK(hipSetDevice(h->device));
+    // SpMV work lists: the window is sized so that a window of FP64 pairs fits in one
+    // workgroup's LDS. They depend on the sparsity pattern only, so a host thread builds them
+    // while the device equilibrates the values.
+    int lds_max = 0;
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    h->win_cols = kWinCols;
+    while (h->win_cols > 1024 &&
+           (size_t)h->win_cols * sizeof(double2) + 1024 > (size_t)lds_max)
+      h->win_cols >>= 1;
+    TilePlan ta, tb;
+    std::exception_ptr plan_err;
+    std::thread planner([&]() {
+      try {
+        ta = h->plan_tiles(H.a_ptr, H.a_col.data(), H.m, H.n);
+        tb = h->plan_tiles(H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
+      } catch (...) {
+        plan_err = std::current_exception();
+      }
+    });
+    struct Join {  // the planner reads H: it is joined on every way out of this block
+      std::thread& t;
+      ~Join() {
+        if (t.joinable()) t.join();
+      }
+    } join{planner};
     Plan pa = make_plan(H.a_ptr, H.m);
     Plan pb = make_plan(H.b_ptr, H.n);
     for (Plan* pl : {&pa, &pb})
@@ -688,6 +806,8 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->na_items = (int32_t)pa.items.size();
     h->nb_items = (int32_t)pb.items.size();
     h->vgrid = grid_for(h->n);
+    h->nnzA = (int32_t)H.a_col.size();
+    h->nnzB = (int32_t)H.b_col.size();
     h->a_ptr = h->upload(H.a_ptr);
     h->a_col = h->upload(H.a_col);
     h->b_ptr = h->upload(H.b_ptr);
@@ -695,61 +815,43 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->b_col = h->upload(H.b_col);
     h->a_items = h->upload(pa.items);
     h->b_items = h->upload(pb.items);
-    h->diagP = h->upload(H.diagP);
-    h->colsq = h->upload(H.colsq);
+    h->diagP = h->alloc<double>(H.n);
+    h->colsq = h->alloc<double>(H.n);
     if (settings->rho_vector) {
       h->eqrow = h->upload(H.eqrow);
-      h->colsq_eq = h->upload(H.colsq_eq);
+      h->colsq_eq = h->alloc<double>(H.n);
     }
-    std::vector<double> dinv(H.n), einv(H.m);
-    for (int i = 0; i < H.n; ++i) dinv[i] = 1.0 / H.D[i];
-    for (int i = 0; i < H.m; ++i) einv[i] = 1.0 / H.E[i];
-    h->dscale = h->upload(dinv);
-    h->escale = h->upload(einv);
-    // SpMV work lists: the window is sized so that a window of FP64 pairs fits in one
-    // workgroup's LDS
-    int lds_max = 0;
-    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
-    h->win_cols = kWinCols;
-    while (h->win_cols > 1024 &&
-           (size_t)h->win_cols * sizeof(double2) + 1024 > (size_t)lds_max)
-      h->win_cols >>= 1;
-    h->build_plan(h->plan_a, H.a_ptr, H.a_col.data(), H.m, H.n);
-    h->build_plan(h->plan_b, H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
+    h->dscale = h->alloc<double>(H.n);
+    h->escale = h->alloc<double>(H.m);
+    // partials hold up to max(work lists, vector grids) workgroups; the work-list counts are
+    // known once the planner is done, so size them for the vector grids first
     int maxgrid = std::max(1024, std::max(h->na_items, h->nb_items));
-    maxgrid = std::max(maxgrid, std::max(h->plan_a.ncomb, h->plan_b.ncomb));
-    h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
     h->st = h->alloc<DevState>(1);
     HIPCHK(hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream));
     HIPCHK(hipHostMalloc((void**)&h->st_host, sizeof(DevState), hipHostMallocMapped));
     std::memset(h->st_host, 0, sizeof(DevState));
     HIPCHK(hipHostGetDevicePointer((void**)&h->st_mirror_dev, h->st_host, 0));
-    h->alloc_prec64(H);
-    if (settings->precision == QPG_MIXED) h->alloc_prec32(H);
-    for (DevPlan* pl : {&h->plan_a, &h->plan_b}) {
-      const hvec<double>& v = pl == &h->plan_a ? H.a_val : H.b_val;
-      h->place_values<double>(*pl, v);
-      if (settings->precision == QPG_MIXED) h->place_values<float>(*pl, v);
-      hvec<int32_t>().swap(pl->src);
+    h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
+    h->alloc_prec64(H);  // raw values, q, clamped bounds; vectors
+    h->equilibrate();
+    planner.join();
+    if (plan_err) std::rethrow_exception(plan_err);
+    h->upload_plan(h->plan_a, ta, H.a_ptr, H.m);
+    h->upload_plan(h->plan_b, tb, H.b_ptr, H.n);
+    if (std::max(h->plan_a.ncomb, h->plan_b.ncomb) > maxgrid) {
+      maxgrid = std::max(h->plan_a.ncomb, h->plan_b.ncomb);
+      h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
     }
+    if (settings->precision == QPG_MIXED) h->alloc_prec32();
+    h->place_values(h->plan_a, h->p64.a_val, settings->precision == QPG_MIXED);
+    h->place_values(h->plan_b, h->p64.b_val, settings->precision == QPG_MIXED);
     for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);
     for (double* v : {h->p64.z, h->p64.y, h->p64.w, h->p64.zt, h->p64.ax}) h->fill(v, h->m, 0.0);
     if (h->p32.ready) {
       for (float* v : {h->p32.x, h->p32.xt, h->p32.r, h->p32.p, h->p32.kp, h->p32.b}) h->fill(v, h->n, 0.f);
       for (float* v : {h->p32.z, h->p32.y, h->p32.w, h->p32.zt}) h->fill(v, h->m, 0.f);
     }
-    h->nnzA = (int32_t)H.a_col.size();
-    h->nnzB = (int32_t)H.b_col.size();
-    h->diagP_h = H.diagP;
-    h->colsq_h = H.colsq;
-    h->D = H.D;
-    h->E = H.E;
-    h->c = H.c;
     h->q_norm = H.q_norm_unscaled;
-    double qbn = 0.0;
-    for (double v : H.qb) qbn = std::max(qbn, std::fabs(v));
-    h->qb_norm = qbn;
-    h->scaling_passes = H.scaling_passes;
     h->rho_cur = settings->rho;
     h->jacobi<double>(h->rho_cur);
     if (h->p32.ready) h->jacobi<float>(h->rho_cur);

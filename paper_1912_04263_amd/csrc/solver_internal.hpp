@@ -297,12 +297,13 @@ struct qpg_solver {
   void keep_certificate();
 
   int solve();
-  void build_plan(DevPlan& pl, const std::vector<int32_t>& rowptr, const int32_t* col,
-                  int32_t nrows, int32_t ncols);
-  template <typename T>
-  void place_values(DevPlan& pl, const qpg::hvec<double>& csr_val);
+  TilePlan plan_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows,
+                      int32_t ncols) const;
+  void upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows);
+  void place_values(DevPlan& pl, const double* csr_val, bool fp32);
   void alloc_prec64(const HostProblem& H);
-  void alloc_prec32(const HostProblem& H);
+  void alloc_prec32();
+  void equilibrate();
 };
 
 template <>
