@@ -31,14 +31,13 @@ __device__ __forceinline__ T row_rho(const uint8_t* eq, int i, T rho) {
 
 // Scalars of the iteration that live on the device.
 struct DevState {
-  double rz;      // rᵀM⁻¹r of the current PCG iterate
+  double rzp[2];  // rᵀM⁻¹r of the current PCG iterate, indexed by the iteration's parity
   double alpha;   // PCG step length
   double beta;    // PCG direction update
   double kappa;   // pᵀKp
   double bnorm;   // ‖b‖∞
   double rnorm;   // ‖r‖∞
   double thresh;  // PCG stopping threshold on ‖r‖∞
-  double pad0;
   int32_t iter;       // PCG iterations of the current solve
   int32_t done;       // PCG finished (converged, capped or broken down)
   int32_t breakdown;  // pᵀKp ≤ 0 / NaN or rᵀM⁻¹r NaN seen
@@ -49,7 +48,8 @@ struct DevState {
 };
 
 struct RedBuf {
-  double* partials;  // [workgroups][kMaxSlots], read by the following k_finalize
+  double* partials;   // [workgroups][kMaxSlots], read by the following k_finalize or vector kernel
+  double* vpartials;  // the same for k_pcg_update, which reads `partials` of the B pass meanwhile
 };
 
 // NaN-propagating max (a NaN residual must not disappear inside a norm).
@@ -385,7 +385,7 @@ struct OpRhsR0 {
   __device__ void operator()(const double* t) const {
     st->bnorm = t[0];
     st->thresh = rel ? eps * t[0] : eps;
-    st->rz = t[1];
+    st->rzp[0] = t[1];
     st->rnorm = t[2];
     st->iter = 0;
     st->maxit = maxit;
@@ -422,7 +422,7 @@ struct OpR0 {
     red[1] = nmax(red[1], fabs((double)ri));
   }
   __device__ void operator()(const double* t) const {
-    st->rz = t[0];
+    st->rzp[0] = t[0];
     st->rnorm = t[1];
     st->iter = 0;
     st->maxit = maxit;
@@ -431,11 +431,13 @@ struct OpR0 {
   }
 };
 
-// PCG K-matvec, second half: Kp = P̄p + σp + Āᵀw (w = ρ̄Āp); κ = pᵀKp; α = rᵀM⁻¹r / κ.
+// PCG K-matvec, second half: Kp = P̄p + σp + Āᵀw (w = ρ̄Āp) and the partials of κ = pᵀKp, which
+// k_pcg_update combines.
 // p and w are the two parts of one allocation (w = p + n), so column c of B gathers p[c].
 template <typename T>
 struct OpKp {
   QPG_NO_SIDE
+  QPG_NO_FIN
   QPG_ONE_PRODUCT
   static constexpr int NS = 1;
   static constexpr unsigned MAXMASK = 0u;
@@ -451,18 +453,6 @@ struct OpKp {
     const T k = s1 + s2 + sigma * pi;
     kp[i] = k;
     red[0] += (double)pi * (double)k;
-  }
-  __device__ void operator()(const double* t) const {
-    st->kappa = t[0];
-    if (t[0] > 0.0) {
-      st->alpha = st->rz / t[0];
-    } else {
-      // with M⁻¹ positive, p = 0 only when r = 0 (an exact solve); any other pᵀKp ≤ 0 or NaN
-      // is a breakdown
-      st->alpha = 0.0;
-      st->done = 1;
-      if (!(t[0] == 0.0 && st->rnorm == 0.0)) st->breakdown = 1;
-    }
   }
 };
 
@@ -670,7 +660,34 @@ struct OpInfeasB {
 
 // -------------------------------------------------------------------------------- vector kernels
 
-// PCG update (Algorithm 3): x̃ += αp; r += αKp; y = M⁻¹r (not stored); rᵀy; ‖r‖∞.
+// Every workgroup combines the same `count` published partials in the same fixed order (thread
+// t takes workgroups t, t + 256, …, then a fixed tree), so all of them hold identical totals:
+// the scalar step that a separate finalize kernel would take runs redundantly in each.
+template <int NS, unsigned MAXMASK>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int count, double (&tot)[NS]) {
+  __shared__ double lds[kMaxSlots * 4];
+  __shared__ double res[kMaxSlots];
+  double v[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) v[s] = 0.0;
+  for (int b = threadIdx.x; b < count; b += kBlock) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = comb<MAXMASK>(s, v[s], partials[(size_t)b * kMaxSlots + s]);
+  }
+  block_reduce<NS, MAXMASK>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) res[s] = v[s];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) tot[s] = res[s];
+}
+
+// PCG update (Algorithm 3), iteration `it` of the solve: κ = pᵀKp from the B pass's partials,
+// α = rᵀM⁻¹r / κ; x̃ += αp; r += αKp; y = M⁻¹r (not stored); partials of rᵀy and ‖r‖∞ for
+// k_pcg_dir. With M⁻¹ positive, κ ≤ 0 means r = 0 (an exact solve) or a breakdown; α = 0 then,
+// and k_pcg_dir ends the solve.
 // With zt set, z̃ = Āx̃ follows x̃: z̃ += α·Āp, with Āp = w/ρ̄ from this iteration's Ā pass, so the
 // ADMM update after PCG needs no SpMV of its own.
 template <typename T>
@@ -679,12 +696,22 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt
                                                        const T* __restrict__ p,
                                                        const T* __restrict__ kp,
                                                        const T* __restrict__ dinv,
-                                                       const DevState* st, double* partials,
+                                                       DevState* st, const double* __restrict__ kp_partials,
+                                                       int kp_count, double* __restrict__ partials,
                                                        const int32_t* __restrict__ gate, int m,
                                                        T* __restrict__ zt, const T* __restrict__ w,
-                                                       T rho_inv) {
+                                                       T rho_inv, int it) {
   if (gate && *gate) return;
-  const T a = (T)st->alpha;
+  double kap[1];
+  reduce_partials<1, 0u>(kp_partials, kp_count, kap);
+  const double kappa = kap[0];
+  const double alpha = kappa > 0.0 ? st->rzp[it & 1] / kappa : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->kappa = kappa;
+    st->alpha = alpha;
+    if (!(kappa > 0.0) && !(kappa == 0.0 && st->rnorm == 0.0)) st->breakdown = 1;
+  }
+  const T a = (T)alpha;
   double red[2] = {0.0, 0.0};
   const int total = zt ? (n > m ? n : m) : n;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
@@ -710,31 +737,38 @@ __global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__
   op.side();
 }
 
-// β = r⁺ᵀy⁺ / rᵀy, iteration count and the stopping flag (run by k_finalize).
-struct FinPcgUpdate {
-  DevState* st;
-  __device__ void operator()(const double* t) const {
-    const double rz_new = t[0];
-    st->beta = rz_new / st->rz;
-    st->rz = rz_new;
-    st->rnorm = t[1];
-    st->iter += 1;
-    if (rz_new != rz_new) st->breakdown = 1;
-    st->done = (t[1] <= st->thresh || st->iter >= st->maxit || st->breakdown) ? 1 : 0;
-  }
-};
-
-// PCG direction: p = −M⁻¹r + βp.
+// PCG direction (Algorithm 3), iteration `it`: β = r⁺ᵀy⁺ / rᵀy from k_pcg_update's partials;
+// p = −M⁻¹r + βp. Workgroup 0 stores the new rᵀy under the next parity, β, ‖r‖∞, the iteration
+// count and the stopping flag, and mirrors the scalars to the host when asked (also when the
+// iteration is gated off). Other workgroups read only the previous parity's rᵀy, so no value is
+// read while it is written; one that sees the stopping flag already set skips its share of p,
+// which is not used once the solve has stopped.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
                                                     const T* __restrict__ r,
                                                     const T* __restrict__ dinv,
-                                                    const DevState* st,
-                                                    const int32_t* __restrict__ gate) {
-  if (gate && *gate) return;
-  const T b = (T)st->beta;
+                                                    DevState* st, const double* __restrict__ partials,
+                                                    int count, const int32_t* __restrict__ gate, int it,
+                                                    DevState* mirror) {
+  if (gate && *gate) {
+    if (mirror && blockIdx.x == 0 && threadIdx.x == 0) *mirror = *st;
+    return;
+  }
+  double t[2];
+  reduce_partials<2, 2u>(partials, count, t);
+  const double rz_new = t[0], beta = rz_new / st->rzp[it & 1];
+  const T b = (T)beta;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
     p[i] = -(r[i] * dinv[i]) + b * p[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->rzp[(it + 1) & 1] = rz_new;
+    st->beta = beta;
+    st->rnorm = t[1];
+    st->iter = it + 1;
+    if (rz_new != rz_new) st->breakdown = 1;
+    st->done = (t[1] <= st->thresh || it + 1 >= st->maxit || st->breakdown || !(st->kappa > 0.0)) ? 1 : 0;
+    if (mirror) *mirror = *st;
+  }
 }
 
 // Jacobi preconditioner (Section 6.3.1): M⁻¹_ii = 1 / (diag(P̄)_i + σ + ρ̄‖Ā_i‖²); with

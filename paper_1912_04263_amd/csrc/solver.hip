@@ -528,12 +528,14 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
         break;
       case QPG_KERNEL_PCG_UPDATE:
         hipLaunchKernelGGL((k_pcg_update<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.xt,
-                           V.r, V.p, V.kp, V.dinv, (const DevState*)h->st, h->rb.partials,
-                           (const int32_t*)nullptr, h->m, V.zt, (const T*)V.w, (T)(1.0 / h->rho_cur));
+                           V.r, V.p, V.kp, V.dinv, h->st, (const double*)h->rb.partials, h->plan_b.ncomb,
+                           h->rb.vpartials, (const int32_t*)nullptr, h->m, V.zt, (const T*)V.w,
+                           (T)(1.0 / h->rho_cur), 0);
         break;
       default:
-        hipLaunchKernelGGL((k_pcg_dir<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.p, V.r,
-                           V.dinv, (const DevState*)h->st, (const int32_t*)nullptr);
+        hipLaunchKernelGGL((k_pcg_dir<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.p,
+                           (const T*)V.r, (const T*)V.dinv, h->st, (const double*)h->rb.vpartials, h->vgrid,
+                           (const int32_t*)nullptr, 0, (DevState*)nullptr);
     }
   };
   hipEvent_t e0, e1;
@@ -832,6 +834,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     std::memset(h->st_host, 0, sizeof(DevState));
     HIPCHK(hipHostGetDevicePointer((void**)&h->st_mirror_dev, h->st_host, 0));
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
+    h->rb.vpartials = h->alloc<double>((size_t)1024 * kMaxSlots);
     h->alloc_prec64(H);  // raw values, q, clamped bounds; vectors
     h->equilibrate();
     planner.join();
