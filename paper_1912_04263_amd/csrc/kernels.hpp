@@ -42,8 +42,12 @@ struct DevState {
   int32_t done;       // PCG finished (converged, capped or broken down)
   int32_t breakdown;  // pᵀKp ≤ 0 / NaN or rᵀM⁻¹r NaN seen
   int32_t maxit;      // PCG iteration cap
-  uint32_t pad1;
-  uint32_t pad2;
+  // speculative ADMM iterations (launched without a host read between them)
+  int32_t abort;         // set when one of them needs the host: everything after it is skipped
+  int32_t abort_k;       // the ADMM iteration that set it
+  int32_t abort_reason;  // 1 PCG not finished within the launched iterations, 2 breakdown, 3 capped
+  int32_t pcg_sum;       // PCG iterations of the completed speculative ADMM iterations
+  int32_t pcg_max;       // and their largest count
   double norms[24];   // residual-check outputs (OpRPrim / OpRDual: 0..13, OpInfeasA/B: 16..22)
 };
 
@@ -169,6 +173,50 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict
 template <class S>
 __global__ void k_mirror(const S* st, S* mirror) {
   if (threadIdx.x == 0) *mirror = *st;
+}
+
+// After the PCG iterations launched for speculative ADMM iteration k: when the solve has not
+// finished, broke down or hit the cap, set the abort flag (which gates every later kernel of the
+// speculation, and the PCG kernels through `done`) so that the host takes over from iteration k;
+// otherwise count the iterations.
+template <class S>
+__global__ void k_after_pcg(S* st, int k) {
+  if (threadIdx.x != 0 || st->abort) return;
+  const int it = st->iter;
+  int reason = 0;
+  if (st->breakdown)
+    reason = 2;
+  else if (!st->done)
+    reason = 1;
+  else if (it >= st->maxit && st->rnorm > st->thresh)
+    reason = 3;
+  if (reason) {
+    st->abort = 1;
+    st->abort_k = k;
+    st->abort_reason = reason;
+    st->done = 1;
+  } else {
+    st->pcg_sum += it;
+    if (it > st->pcg_max) st->pcg_max = it;
+  }
+}
+
+// The host resumes after an abort: clear it, and reopen the PCG solve when it was cut short.
+template <class S>
+__global__ void k_resume(S* st, int reopen) {
+  if (threadIdx.x != 0) return;
+  st->abort = 0;
+  if (reopen) st->done = 0;
+}
+
+template <class S>
+__global__ void k_spec_reset(S* st) {
+  if (threadIdx.x != 0) return;
+  st->abort = 0;
+  st->abort_k = 0;
+  st->abort_reason = 0;
+  st->pcg_sum = 0;
+  st->pcg_max = 0;
 }
 
 template <typename T>
@@ -730,7 +778,9 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt
 // An SpMV operation's row epilogue and side task without the SpMV: the row values s1 are given
 // (used by the ADMM update when z̃ = Āx̃ is already known).
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__ s1, Op op) {
+__global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__ s1, Op op,
+                                                 const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;
   double red[1] = {0.0};
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < rows; i += gridDim.x * kBlock)
     op.epilogue(i, s1[i], T(0), T(0), red);

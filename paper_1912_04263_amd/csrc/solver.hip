@@ -134,17 +134,102 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // infeasible problem ends up; on a converging problem they would only add cost.
   constexpr int kInfeasAfter = 2;
   bool armed = false;
+  // Speculation: an ADMM iteration without a check or a trial is launched without waiting for
+  // its PCG solve. Its PCG runs a predicted number of iterations (the last count seen), then
+  // k_after_pcg sets st->abort if the solve is unfinished, broke down or hit the cap; every later
+  // kernel of the speculation is gated on that flag (the PCG kernels through `done`). The host
+  // reads the state at the next check (or before a trial) and, after an abort, resumes at the
+  // iteration that set it, whose state is exactly what its PCG iterations left. So the host
+  // waits once per check instead of once per ADMM iteration.
+  const int32_t* agate = &st->abort;
+  hipLaunchKernelGGL(k_spec_reset<DevState>, dim3(1), dim3(64), 0, stream, st);
+  bool pending = false;  // speculative iterations launched since the last host read
+  int last_cap_k = -2;
+  auto finish = [&](int kk) {  // st_host is current at every return
+    info.pcg_iter_total += st_host->pcg_sum;
+    info.pcg_iter_max = std::max(info.pcg_iter_max, (int)st_host->pcg_max);
+    last_precond_learned = use_learned;
+    return kk;
+  };
+  // bookkeeping after the PCG solve of iteration kk (it iterations); true: stop the ADMM loop
+  auto after_pcg = [&](int kk, int it) {
+    const bool capped = it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh;
+    if (use_learned && (st_host->breakdown || capped)) {
+      use_learned = false;  // runtime guard
+      info.precond_switches++;
+      jacobi<T>(rho);
+    }
+    info.pcg_iter_total += it;
+    info.pcg_iter_max = std::max(info.pcg_iter_max, it);
+    if (st_host->breakdown) {
+      if (std::is_same<T, float>::value)
+        fallback_request = 1;
+      else
+        status = QPG_NUMERICAL_ERROR;
+      return true;
+    }
+    if (capped) {
+      cap_streak = (kk == last_cap_k + 1) ? cap_streak + 1 : 1;
+      last_cap_k = kk;
+    }
+    if (std::is_same<T, float>::value && cap_streak >= 3) {
+      fallback_request = 1;
+      return true;
+    }
+    return false;
+  };
+  // (a7)–(a8) z̃ = Āx̃ fused with relaxation, projection and dual update; x update; with Āx
+  // tracked (FP64) the primal residual of a check iteration comes out of the same pass. Between
+  // checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a vector pass; a
+  // check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
+  auto launch_update = [&](bool check, T* dxy) {
+    T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
+    OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
+                           (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
+    if (check && ax) {
+      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
+                           (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
+      finalize(up, spmv_A<T>(up, agate), agate);
+    } else if (check || eqrow) {  // with R = diag(ρ_i), z̃ is not carried through PCG
+      spmv_A<T>(upd, agate);
+    } else {
+      hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(grid_for(std::max(n, m))), dim3(kBlock), 0,
+                         stream, m, (const T*)V.zt, upd, agate);
+    }
+  };
+  // after a host read that shows an abort: finish iteration j = abort_k (its PCG, then its
+  // update) and return the iteration to continue from; −1 when the ADMM loop must stop
+  auto resume = [&]() {
+    const int j = st_host->abort_k, reason = st_host->abort_reason;
+    hipLaunchKernelGGL(k_resume<DevState>, dim3(1), dim3(64), 0, stream, st, reason == 1 ? 1 : 0);
+    const int it = reason == 1 ? pcg_loop<T>(rho, s.pcg_max_iter, true, st_host->iter) : st_host->iter;
+    pending = false;
+    if (after_pcg(j, it)) return -1;
+    launch_update(false, nullptr);
+    return j + 1;
+  };
   int k = k_start;
-  for (; k <= s.max_iter; ++k) {
+  int it = 0;
+  while (k <= s.max_iter) {
     // PCG tolerance as a decreasing function of k (the alternative Section 6.3.3 attributes to
     // SCS), when chosen instead of the residual rule: ε_k = max(λ·(k + 1)^(−3/2), ε_min)
     if (!fixed_eps && s.pcg_eps_schedule == 1)
       eps_pcg = std::max(s.pcg_lambda * std::pow((double)k + 1.0, -1.5), s.pcg_eps_min);
+    const bool check = (k % s.check_every == 0 || k == s.max_iter);
     // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
     OpRhsR0<T> rr{V.x, V.xt, V.qb, V.gp, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
                   s.pcg_rel_test, eps_pcg, st};
-    int it;
     if (trial) {
+      if (pending) {  // read the speculation's outcome first
+        hipLaunchKernelGGL(k_mirror<DevState>, dim3(1), dim3(64), 0, stream, (const DevState*)st, st_mirror_dev);
+        sync_state();
+        pending = false;
+        if (st_host->abort) {
+          k = resume();
+          if (k < 0) return finish(st_host->abort_k);
+          continue;
+        }
+      }
       copy(V.b, (const T*)V.xt, n);  // the warm start, kept for the second run
       learned_dinv<T>(rho);
       finalize(rr, spmv_B<T>(rr));
@@ -168,54 +253,35 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       }
       info.pcg_iter_total += it_l;
       trial = false;
+      if (after_pcg(k, it)) return finish(k);
+    } else if (!check) {
+      // speculative: PCG with the predicted iteration count, no host read
+      finalize(rr, spmv_B<T>(rr, agate), agate);
+      const int b = std::max(1, std::min(last_pcg, s.pcg_max_iter));
+      for (int i = 0; i < b; ++i) pcg_iteration<T>(rho, true, false, i);
+      hipLaunchKernelGGL(k_after_pcg<DevState>, dim3(1), dim3(64), 0, stream, st, k);
+      pending = true;
     } else {
-      finalize(rr, spmv_B<T>(rr));
+      finalize(rr, spmv_B<T>(rr, agate), agate);
       // (a3)–(a6) PCG iterations
       it = pcg_loop<T>(rho, s.pcg_max_iter, true);
-      if (use_learned && (st_host->breakdown ||
-                          (it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh))) {
-        use_learned = false;  // runtime guard
-        info.precond_switches++;
-        jacobi<T>(rho);
+      if (st_host->abort) {  // a speculative iteration before this one needs the host
+        k = resume();
+        if (k < 0) return finish(st_host->abort_k);
+        continue;
       }
+      pending = false;
+      if (after_pcg(k, it)) return finish(k);
     }
-    info.pcg_iter_total += it;
-    info.pcg_iter_max = std::max(info.pcg_iter_max, it);
-    if (st_host->breakdown) {
-      if (std::is_same<T, float>::value) {
-        fallback_request = 1;
-        return k;
-      }
-      status = QPG_NUMERICAL_ERROR;
-      last_precond_learned = use_learned;
-      return k;
-    }
-    cap_streak = (it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh) ? cap_streak + 1 : 0;
-    if (std::is_same<T, float>::value && cap_streak >= 3) {
-      fallback_request = 1;
-      return k;
-    }
-    // (a7)–(a8) z̃ = Āx̃ fused with relaxation, projection and dual update; x update; with
-    // Āx tracked (FP64) the primal residual of a check iteration comes out of the same pass
-    const bool check = (k % s.check_every == 0 || k == s.max_iter);
-    T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
     T* dxy = (check && infeas && armed) ? V.dxy : nullptr;  // δx̄, δȳ of this step (Section 3.1)
-    // Between checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a
-    // vector pass; a check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
-    OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
-                           (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
-    if (check && ax) {
-      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
-                           (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
-      finalize(up, spmv_A<T>(up));
-    } else if (check || eqrow) {  // with R = diag(ρ_i), z̃ is not carried through PCG
-      spmv_A<T>(upd);
-    } else {
-      hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(grid_for(std::max(n, m))), dim3(kBlock), 0,
-                         stream, m, (const T*)V.zt, upd);
+    T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
+    launch_update(check, dxy);
+    if (!check) {
+      ++k;
+      continue;
     }
     // (a9) residuals and termination every check_every iterations
-    if (check) {
+    {
       if (!ax) {
         OpRPrim<T> rp{V.x, V.z, escale, st};
         finalize(rp, spmv_A<T>(rp));
@@ -236,18 +302,15 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         std::fprintf(stderr, "qpg %5d  prim %.3e (%.1e)  dual %.3e (%.1e)  rho %.3e  pcg %d  %s\n", k,
                      prim, eps_p, dual, eps_d, rho, it, std::is_same<T, float>::value ? "fp32" : "fp64");
       if (!(prim == prim) || !(dual == dual)) {
-        if (std::is_same<T, float>::value) {
+        if (std::is_same<T, float>::value)
           fallback_request = 1;
-          return k;
-        }
-        status = QPG_NUMERICAL_ERROR;
-        last_precond_learned = use_learned;
-        return k;
+        else
+          status = QPG_NUMERICAL_ERROR;
+        return finish(k);
       }
       if (prim <= eps_p && dual <= eps_d) {
         status = QPG_SOLVED;
-        last_precond_learned = use_learned;
-        return k;
+        return finish(k);
       }
       // infeasibility certificates from the differences of this step (Section 3, 3.1)
       if (dxy) {
@@ -267,8 +330,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         if (inf != QPG_UNSOLVED) {
           keep_certificate<T>();
           status = inf;
-          last_precond_learned = use_learned;
-          return k;
+          return finish(k);
         }
       }
       // FP32 stagnation: no 1% improvement of the worse normalised residual in 20 checks
@@ -278,7 +340,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         since_best = 0;
       } else if (++since_best >= 20 && std::is_same<T, float>::value) {
         fallback_request = 1;
-        return k;
+        return finish(k);
       }
       armed = since_best >= kInfeasAfter;
       // PCG tolerance from the scaled residuals (Section 6.3.3). With the relative test
@@ -317,10 +379,10 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         }
       }
     }
+    ++k;
   }
   status = QPG_MAX_ITER_REACHED;
-  last_precond_learned = use_learned;
-  return std::min(k, s.max_iter);
+  return finish(std::min(k, s.max_iter));
 }
 
 int qpg_solver::solve() {

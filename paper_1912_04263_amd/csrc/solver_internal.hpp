@@ -243,12 +243,13 @@ struct qpg_solver {
   // Run PCG iterations after the initialisation kernel until st->done. The first batch is one
   // shorter than the previous PCG solve took, so that iterations launched after convergence
   // (which exit at once) stay rare; then one iteration per host check. Returns the count.
+  // `start` iterations of this solve have run already (a solve resumed after a speculation).
   template <typename T>
-  int pcg_loop(double rho, int maxit, bool track_zt = false) {
-    int issued = 0;
+  int pcg_loop(double rho, int maxit, bool track_zt = false, int start = 0) {
+    int issued = start;
     int batch = std::max(1, std::min(last_pcg - 1, maxit));
     for (;;) {
-      int k = std::min(batch, maxit - issued);
+      int k = std::max(0, std::min(batch, maxit - issued));
       for (int i = 0; i < k; ++i) pcg_iteration<T>(rho, track_zt, i == k - 1, issued + i);
       if (k == 0) hipLaunchKernelGGL(k_mirror<DevState>, dim3(1), dim3(64), 0, stream, (const DevState*)st, st_mirror_dev);
       issued += k;
