@@ -410,3 +410,18 @@ def test_pcg_tolerance_schedule_final_answer(name):
         assert info.status == "solved"
         assert abs(info.obj_val - ref.obj) <= 1e-4 * max(1.0, abs(ref.obj))
         assert np.max(np.abs(s.x() - ref.x)) <= 1e-3 * np.max(np.abs(ref.x))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_is_bitwise_reproducible(precision):
+    """Speculative ADMM iterations (launched between checks without waiting for the host) and
+    the resumption after a PCG solve that needs more iterations than predicted leave the result
+    independent of timing: two solves agree bitwise."""
+    say("reproducible solve", precision)
+    p = problem("lasso_small")
+    with qpg.Solver.from_qp(p, eps_abs=1e-6, eps_rel=1e-6, max_iter=20000, precision=precision) as s:
+        i1 = s.solve()
+        x1, y1 = s.x(), s.y()
+        i2 = s.solve()
+        assert (i1.iter, i1.pcg_iter_total) == (i2.iter, i2.pcg_iter_total)
+        assert np.array_equal(x1, s.x()) and np.array_equal(y1, s.y())
