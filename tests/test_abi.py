@@ -43,6 +43,9 @@ int main(void) {
          offsetof(qpg_info, scaling_passes), offsetof(qpg_info, precond_switches));
   printf("%zu %zu %zu\n", offsetof(qpg_settings, precond_weights), offsetof(qpg_settings, precond_trial),
          offsetof(qpg_settings, spmv_plain_nnz));
+  printf("%zu %zu %zu %zu\n", offsetof(qpg_settings, eps_prim_inf), offsetof(qpg_settings, eps_dual_inf),
+         offsetof(qpg_settings, rho_vector), offsetof(qpg_settings, pcg_eps_schedule));
+  printf("%zu %d %d\n", offsetof(qpg_info, infeas_checks), QPG_PRIMAL_INFEASIBLE, QPG_DUAL_INFEASIBLE);
   printf("%d\n", QPG_NET_NPARAMS);
   return 0;
 }
@@ -58,7 +61,9 @@ int main(void) {
     want = [C.sizeof(qpg.Csc), C.sizeof(S), C.sizeof(I),
             S.pcg_max_iter.offset, S.stream.offset, S.verbose.offset, S.rho_update_gate.offset,
             I.obj_val.offset, I.solve_time.offset, I.scaling_passes.offset, I.precond_switches.offset,
-            S.precond_weights.offset, S.precond_trial.offset, S.spmv_plain_nnz.offset, qpg.QPG_NET_NPARAMS]
+            S.precond_weights.offset, S.precond_trial.offset, S.spmv_plain_nnz.offset,
+            S.eps_prim_inf.offset, S.eps_dual_inf.offset, S.rho_vector.offset, S.pcg_eps_schedule.offset,
+            I.infeas_checks.offset, qpg.QPG_PRIMAL_INFEASIBLE, qpg.QPG_DUAL_INFEASIBLE, qpg.QPG_NET_NPARAMS]
     assert got == want
 
 
@@ -73,6 +78,8 @@ def test_default_settings_follow_the_paper():
     assert (s.pcg_lambda, s.pcg_eps_min) == (0.15, 1e-7)          # Section 6.3.3
     assert (s.check_every, s.rho_update_every) == (5, 10)         # Section 6.3.2–6.3.3, Table 1
     assert s.precision == qpg.QPG_FP64 and s.pcg_rel_test == 1
+    assert s.rho_vector == 0 and s.pcg_eps_schedule == 0                # R = ρ̄I (Section 6.3)
+    assert (s.eps_prim_inf, s.eps_dual_inf) == (1e-4, 1e-4)
 
 
 def _tiny():
@@ -109,7 +116,10 @@ def test_setup_rejects_unsorted_indices_and_bad_settings():
     h = C.c_void_p()
     rc = L.qpg_setup(C.byref(h), C.byref(Pc.c), qpg._dptr(q), C.byref(Ac), qpg._dptr(l), qpg._dptr(u), C.byref(s))
     assert rc == qpg.QPG_ERR_ARG and b"increasing" in L.qpg_last_error(None)
-    for bad in (dict(alpha=2.0), dict(rho=0.0), dict(check_every=0), dict(precision=7)):
+    w = np.zeros(qpg.QPG_NET_NPARAMS, np.float32)
+    for bad in (dict(alpha=2.0), dict(rho=0.0), dict(check_every=0), dict(precision=7),
+                dict(eps_prim_inf=-1.0), dict(eps_dual_inf=np.inf), dict(rho_vector=2),
+                dict(rho_vector=1, precond="learned", precond_weights=w), dict(pcg_eps_schedule=3)):
         with pytest.raises(qpg.QpgError) as e:
             qpg.Solver(P, q, A, l, u, **bad)
         assert e.value.code == qpg.QPG_ERR_ARG
