@@ -175,13 +175,14 @@ __global__ void k_mirror(const S* st, S* mirror) {
   if (threadIdx.x == 0) *mirror = *st;
 }
 
-// After the PCG iterations launched for speculative ADMM iteration k: when the solve has not
+// After the PCG iterations launched for speculative ADMM iteration k (run by workgroup 0 of the
+// last launched k_pcg_dir, after it has stored the iteration's scalars): when the solve has not
 // finished, broke down or hit the cap, set the abort flag (which gates every later kernel of the
 // speculation, and the PCG kernels through `done`) so that the host takes over from iteration k;
 // otherwise count the iterations.
 template <class S>
-__global__ void k_after_pcg(S* st, int k) {
-  if (threadIdx.x != 0 || st->abort) return;
+__device__ __forceinline__ void after_pcg(S* st, int k) {
+  if (st->abort) return;
   const int it = st->iter;
   int reason = 0;
   if (st->breakdown)
@@ -200,6 +201,7 @@ __global__ void k_after_pcg(S* st, int k) {
     if (it > st->pcg_max) st->pcg_max = it;
   }
 }
+
 
 // The host resumes after an abort: clear it, and reopen the PCG solve when it was cut short.
 template <class S>
@@ -792,16 +794,20 @@ __global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__
 // count and the stopping flag, and mirrors the scalars to the host when asked (also when the
 // iteration is gated off). Other workgroups read only the previous parity's rᵀy, so no value is
 // read while it is written; one that sees the stopping flag already set skips its share of p,
-// which is not used once the solve has stopped.
+// which is not used once the solve has stopped. spec_k ≥ 0: this is the last PCG iteration
+// launched for speculative ADMM iteration spec_k (see after_pcg).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
                                                     const T* __restrict__ r,
                                                     const T* __restrict__ dinv,
                                                     DevState* st, const double* __restrict__ partials,
                                                     int count, const int32_t* __restrict__ gate, int it,
-                                                    DevState* mirror) {
+                                                    DevState* mirror, int spec_k) {
   if (gate && *gate) {
-    if (mirror && blockIdx.x == 0 && threadIdx.x == 0) *mirror = *st;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (spec_k >= 0) after_pcg(st, spec_k);
+      if (mirror) *mirror = *st;
+    }
     return;
   }
   double t[2];
@@ -817,6 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
     st->iter = it + 1;
     if (rz_new != rz_new) st->breakdown = 1;
     st->done = (t[1] <= st->thresh || it + 1 >= st->maxit || st->breakdown || !(st->kappa > 0.0)) ? 1 : 0;
+    if (spec_k >= 0) after_pcg(st, spec_k);
     if (mirror) *mirror = *st;
   }
 }

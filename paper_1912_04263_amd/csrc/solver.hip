@@ -258,8 +258,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       // speculative: PCG with the predicted iteration count, no host read
       finalize(rr, spmv_B<T>(rr, agate), agate);
       const int b = std::max(1, std::min(last_pcg, s.pcg_max_iter));
-      for (int i = 0; i < b; ++i) pcg_iteration<T>(rho, true, false, i);
-      hipLaunchKernelGGL(k_after_pcg<DevState>, dim3(1), dim3(64), 0, stream, st, k);
+      for (int i = 0; i < b; ++i) pcg_iteration<T>(rho, true, false, i, i == b - 1 ? k : -1);
       pending = true;
     } else {
       finalize(rr, spmv_B<T>(rr, agate), agate);
@@ -597,7 +596,7 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
       default:
         hipLaunchKernelGGL((k_pcg_dir<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.p,
                            (const T*)V.r, (const T*)V.dinv, h->st, (const double*)h->rb.vpartials, h->vgrid,
-                           (const int32_t*)nullptr, 0, (DevState*)nullptr);
+                           (const int32_t*)nullptr, 0, (DevState*)nullptr, -1);
     }
   };
   hipEvent_t e0, e1;

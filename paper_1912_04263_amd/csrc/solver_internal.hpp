@@ -226,7 +226,7 @@ struct qpg_solver {
   // One PCG iteration (Algorithm 3), all on the device; skipped once st->done is set. With
   // track_zt, z̃ = Āx̃ is carried along (see k_pcg_update).
   template <typename T>
-  void pcg_iteration(double rho, bool track_zt, bool mirror, int it) {
+  void pcg_iteration(double rho, bool track_zt, bool mirror, int it, int spec_k = -1) {
     Prec<T>& V = P<T>();
     const int32_t* gate = &st->done;
     spmv_A<T>(OpScaled<T>{V.p, V.w, (T)rho, eqrow}, gate);
@@ -237,7 +237,7 @@ struct qpg_solver {
                        (track_zt && !eqrow) ? V.zt : (T*)nullptr, (const T*)V.w, (T)(1.0 / rho), it);
     hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, (const T*)V.r,
                        (const T*)V.dinv, st, (const double*)rb.vpartials, vgrid, gate, it,
-                       mirror ? st_mirror_dev : (DevState*)nullptr);
+                       mirror ? st_mirror_dev : (DevState*)nullptr, spec_k);
   }
 
   // Run PCG iterations after the initialisation kernel until st->done. The first batch is one
@@ -250,7 +250,8 @@ struct qpg_solver {
     int batch = std::max(1, std::min(last_pcg - 1, maxit));
     for (;;) {
       int k = std::max(0, std::min(batch, maxit - issued));
-      for (int i = 0; i < k; ++i) pcg_iteration<T>(rho, track_zt, i == k - 1, issued + i);
+      for (int i = 0; i < k; ++i)
+        pcg_iteration<T>(rho, track_zt, i == k - 1, issued + i);
       if (k == 0) hipLaunchKernelGGL(k_mirror<DevState>, dim3(1), dim3(64), 0, stream, (const DevState*)st, st_mirror_dev);
       issued += k;
       sync_state();
