@@ -425,3 +425,49 @@ def test_solve_is_bitwise_reproducible(precision):
         i2 = s.solve()
         assert (i1.iter, i1.pcg_iter_total) == (i2.iter, i2.pcg_iter_total)
         assert np.array_equal(x1, s.x()) and np.array_equal(y1, s.y())
+
+
+def _edge_qp(seed):
+    """Small random QPs with the structure the kernels special-case: empty rows and columns of A,
+    an all-zero P column (a variable only in constraints), equality rows, one-sided and free
+    bounds, and rows much longer than the others."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(20, 300))
+    m = int(rng.integers(4, 400))
+    M = sp.random(n, n, density=float(rng.uniform(0.01, 0.2)), random_state=rng, format="csr")
+    P = (M @ M.T + 1e-2 * sp.identity(n)).tolil()
+    j = int(rng.integers(n - 1))
+    P[j, :] = 0.0
+    P[:, j] = 0.0
+    P = P.tocsr()
+    A = sp.random(m, n, density=float(rng.uniform(0.005, 0.1)), random_state=rng, format="lil")
+    A[0, :] = 0.0                                        # empty row
+    A[1, :] = rng.standard_normal(n)                     # a full row
+    A[:, n - 1] = 0.0                                    # empty column (kept bounded by P)
+    A[m - 1, :] = 0.0
+    A[m - 1, j] = 1.0                                    # the P-free variable, bounded in [0, 1]
+    A = A.tocsr()
+    q = rng.standard_normal(n)
+    l = -rng.random(m) - 0.1
+    u = rng.random(m) + 0.1
+    eq = rng.random(m) < 0.1
+    l[eq] = u[eq] = 0.0                                  # equality rows
+    free = rng.random(m) < 0.1
+    l[free] = -np.inf                                    # one-sided rows
+    l[m - 1], u[m - 1] = 0.0, 1.0
+    return sp.triu(P, format="csc"), q, sp.csc_matrix(A), l, u
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_edge_structure_final_answers(seed):
+    P_triu, q, A, l, u = _edge_qp(seed)
+    say("edge structure", seed, A.shape)
+    Pf = sp.csr_matrix(P_triu + sp.triu(P_triu, 1).T)
+    ref = o_admm.solve(Pf, q, sp.csr_matrix(A), l, u, eps_abs=1e-9, eps_rel=1e-9, max_iter=50000)
+    assert ref.status == "solved"
+    for precision in ("fp64", "mixed"):
+        with qpg.Solver(P_triu, q, A, l, u, eps_abs=1e-6, eps_rel=1e-6, max_iter=20000, precision=precision) as s:
+            info = s.solve()
+            assert info.status == "solved", (precision, info)
+            assert abs(info.obj_val - ref.obj) <= 1e-4 * max(1.0, abs(ref.obj)), precision
+            assert np.max(np.abs(s.x() - ref.x)) <= 1e-3 * max(1.0, np.max(np.abs(ref.x))), precision
