@@ -471,3 +471,31 @@ def test_edge_structure_final_answers(seed):
             assert info.status == "solved", (precision, info)
             assert abs(info.obj_val - ref.obj) <= 1e-4 * max(1.0, abs(ref.obj)), precision
             assert np.max(np.abs(s.x() - ref.x)) <= 1e-3 * max(1.0, np.max(np.abs(ref.x))), precision
+
+
+def test_mixed_precision_falls_back_to_fp64_on_stagnation():
+    """eps 1e-9 is out of FP32's reach: after 20 checks without progress the solve continues in
+    FP64 from the FP32 iterates and ends at the oracle's answer."""
+    say("fallback: stagnation")
+    p = problem("lasso_small")
+    ref = oracle_solution("lasso_small")
+    with qpg.Solver.from_qp(p, eps_abs=1e-9, eps_rel=1e-9, max_iter=20000, precision="mixed",
+                            pcg_eps_min=1e-12) as s:
+        info = s.solve()
+        assert info.fallback_events == 1 and info.precision_used == "fp64"
+        assert info.status == "solved"
+        assert np.max(np.abs(s.x() - ref.x)) <= 1e-6 * max(1.0, np.max(np.abs(ref.x)))
+
+
+def test_mixed_precision_falls_back_after_three_capped_pcg_solves():
+    """A PCG cap of one iteration under a fixed tight tolerance caps every solve; in FP32 the
+    third capped solve in a row (seen by the host through the speculation's abort flag) moves the
+    solve to FP64, which keeps going with capped solves."""
+    say("fallback: capped PCG")
+    p = problem("random_c0")
+    with qpg.Solver.from_qp(p, precision="mixed", pcg_max_iter=1, pcg_eps_fixed=1e-12, max_iter=400) as s:
+        info = s.solve()
+        assert info.fallback_events == 1 and info.precision_used == "fp64"
+        assert info.iter >= 3 and info.pcg_iter_max == 1
+        # the iteration that requested the fallback runs again in FP64
+        assert info.pcg_iter_total <= info.iter + info.fallback_events
