@@ -499,3 +499,18 @@ def test_mixed_precision_falls_back_after_three_capped_pcg_solves():
         assert info.iter >= 3 and info.pcg_iter_max == 1
         # the iteration that requested the fallback runs again in FP64
         assert info.pcg_iter_total <= info.iter + info.fallback_events
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_indefinite_p_ends_in_a_numerical_error(precision):
+    """With P negative definite, pᵀKp < 0 in the first PCG step: a breakdown, reported as a
+    status (after the FP64 retry in mixed precision) rather than a wrong answer."""
+    say("pcg breakdown", precision)
+    n = 50
+    P = sp.diags(np.full(n, -10.0)).tocsc()
+    rng = np.random.default_rng(8)
+    with qpg.Solver(P, rng.standard_normal(n), sp.identity(n, format="csc"), -np.ones(n), np.ones(n),
+                    precision=precision, scaling_iters=0) as s:
+        info = s.solve()
+        assert info.status == "numerical_error"
+        assert info.fallback_events == (1 if precision == "mixed" else 0)
