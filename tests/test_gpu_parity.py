@@ -514,3 +514,24 @@ def test_indefinite_p_ends_in_a_numerical_error(precision):
         info = s.solve()
         assert info.status == "numerical_error"
         assert info.fallback_events == (1 if precision == "mixed" else 0)
+
+
+@pytest.mark.parametrize("passes", [0, 1, 3])
+@pytest.mark.parametrize("name", ["svm_small", "portfolio_small", "huber_small"])
+def test_device_equilibration_pass_by_pass(name, passes):
+    """Ruiz equilibration on the device (Algorithm 2) after 0, 1 and 3 passes against the oracle's,
+    including the pass count, and the equilibrated matrices themselves through the operators."""
+    say("device ruiz", name, passes)
+    p = problem(name)
+    Do, Eo, co, Pbo, qbo, Abo, npass = o_ruiz.ruiz(p.P_full(), p.q, sp.csr_matrix(p.A), passes)
+    with qpg.Solver.from_qp(p, scaling_iters=passes) as s:
+        D, E, c = s.scaling()
+        np.testing.assert_allclose(D, Do, rtol=1e-12)
+        np.testing.assert_allclose(E, Eo, rtol=1e-12)
+        assert c == pytest.approx(co, rel=1e-12)
+        assert s.info().scaling_passes == npass
+        v = np.random.default_rng(9).standard_normal(s.n)
+        for op, M in ((qpg.QPG_OP_A, Abo), (qpg.QPG_OP_P, Pbo)):
+            got = s.apply(op, v)
+            scale = np.abs(M) @ np.abs(v)
+            assert np.max(np.abs(got - M @ v) / np.maximum(scale, 1e-300)) <= 1e-11
