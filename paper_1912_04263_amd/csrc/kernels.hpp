@@ -395,14 +395,27 @@ struct OpB {
   __device__ void epilogue(int r, T s1, T s2, T, double*) const { out[r] = s1 + s2; }
 };
 
+// Scalars of a right-hand-side pass: ‖b‖∞, the PCG threshold, r⁰ᵀM⁻¹r⁰, ‖r⁰‖∞ and the stopping
+// flag of Algorithm 3's initialisation (the test ‖r‖∞ ≤ ε‖b‖∞, or ≤ ε when rel is 0).
+__device__ inline void rhs_scalars(DevState* st, const double* t, int maxit, int rel, double eps) {
+  st->bnorm = t[0];
+  st->thresh = rel ? eps * t[0] : eps;
+  st->rzp[0] = t[1];
+  st->rnorm = t[2];
+  st->iter = 0;
+  st->maxit = maxit;
+  st->breakdown = (t[1] != t[1]) ? 1 : 0;
+  st->done = (t[2] <= st->thresh || st->breakdown || maxit <= 0) ? 1 : 0;
+}
+
 // Right-hand side of the reduced KKT system (eq. kkt_red_sc) and the warm-started PCG residual
 // (Algorithm 3 initialisation) in one pass over B = [P̄ | Āᵀ]:
-//   b  = σx − q̄ + Āᵀ(ρ̄z − y)                                   (only ‖b‖∞ is needed)
+//   b  = σx − q̄ + Āᵀ(ρ̄z − y)
 //   r⁰ = Kx̃ − b = P̄x̃ + σ(x̃ − x) + q̄ + Āᵀ(ρ̄(z̃ − z) + y),  z̃ = Āx̃
 //   p⁰ = −M⁻¹r⁰;  rᵀM⁻¹r;  ‖r‖∞.
-// The update pass that produced z̃, z and y (OpUpdate) writes one array of n + m pairs: (x̃_i, 0)
-// for the P̄ columns, then (ρ̄(z̃ − z) + y, ρ̄z − y) for the Āᵀ columns, so each entry of B costs
-// a single gather from a single array.
+// The gathered vectors are two planes of n + m entries in one allocation g: plane 0 holds x̃
+// for the P̄ columns, then ρ̄(z̃ − z) + y for the Āᵀ columns; plane 1 holds 0, then ρ̄z − y
+// (written by k_pairs). b is kept in bk for the next right-hand side (OpRhsRec).
 template <typename T>
 struct OpRhsR0 {
   QPG_NO_SIDE
@@ -412,15 +425,16 @@ struct OpRhsR0 {
   const T* x;
   const T* xt;
   const T* qb;
-  const pair_t<T>* gp;  // n + m pairs: (x̃, 0), then (ρ̄(z̃ − z) + y, ρ̄z − y)
+  const T* g;  // two planes of n + m
   const T* dinv;
   T* r;
   T* p;
+  T* bk;
   T sigma;
-  int n, maxit, rel;
+  int n, m, maxit, rel;
   double eps;
   DevState* st;
-  __device__ pair_t<T> gather(int c) const { return gp[c]; }
+  __device__ pair_t<T> gather(int c) const { return pair_t<T>{g[c], g[(size_t)(n + m) + c]}; }
   __device__ void epilogue(int i, T s1, T s2, T s3, double* red) const {
     const T xi = x[i];
     const T bi = sigma * xi - qb[i] + s3;
@@ -428,20 +442,57 @@ struct OpRhsR0 {
     const T yi = ri * dinv[i];
     r[i] = ri;
     p[i] = -yi;
+    bk[i] = bi;
     red[0] = nmax(red[0], fabs((double)bi));
     red[1] += (double)ri * (double)yi;
     red[2] = nmax(red[2], fabs((double)ri));
   }
-  __device__ void operator()(const double* t) const {
-    st->bnorm = t[0];
-    st->thresh = rel ? eps * t[0] : eps;
-    st->rzp[0] = t[1];
-    st->rnorm = t[2];
-    st->iter = 0;
-    st->maxit = maxit;
-    st->breakdown = (t[1] != t[1]) ? 1 : 0;
-    st->done = (t[2] <= st->thresh || st->breakdown || maxit <= 0) ? 1 : 0;
+  __device__ void operator()(const double* t) const { rhs_scalars(st, t, maxit, rel, eps); }
+};
+
+// The same right-hand side and warm-started residual with one product per entry instead of two,
+// from the previous PCG solve (Algorithm 3) of K'x̃ = b' that left x̃ and its residual r' in place,
+// K' = P̄ + σI + ρ̄'ĀᵀĀ. Since r' + b' = K'x̃ and z̃ = Āx̃,
+//   ρ̄Āᵀz̃ = γ(r' + b' − P̄x̃ − σx̃),  γ = ρ̄/ρ̄'   (R = diag(ρ_i) scales by the same γ),
+// and b = σx − q̄ + ρ̄Āᵀz̃ − Āᵀ(ρ̄(z̃ − z) + y). With s1 = P̄x̃ and s2 = Āᵀ(ρ̄(z̃ − z) + y), the
+// sums of plane 0 of g over the two parts of B:
+//   b = σx − q̄ + γ(r' + b' − s1 − σx̃) − s2,   r⁰ = s1 + σ(x̃ − x) + q̄ + s2 (as in OpRhsR0).
+// r⁰ is computed exactly as in OpRhsR0. b differs from the direct value by rounding, by the gap
+// between the recursively updated r' and K'x̃ − b', and by the error b' itself carried; it enters
+// only the stopping threshold ε‖b‖∞ and the next pass (the caller recomputes it directly from time
+// to time). The pass gathers one plane, so its LDS window holds half the bytes of OpRhsR0's.
+template <typename T>
+struct OpRhsRec {
+  QPG_NO_SIDE
+  QPG_ONE_PRODUCT
+  static constexpr int NS = 3;
+  static constexpr unsigned MAXMASK = 0x5u;  // ‖b‖∞, rᵀM⁻¹r, ‖r‖∞
+  const T* x;
+  const T* xt;
+  const T* qb;
+  const T* g;  // plane 0 of the right-hand-side vectors (n + m)
+  const T* dinv;
+  T* r;   // in: r' (n); out: r⁰
+  T* p;
+  T* bk;  // in: b' (n); out: b
+  T sigma, gamma;
+  int maxit, rel;
+  double eps;
+  DevState* st;
+  __device__ T gather(int c) const { return g[c]; }
+  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+    const T xi = x[i], xti = xt[i];
+    const T bi = (sigma * xi - qb[i]) + gamma * (((r[i] + bk[i]) - s1) - sigma * xti) - s2;
+    const T ri = ((s1 + sigma * (xti - xi)) + qb[i]) + s2;
+    const T yi = ri * dinv[i];
+    r[i] = ri;
+    p[i] = -yi;
+    bk[i] = bi;
+    red[0] = nmax(red[0], fabs((double)bi));
+    red[1] += (double)ri * (double)yi;
+    red[2] = nmax(red[2], fabs((double)ri));
   }
+  __device__ void operator()(const double* t) const { rhs_scalars(st, t, maxit, rel, eps); }
 };
 
 // PCG initialisation for a given right-hand side b (Algorithm 3): r = Kx̃ − b with
@@ -508,10 +559,10 @@ struct OpKp {
 
 // ADMM update (Algorithm 1, relaxation, projection and dual steps) fused with z̃ = Āx̃
 // (Section 4) over the rows of Ā:
-//   v = αz̃ + (1−α)z;  z⁺ = Π_[l̄,ū](v + y/ρ̄);  y ← y + ρ̄(v − z⁺);  z̃ kept, and the pair
-//   (ρ̄(z̃ − z⁺) + y⁺, ρ̄z⁺ − y⁺) written for the next OpRhsR0 (after the n pairs (x̃, 0));
+//   v = αz̃ + (1−α)z;  z⁺ = Π_[l̄,ū](v + y/ρ̄);  y ← y + ρ̄(v − z⁺);  z̃ kept, and
+//   ρ̄(z̃ − z⁺) + y⁺ written to plane 0 of the right-hand-side vectors (after the n entries x̃);
 //   Āx ← αz̃ + (1−α)Āx when `ax` is tracked (x ← αx̃ + (1−α)x makes this exact);
-//   side task: x ← αx̃ + (1−α)x, and the pairs (x̃, 0).
+//   side task: x ← αx̃ + (1−α)x, and x̃ into plane 0.
 // With CHECK, the primal residual r̄_p = Āx − z⁺ and its norms are reduced as well:
 // slots ‖r̄_p‖, ‖E⁻¹r̄_p‖, ‖Āx‖, ‖E⁻¹Āx‖, ‖z‖, ‖E⁻¹z‖ → norms[0..5].
 // With dxy set, the iterate differences of this step, δx̄ = x⁺ − x (n) and δȳ = y⁺ − y (m), are
@@ -527,7 +578,7 @@ struct OpUpdate {
   T* y;
   T* zt;
   T* ax;
-  pair_t<T>* gp;  // n + m pairs read by the next OpRhsR0
+  T* g;  // plane 0 of the right-hand-side vectors (n + m), read by the next OpRhsRec / OpRhsR0
   const T* lb;
   const T* ub;
   const double* einv;
@@ -550,7 +601,7 @@ struct OpUpdate {
     y[i] = yn;
     z[i] = zn;
     zt[i] = s1;
-    gp[n + i] = pair_t<T>{ri * (s1 - zn) + yn, ri * zn - yn};
+    g[n + i] = ri * (s1 - zn) + yn;
     if (ax) {
       const T a = alpha * s1 + (T(1) - alpha) * ax[i];
       ax[i] = a;
@@ -572,7 +623,7 @@ struct OpUpdate {
       const T xn = alpha * xti + (T(1) - alpha) * xi;
       x[i] = xn;
       if (dxy) dxy[i] = xn - xi;
-      gp[i] = pair_t<T>{xti, T(0)};
+      g[i] = xti;
     }
   }
   __device__ void operator()(const double* t) const {
@@ -841,20 +892,24 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
   }
 }
 
-// The pairs read by OpRhsR0: (x̃, 0) for the n P̄ columns, (ρ̄(z̃ − z) + y, ρ̄z − y) for the m
-// Āᵀ columns — at the start, after ρ̄ changes, and after the precision switches.
+// Both planes of the right-hand-side vectors read by OpRhsR0 (plane 0 also by OpRhsRec): x̃ and 0
+// for the n P̄ columns, ρ̄(z̃ − z) + y and ρ̄z − y for the m Āᵀ columns. Run before every OpRhsR0
+// pass: the update passes keep only plane 0 current.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pairs(int n, int m, pair_t<T>* __restrict__ gp,
+__global__ __launch_bounds__(kBlock) void k_pairs(int n, int m, T* __restrict__ g,
                                                   const T* __restrict__ xt, const T* __restrict__ zt,
                                                   const T* __restrict__ z, const T* __restrict__ y, T rho,
                                                   const uint8_t* __restrict__ eq) {
+  const size_t ps = (size_t)n + m;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + m; i += gridDim.x * kBlock) {
     if (i < n) {
-      gp[i] = pair_t<T>{xt[i], T(0)};
+      g[i] = xt[i];
+      g[ps + i] = T(0);
     } else {
       const int j = i - n;
       const T r = row_rho(eq, j, rho);
-      gp[i] = pair_t<T>{r * (zt[j] - z[j]) + y[j], r * z[j] - y[j]};
+      g[i] = r * (zt[j] - z[j]) + y[j];
+      g[ps + i] = r * z[j] - y[j];
     }
   }
 }

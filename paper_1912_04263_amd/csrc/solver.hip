@@ -32,7 +32,8 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.z = alloc<double>(m);
   V.zt = alloc<double>(m);
   V.ax = alloc<double>(m);
-  V.gp = alloc<double2>((size_t)n + m);
+  V.bk = alloc<double>(n);
+  V.g = alloc<double>(2 * ((size_t)n + m));
   V.dxy = alloc<double>((size_t)n + m);
   V.ready = true;
 }
@@ -64,7 +65,8 @@ void qpg_solver::alloc_prec32() {
   V.dinv = alloc<float>(n);
   V.z = alloc<float>(m);
   V.zt = alloc<float>(m);
-  V.gp = alloc<float2>((size_t)n + m);
+  V.bk = alloc<float>(n);
+  V.g = alloc<float>(2 * ((size_t)n + m));
   V.dxy = alloc<float>((size_t)n + m);
   V.ready = true;
 }
@@ -184,10 +186,10 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
   auto launch_update = [&](bool check, T* dxy) {
     T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
-    OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale,
+    OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.g, V.lb, V.ub, escale,
                            (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
     if (check && ax) {
-      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.gp, V.lb, V.ub, escale, (T)alpha,
+      OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.g, V.lb, V.ub, escale, (T)alpha,
                            (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
       finalize(up, spmv_A<T>(up, agate), agate);
     } else if (check || eqrow) {  // with R = diag(ρ_i), z̃ is not carried through PCG
@@ -208,6 +210,27 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     launch_update(false, nullptr);
     return j + 1;
   };
+  // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B: from
+  // the previous solve's residual and right-hand side when they are in place (OpRhsRec, one
+  // product per entry), else directly (OpRhsR0, two products, after k_pairs). The recurrence
+  // carries the error of b' (the gap between the recursive and the true residual of each solve)
+  // into b, so b is recomputed directly every kRhsRefresh iterations; in FP64 the carried error
+  // stays at rounding level, in FP32 the refresh bounds it.
+  constexpr int kRhsRefresh = 50;
+  double rho_b = 0.0;  // ρ̄ of the PCG solve whose x̃, r and bk are in place; 0: none
+  auto rhs = [&](const int32_t* gate, int kk) {
+    if (rho_b > 0.0 && kk % kRhsRefresh != 0) {
+      OpRhsRec<T> rc{V.x, V.xt, V.qb, V.g, V.dinv, V.r, V.p, V.bk, (T)sigma, (T)(rho / rho_b),
+                     s.pcg_max_iter, s.pcg_rel_test, eps_pcg, st};
+      finalize(rc, spmv_B<T>(rc, gate), gate);
+    } else {
+      pairs<T>(rho);
+      OpRhsR0<T> rr{V.x, V.xt, V.qb, V.g, V.dinv, V.r, V.p, V.bk, (T)sigma, n, m,
+                    s.pcg_max_iter, s.pcg_rel_test, eps_pcg, st};
+      finalize(rr, spmv_B<T>(rr, gate), gate);
+    }
+    rho_b = rho;
+  };
   int k = k_start;
   int it = 0;
   while (k <= s.max_iter) {
@@ -216,9 +239,6 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     if (!fixed_eps && s.pcg_eps_schedule == 1)
       eps_pcg = std::max(s.pcg_lambda * std::pow((double)k + 1.0, -1.5), s.pcg_eps_min);
     const bool check = (k % s.check_every == 0 || k == s.max_iter);
-    // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B
-    OpRhsR0<T> rr{V.x, V.xt, V.qb, V.gp, V.dinv, V.r, V.p, (T)sigma, n, s.pcg_max_iter,
-                  s.pcg_rel_test, eps_pcg, st};
     if (trial) {
       if (pending) {  // read the speculation's outcome first
         hipLaunchKernelGGL(k_mirror<DevState>, dim3(1), dim3(64), 0, stream, (const DevState*)st, st_mirror_dev);
@@ -232,7 +252,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       }
       copy(V.b, (const T*)V.xt, n);  // the warm start, kept for the second run
       learned_dinv<T>(rho);
-      finalize(rr, spmv_B<T>(rr));
+      rho_b = 0.0;  // both runs start from the same warm start, with the right-hand side direct
+      rhs(nullptr, k);
       const int it_l = pcg_loop<T>(rho, s.pcg_max_iter, true);
       const double rn_l = st_host->rnorm;
       const bool cap_l = it_l >= s.pcg_max_iter && rn_l > st_host->thresh;
@@ -240,7 +261,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       copy(V.xt, (const T*)V.b, n);
       spmv_A<T>(OpScaled<T>{V.xt, V.zt, (T)1});  // z̃ = Āx̃ of the restored warm start
       jacobi<T>(rho);
-      finalize(rr, spmv_B<T>(rr));
+      rho_b = 0.0;
+      rhs(nullptr, k);
       it = pcg_loop<T>(rho, s.pcg_max_iter, true);
       const bool cap_j = it >= s.pcg_max_iter && st_host->rnorm > st_host->thresh;
       use_learned = !broke_l && ((!cap_l && it_l < it) || (cap_l && cap_j && rn_l < st_host->rnorm));
@@ -256,12 +278,12 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       if (after_pcg(k, it)) return finish(k);
     } else if (!check) {
       // speculative: PCG with the predicted iteration count, no host read
-      finalize(rr, spmv_B<T>(rr, agate), agate);
+      rhs(agate, k);
       const int b = std::max(1, std::min(last_pcg, s.pcg_max_iter));
       for (int i = 0; i < b; ++i) pcg_iteration<T>(rho, true, false, i, i == b - 1 ? k : -1);
       pending = true;
     } else {
-      finalize(rr, spmv_B<T>(rr, agate), agate);
+      rhs(agate, k);
       // (a3)–(a6) PCG iterations
       it = pcg_loop<T>(rho, s.pcg_max_iter, true);
       if (st_host->abort) {  // a speculative iteration before this one needs the host

@@ -46,10 +46,13 @@ struct Prec {
   T *x = nullptr, *y = nullptr;  // ADMM iterates: x = xy, y = xy + n
   T *z = nullptr, *xt = nullptr;  // z (m), PCG solution x̃ (n)
   T *r = nullptr, *p = nullptr, *kp = nullptr, *b = nullptr, *dinv = nullptr;  // PCG (n); p = pw
+  T* bk = nullptr;  // right-hand side b of the ADMM iteration's PCG solve (n)
   T* w = nullptr;   // ρ̄Āp (m) = pw + n
   T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
   T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
-  pair_t<T>* gp = nullptr;  // (x̃, 0) (n), then (ρ̄(z̃ − z) + y, ρ̄z − y) (m), for the right-hand side
+  // vectors gathered by the right-hand-side pass, two planes of n + m: x̃ then ρ̄(z̃ − z) + y;
+  // 0 then ρ̄z − y (plane 1 only for OpRhsR0, written by k_pairs)
+  T* g = nullptr;
   T* dxy = nullptr;         // δx̄ (n), then δȳ (m): differences of the last checked ADMM step
   bool ready = false;
 };
@@ -275,7 +278,7 @@ struct qpg_solver {
   template <typename T>
   void pairs(double rho) {
     Prec<T>& V = P<T>();
-    hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(n + m)), dim3(kBlock), 0, stream, n, m, V.gp,
+    hipLaunchKernelGGL((k_pairs<T>), dim3(grid_for(n + m)), dim3(kBlock), 0, stream, n, m, V.g,
                          (const T*)V.xt, (const T*)V.zt, (const T*)V.z, (const T*)V.y, (T)rho,
                          (const uint8_t*)eqrow);
   }

@@ -201,6 +201,30 @@ def test_admm_iterates_match_oracle_trace(name):
                 assert np.max(np.abs(got - want)) <= 1e-8 * max(1.0, np.max(np.abs(want))), k
 
 
+@pytest.mark.parametrize("name", ["svm_small", "control_small"])
+def test_admm_iterates_across_a_rho_update_match_oracle_trace(name):
+    """ρ̄ changes at iteration 10 on both sides (Section 3.4). Iteration 1 forms its right-hand
+    side directly; every later one from the previous solve's residual and right-hand side, and
+    iteration 11 with the factor ρ̄_new/ρ̄_old; the iterates before and after must match."""
+    say("admm trace across a rho update", name)
+    p = problem(name)
+    K = 20
+    ref = o_admm.solve(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, eps_abs=0.0, eps_rel=0.0,
+                       max_iter=K, adaptive_rho=True, rho_interval=10, record=K)
+    assert ref.rho_updates == 1 and ref.rho != 0.1
+    for k in (2, 10, 11, 15, 20):
+        st = qpg.default_settings(rho_update_every=10, check_every=5, pcg_eps_fixed=1e-13,
+                                  pcg_max_iter=5000, max_iter=k)
+        with qpg.Solver.from_qp(p, settings=st) as s:
+            info = s.solve()
+            if 10 <= k < K:  # (the check at k = K may update ρ̄ again, after the iterate)
+                assert info.rho_updates == 1
+                assert abs(info.rho_final - ref.rho) <= 1e-9 * ref.rho
+            xk, zk, yk = ref.trace[k - 1]
+            for got, want in ((s.x(), xk), (s.z(), zk), (s.y(), yk)):
+                assert np.max(np.abs(got - want)) <= 1e-8 * max(1.0, np.max(np.abs(want))), k
+
+
 @pytest.mark.parametrize("name", ["lasso_small", "huber_small", "portfolio_small"])
 def test_admm_iterates_with_vector_rho_match_oracle_trace(name):
     """R = diag(ρ_i), ρ_i = 10³ρ̄ on equality rows (eq. rho_vec): the GPU's K, Jacobi diagonal and
