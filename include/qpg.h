@@ -34,8 +34,10 @@ extern "C" {
 #define QPG_ERR_DATA (-2)   /* NaN or ±inf in P, q or A; NaN in l or u; l_i > u_i */
 #define QPG_ERR_SIZE (-3)   /* a size that overflows the int32 indexing */
 #define QPG_ERR_DEVICE (-4) /* any HIP runtime error (message kept for qpg_last_error) */
-#define QPG_ERR_OOM (-5)    /* device or pinned host allocation failed */
+#define QPG_ERR_OOM (-5)    /* device or host allocation failed */
 #define QPG_ERR_STATE (-6)  /* call not valid in the handle's current state */
+#define QPG_ERR_HOST (-7)   /* other host-side failure, e.g. a worker thread could not start
+                               (message kept for qpg_last_error) */
 
 /* Solver status (qpg_info.status), separate from the error code. */
 #define QPG_UNSOLVED 0

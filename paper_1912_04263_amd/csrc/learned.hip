@@ -345,6 +345,7 @@ int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double r
       h->err = "qpg_hutchinson: probe entries must be +1 or -1";
       return QPG_ERR_ARG;
     }
+  const double rho_restore = h->rho_cur;
   try {
     HIPCHK(hipSetDevice(h->device));
     LearnedState* L = ensure_graph(h);
@@ -378,8 +379,9 @@ int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double r
     std::snprintf(buf, sizeof(buf), "%s failed: %s", e.what, hipGetErrorString(e.code));
     h->err = buf;
     (void)hipGetLastError();
+    h->rho_cur = rho_restore;
     return QPG_ERR_DEVICE;
-  }
+  } QPG_CATCH_HOST(h->err)
   return QPG_OK;
 }
 
@@ -407,6 +409,12 @@ int qpg_net_create(qpg_net** out, const float* params, uint64_t seed, int32_t bf
     int code = net_error(net, e);
     delete net;
     return code;
+  } catch (const std::bad_alloc&) {
+    delete net;
+    return QPG_ERR_OOM;
+  } catch (const std::exception&) {
+    delete net;
+    return QPG_ERR_HOST;
   }
   *out = net;
   return QPG_OK;
@@ -442,7 +450,7 @@ int qpg_net_forward(qpg_net* net, qpg_solver* h, double rho, float* g) {
     HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
     return net_error(net, e);
-  }
+  } QPG_CATCH_HOST(net->err)
   return QPG_OK;
 }
 
@@ -465,7 +473,7 @@ int qpg_net_loss_grad(qpg_net* net, qpg_solver* h, double rho, const float* targ
     HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
     return net_error(net, e);
-  }
+  } QPG_CATCH_HOST(net->err)
   return QPG_OK;
 }
 
@@ -482,7 +490,7 @@ int qpg_net_adam_step(qpg_net* net, float lr) {
     HIPCHK(hipGetLastError());
   } catch (const HipError& e) {
     return net_error(net, e);
-  }
+  } QPG_CATCH_HOST(net->err)
   return QPG_OK;
 }
 

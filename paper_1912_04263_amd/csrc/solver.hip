@@ -781,7 +781,7 @@ int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t re
     return QPG_ERR_STATE;
   } catch (const HipError& e) {
     return device_error(h, e);
-  }
+  } QPG_CATCH_HOST(h->err)
 }
 
 int qpg_spmv_layout(const qpg_solver* h, int32_t matrix, int64_t out[8]) {
@@ -955,6 +955,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     g_setup_error = "host allocation failed";
     delete h;
     return QPG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_setup_error = e.what();
+    delete h;
+    return QPG_ERR_HOST;
   }
   h->info.scaling_passes = h->scaling_passes;
   h->info.setup_time = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -969,7 +973,7 @@ int qpg_solve(qpg_solver* h) {
     return h->solve();
   } catch (const HipError& e) {
     return device_error(h, e);
-  }
+  } QPG_CATCH_HOST(h->err)
 }
 
 int qpg_get_x(const qpg_solver* h, double* x) {
@@ -1035,7 +1039,7 @@ int qpg_apply(qpg_solver* h, int32_t op, int32_t precision, const double* in, do
     return QPG_ERR_ARG;
   } catch (const HipError& e) {
     return device_error(h, e);
-  }
+  } QPG_CATCH_HOST(h->err)
 }
 
 int qpg_pcg(qpg_solver* h, int32_t precision, const double* b, const double* x0, double eps,
@@ -1050,7 +1054,7 @@ int qpg_pcg(qpg_solver* h, int32_t precision, const double* b, const double* x0,
     return QPG_ERR_STATE;
   } catch (const HipError& e) {
     return device_error(h, e);
-  }
+  } QPG_CATCH_HOST(h->err)
 }
 
 int qpg_set_rho(qpg_solver* h, double rho) {
@@ -1063,7 +1067,7 @@ int qpg_set_rho(qpg_solver* h, double rho) {
     HIPCHK(hipStreamSynchronize(h->stream));
   } catch (const HipError& e) {
     return device_error(h, e);
-  }
+  } QPG_CATCH_HOST(h->err)
   return QPG_OK;
 }
 
@@ -1084,6 +1088,7 @@ const char* qpg_error_string(int code) {
     case QPG_ERR_DEVICE: return "HIP device error";
     case QPG_ERR_OOM: return "out of memory";
     case QPG_ERR_STATE: return "invalid state";
+    case QPG_ERR_HOST: return "host-side failure";
     default: return "unknown error";
   }
 }

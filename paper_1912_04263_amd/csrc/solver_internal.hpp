@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <exception>
+#include <new>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -13,6 +16,19 @@
 #include <vector>
 
 #include "kernels.hpp"
+
+// Host exceptions at the C ABI, after the HipError handler of an entry point: allocation
+// failures and any other standard exception become error codes with the message kept in
+// ERRSTR, so that no exception leaves an extern "C" function.
+#define QPG_CATCH_HOST(ERRSTR)                  \
+  catch (const std::bad_alloc&) {               \
+    (ERRSTR) = "host allocation failed";       \
+    return QPG_ERR_OOM;                         \
+  }                                             \
+  catch (const std::exception& e) {             \
+    (ERRSTR) = e.what();                        \
+    return QPG_ERR_HOST;                        \
+  }
 #include "qpg_internal.hpp"
 
 using namespace qpg;
@@ -173,11 +189,19 @@ struct qpg_solver {
            bool combine = true) {
     using G = typename Gathered<Op, T>::type;
     const size_t shmem = (size_t)pl.max_wlen * sizeof(G);
-    static size_t lds_allowed = 0;  // per instantiation: raise the dynamic LDS limit once
-    if (shmem > lds_allowed) {
+    // The dynamic LDS limit is a per-device attribute of each instantiation: raise it once per
+    // device (always, for device ordinals beyond the table).
+    constexpr int kDevTable = 64;
+    static std::atomic<size_t> lds_allowed[kDevTable];
+    const bool tab = device >= 0 && device < kDevTable;
+    if (!tab || shmem > lds_allowed[device].load(std::memory_order_relaxed)) {
       HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<T, Op>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-      lds_allowed = shmem;
+      if (tab) {
+        size_t cur = lds_allowed[device].load(std::memory_order_relaxed);
+        while (cur < shmem && !lds_allowed[device].compare_exchange_weak(cur, shmem)) {
+        }
+      }
     }
     const T* val = std::is_same<T, double>::value ? (const T*)pl.val64 : (const T*)pl.val32;
     hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles, pl.chunks,

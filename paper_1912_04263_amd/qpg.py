@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libqpg.so")
 
 QPG_OK = 0
 QPG_ERR_ARG, QPG_ERR_DATA, QPG_ERR_SIZE, QPG_ERR_DEVICE, QPG_ERR_OOM, QPG_ERR_STATE = -1, -2, -3, -4, -5, -6
+QPG_ERR_HOST = -7
 QPG_UNSOLVED, QPG_SOLVED, QPG_MAX_ITER_REACHED, QPG_NUMERICAL_ERROR = 0, 1, 2, 3
 QPG_PRIMAL_INFEASIBLE, QPG_DUAL_INFEASIBLE = 4, 5
 QPG_FP64, QPG_MIXED = 0, 1

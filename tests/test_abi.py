@@ -125,9 +125,22 @@ def test_setup_rejects_unsorted_indices_and_bad_settings():
         assert e.value.code == qpg.QPG_ERR_ARG
 
 
+def test_header_constants_match_binding():
+    """Every #define QPG_* with an integer value in the header has the same value in qpg.py."""
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(QPG_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text))
+    assert "QPG_ERR_HOST" in defs and len(defs) > 20
+    for name, value in defs.items():
+        assert getattr(qpg, name) == int(value), name
+
+
 def test_error_strings_and_null_handles():
     L = qpg.lib()
     assert L.qpg_error_string(qpg.QPG_ERR_DATA) == b"invalid problem data"
+    codes = [qpg.QPG_ERR_ARG, qpg.QPG_ERR_DATA, qpg.QPG_ERR_SIZE, qpg.QPG_ERR_DEVICE, qpg.QPG_ERR_OOM,
+             qpg.QPG_ERR_STATE, qpg.QPG_ERR_HOST]
+    texts = [L.qpg_error_string(c) for c in codes]
+    assert len(set(texts)) == len(codes) and b"unknown error" not in texts
     assert L.qpg_cleanup(None) == 0
     assert L.qpg_solve(None) == qpg.QPG_ERR_ARG
     assert L.qpg_get_x(None, None) == qpg.QPG_ERR_ARG
