@@ -93,7 +93,7 @@ typedef struct {
   int32_t precond;        /* QPG_PRECOND_JACOBI */
   int32_t device;         /* HIP device ordinal, default 0 */
   void* stream;           /* hipStream_t for all device work, NULL = null stream */
-  int32_t verbose;        /* 1: one line per residual check on stderr */
+  int32_t verbose;        /* 1: one line per setup phase and per residual check on stderr */
   const float* precond_weights; /* QPG_NET_NPARAMS floats for QPG_PRECOND_LEARNED (copied at setup) */
   int32_t precond_trial;  /* 1 (default): before the first PCG solve, and after a ρ̄ change that
                              moves ρ̄ by more than 2× since the last trial, solve once with each

@@ -1,8 +1,12 @@
 // Internal declarations shared by the host preparation code and the device solver.
 #pragma once
 
+#include <sys/mman.h>
+
 #include <cstdint>
+#include <cstdlib>
 #include <functional>
+#include <new>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -32,6 +36,23 @@ struct NoInit : std::allocator<T> {
   template <class U, class... A>
   void construct(U* p, A&&... a) {
     ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+  // Large arrays (the matrix in its several layouts) on transparent huge pages where the kernel
+  // offers them: 2 MB-aligned, advised, so that their first touch takes 512× fewer page faults.
+  static constexpr size_t kHuge = size_t(2) << 20;
+  T* allocate(size_t count) {
+    const size_t bytes = count * sizeof(T);
+    if (bytes < 4 * kHuge) return std::allocator<T>::allocate(count);
+    void* p = std::aligned_alloc(kHuge, (bytes + kHuge - 1) / kHuge * kHuge);
+    if (!p) throw std::bad_alloc();
+    (void)madvise(p, (bytes + kHuge - 1) / kHuge * kHuge, MADV_HUGEPAGE);
+    return static_cast<T*>(p);
+  }
+  void deallocate(T* p, size_t count) {
+    if (count * sizeof(T) < 4 * kHuge)
+      std::allocator<T>::deallocate(p, count);
+    else
+      std::free(p);
   }
 };
 template <class T>

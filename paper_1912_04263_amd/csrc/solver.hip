@@ -834,6 +834,17 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
   }
   *out = nullptr;
   auto t0 = std::chrono::steady_clock::now();
+  // with settings->verbose, the time of each setup phase on stderr (the stream is synchronised
+  // at every mark, so device work is charged to the phase that queued it)
+  auto tmark = t0;
+  auto mark = [&](const char* phase, hipStream_t st) {
+    if (!settings || !settings->verbose) return;
+    if (st) (void)hipStreamSynchronize(st);
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "qpg setup  %-34s %8.1f ms\n", phase,
+                 std::chrono::duration<double, std::milli>(now - tmark).count());
+    tmark = now;
+  };
   HostProblem H;
   std::string msg;
   int rc;
@@ -847,6 +858,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     g_setup_error = msg;
     return rc;
   }
+  mark("host checks, CSC->CSR, B = [P | A^T]", nullptr);
   qpg_solver* h = new (std::nothrow) qpg_solver();
   if (!h) {
     g_setup_error = "host allocation failed";
@@ -906,6 +918,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
       h->eqrow = h->upload(H.eqrow);
       h->colsq_eq = h->alloc<double>(H.n);
     }
+    mark("index uploads", h->stream);
     h->dscale = h->alloc<double>(H.n);
     h->escale = h->alloc<double>(H.m);
     // partials hold up to max(work lists, vector grids) workgroups; the work-list counts are
@@ -919,11 +932,15 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
     h->rb.vpartials = h->alloc<double>((size_t)1024 * kMaxSlots);
     h->alloc_prec64(H);  // raw values, q, clamped bounds; vectors
+    mark("value uploads", h->stream);
     h->equilibrate();
+    mark("equilibration (device)", h->stream);
     planner.join();
     if (plan_err) std::rethrow_exception(plan_err);
+    mark("work lists (wait for the host thread)", nullptr);
     h->upload_plan(h->plan_a, ta, H.a_ptr, H.m);
     h->upload_plan(h->plan_b, tb, H.b_ptr, H.n);
+    mark("work-list uploads", h->stream);
     if (std::max(h->plan_a.ncomb, h->plan_b.ncomb) > maxgrid) {
       maxgrid = std::max(h->plan_a.ncomb, h->plan_b.ncomb);
       h->rb.partials = h->alloc<double>((size_t)maxgrid * kMaxSlots);
@@ -931,6 +948,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     if (settings->precision == QPG_MIXED) h->alloc_prec32();
     h->place_values(h->plan_a, h->p64.a_val, settings->precision == QPG_MIXED);
     h->place_values(h->plan_b, h->p64.b_val, settings->precision == QPG_MIXED);
+    mark("values into SELL order", h->stream);
     for (double* v : {h->p64.x, h->p64.xt, h->p64.r, h->p64.p, h->p64.kp, h->p64.b}) h->fill(v, h->n, 0.0);
     for (double* v : {h->p64.z, h->p64.y, h->p64.w, h->p64.zt, h->p64.ax}) h->fill(v, h->m, 0.0);
     if (h->p32.ready) {
@@ -947,6 +965,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
+    mark("vectors, preconditioner", nullptr);
   } catch (const HipError& e) {
     int code = device_error(nullptr, e);
     delete h;

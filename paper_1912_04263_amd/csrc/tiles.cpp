@@ -160,34 +160,42 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
 
   // Row block [b0, b1) with ranges cut at cut[0..K] and windows (wlen 0: none): for each row and
   // range, the entries left of the window, inside it, and right of it, in column order.
-  std::vector<int32_t> bnd;
-  std::vector<std::vector<Seg>> wsegs;
-  auto add_block = [&](int32_t b0, int32_t b1, const std::vector<int64_t>& cut, const std::vector<int32_t>& wlo,
-                       const std::vector<int32_t>& wlen, std::vector<std::vector<Seg>>* by_range = nullptr) {
-    const int32_t K = (int32_t)cut.size() - 1, Rb = b1 - b0;
+  struct Block {
+    int32_t b0, b1;
+    std::vector<int32_t> wlo, wlen;
+  };
+  // bounds of every row of a block (3K + 1 entry positions per row, binary searches) and the
+  // number of segments each row is cut into; reads the matrix only
+  auto bounds = [&](const Block& bl, int32_t K, int32_t* bnd, int32_t* np, const std::vector<int64_t>& cut) {
     const int32_t stride = 3 * K + 1;
-    bnd.assign((size_t)Rb * stride, 0);
-    for (int32_t i = 0; i < Rb; ++i) {
-      const int32_t r = b0 + i;
-      int32_t* B = &bnd[(size_t)i * stride];
-      int32_t np = 0;
+    for (int32_t i = 0; i < bl.b1 - bl.b0; ++i) {
+      const int32_t r = bl.b0 + i;
+      int32_t* B = bnd + (size_t)i * stride;
+      int32_t c = 0;
       for (int32_t j = 0; j < K; ++j) {
         const int32_t a = j == 0 ? rowptr[r] : seek(r, cut[j]);
         const int32_t e = j == K - 1 ? rowptr[r + 1] : seek(r, cut[j + 1]);
-        const int32_t ia = wlen[j] > 0 ? std::max(a, seek(r, wlo[j])) : e;
-        const int32_t ie = wlen[j] > 0 ? std::min(e, seek(r, (int64_t)wlo[j] + wlen[j])) : e;
+        const int32_t ia = bl.wlen[j] > 0 ? std::max(a, seek(r, bl.wlo[j])) : e;
+        const int32_t ie = bl.wlen[j] > 0 ? std::min(e, seek(r, (int64_t)bl.wlo[j] + bl.wlen[j])) : e;
         B[3 * j] = a;
         B[3 * j + 1] = ia;
         B[3 * j + 2] = ie;
         B[3 * j + 3] = e;
-        np += pieces(a, ia) + pieces(ia, ie) + pieces(ie, e);
+        c += pieces(a, ia) + pieces(ia, ie) + pieces(ie, e);
       }
-      plan.rowslot[r + 1] = plan.rowslot[r] + np;
+      np[i] = c;
     }
+  };
+  // slots, segments and tiles of a block from its bounds, in row order
+  std::vector<std::vector<Seg>> wsegs;
+  auto emit = [&](const Block& bl, int32_t K, const int32_t* bnd, const int32_t* np,
+                  std::vector<std::vector<Seg>>* by_range) {
+    const int32_t stride = 3 * K + 1, Rb = bl.b1 - bl.b0;
+    for (int32_t i = 0; i < Rb; ++i) plan.rowslot[bl.b0 + i + 1] = plan.rowslot[bl.b0 + i] + np[i];
     wsegs.assign(K, {});
     for (int32_t i = 0; i < Rb; ++i) {
-      const int32_t* B = &bnd[(size_t)i * stride];
-      int32_t next = plan.rowslot[b0 + i];
+      const int32_t* B = bnd + (size_t)i * stride;
+      int32_t next = plan.rowslot[bl.b0 + i];
       for (int32_t j = 0; j < K; ++j) {
         std::vector<Seg>& out = by_range ? (*by_range)[j] : plain;
         const size_t before = out.size();
@@ -198,9 +206,41 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
           for (size_t q = before; q < plain.size(); ++q) plain_entries += plain[q].len;
       }
     }
-    for (int32_t j = 0; j < K; ++j) add_tile(wsegs[j], wlo[j], wlen[j]);
+    for (int32_t j = 0; j < K; ++j) add_tile(wsegs[j], bl.wlo[j], bl.wlen[j]);
     flush_plain(false);
   };
+  // The blocks of one run, in batches of bounded size: the window decision (`decide`) and the
+  // bounds of the blocks of a batch are computed in parallel, then the blocks are emitted in
+  // order, so the work list does not depend on the number of threads.
+  std::vector<int32_t> bbuf, npbuf;
+  auto run_blocks = [&](std::vector<Block>& blocks, const std::vector<int64_t>& cut,
+                        std::vector<std::vector<Seg>>* by_range, const auto& decide) {
+    const int32_t K = (int32_t)cut.size() - 1, stride = 3 * K + 1;
+    constexpr int64_t kBatchInts = int64_t(1) << 24;
+    size_t j0 = 0;
+    while (j0 < blocks.size()) {
+      std::vector<int64_t> off(1, 0), roff(1, 0);
+      size_t j1 = j0;
+      while (j1 < blocks.size()) {
+        const int64_t rb = blocks[j1].b1 - blocks[j1].b0;
+        if (j1 > j0 && off.back() + rb * stride > kBatchInts) break;
+        off.push_back(off.back() + rb * stride);
+        roff.push_back(roff.back() + rb);
+        ++j1;
+      }
+      bbuf.resize((size_t)off.back());
+      npbuf.resize((size_t)roff.back());
+      parallel_chunks((int64_t)(j1 - j0), 1, [&](int64_t q, int64_t, int64_t) {
+        Block& bl = blocks[j0 + q];
+        decide(bl);
+        bounds(bl, K, bbuf.data() + off[q], npbuf.data() + roff[q], cut);
+      });
+      for (size_t q = 0; q < j1 - j0; ++q)
+        emit(blocks[j0 + q], K, bbuf.data() + off[q], npbuf.data() + roff[q], by_range);
+      j0 = j1;
+    }
+  };
+  const auto keep = [](Block&) {};
 
   // rows per block: about `target` entries, and at least one full chunk of segments
   auto block_rows = [&](int64_t target, double seg_entries) {
@@ -290,20 +330,22 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       cut[K] = ncols;
       const double aseg = (double)covS / (double)(rows_g * K);
       const int32_t R = block_rows(tile_nnz, aseg);
+      std::vector<Block> blocks;
       for (int32_t b0 = g0; b0 < g1; b0 += R) {
         const int32_t b1 = std::min(g1, b0 + R), Rb = b1 - b0;
-        std::vector<int32_t> wlo(K, 0), wlen(K, 0);
+        Block bl{b0, b1, std::vector<int32_t>(K, 0), std::vector<int32_t>(K, 0)};
         for (int32_t j = 0; j < K; ++j) {
           const int32_t w0 = (int32_t)(S[j] << sh);
           const int32_t wl = (int32_t)std::min<int64_t>(wcap, (int64_t)ncols - w0);
           // entries of this block in the window ≈ its share of the run's count
           if (cntS[j] * Rb / rows_g * 16 >= wl) {
-            wlo[j] = w0;
-            wlen[j] = wl;
+            bl.wlo[j] = w0;
+            bl.wlen[j] = wl;
           }
         }
-        add_block(b0, b1, cut, wlo, wlen);
+        blocks.push_back(std::move(bl));
       }
+      run_blocks(blocks, cut, nullptr, keep);
     } else if (S2.size() >= 2 && 2 * covS2 >= nnz_g && 2 * best < nnz_g) {
       // ---- multi-range blocks without windows, tiles issued range by range
       const int32_t K = (int32_t)S2.size();
@@ -313,8 +355,10 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       cut[K] = ncols;
       const int32_t R = block_rows(plain_nnz, (double)covS2 / (double)(rows_g * K));
       std::vector<std::vector<Seg>> by_range(K);
-      const std::vector<int32_t> none(K, 0);
-      for (int32_t b0 = g0; b0 < g1; b0 += R) add_block(b0, std::min(g1, b0 + R), cut, none, none, &by_range);
+      std::vector<Block> blocks;
+      for (int32_t b0 = g0; b0 < g1; b0 += R)
+        blocks.push_back(Block{b0, std::min(g1, b0 + R), std::vector<int32_t>(K, 0), std::vector<int32_t>(K, 0)});
+      run_blocks(blocks, cut, &by_range, keep);
       for (int32_t j = 0; j < K; ++j) {
         std::vector<Seg>& v = by_range[j];
         size_t i = 0;
@@ -335,34 +379,37 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       const int32_t R = block_rows(target, avg);
       const int64_t run_lo = best_lo, run_hi = best_hi;
       const std::vector<int64_t> cut = {0, (int64_t)ncols};
-      for (int32_t b0 = g0; b0 < g1; b0 += R) {
-        const int32_t b1 = std::min(g1, b0 + R);
-        const int64_t nb = (int64_t)rowptr[b1] - rowptr[b0];
+      // the block's whole column span as its window when it fits, else the run's densest window
+      // when that holds half of the block's entries
+      auto decide = [&](Block& bl) {
+        const int64_t nb = (int64_t)rowptr[bl.b1] - rowptr[bl.b0];
         int32_t cmin = ncols, cmax = -1;
         int64_t in_run = 0;
-        for (int32_t r = b0; r < b1; ++r) {
+        for (int32_t r = bl.b0; r < bl.b1; ++r) {
           const int32_t a = rowptr[r], e = rowptr[r + 1];
           if (a == e) continue;
           cmin = std::min(cmin, col[a]);
           cmax = std::max(cmax, col[e - 1]);
           if (window_run) in_run += seek(r, run_hi) - seek(r, run_lo);
         }
-        std::vector<int32_t> wlo(1, 0), wlen(1, 0);
         if (cmax >= 0 && (int64_t)cmax - cmin + 1 <= wcap) {
           if (nb * 16 >= (int64_t)cmax - cmin + 1) {
-            wlo[0] = cmin;
-            wlen[0] = cmax - cmin + 1;
+            bl.wlo[0] = cmin;
+            bl.wlen[0] = cmax - cmin + 1;
           }
         } else if (window_run && 2 * in_run >= nb) {
           const int32_t a = (int32_t)std::max<int64_t>(run_lo, cmin);
           const int32_t e = (int32_t)std::min<int64_t>(run_hi, (int64_t)cmax + 1);
           if (e > a && in_run * 16 >= e - a) {
-            wlo[0] = a;
-            wlen[0] = e - a;
+            bl.wlo[0] = a;
+            bl.wlen[0] = e - a;
           }
         }
-        add_block(b0, b1, cut, wlo, wlen);
-      }
+      };
+      std::vector<Block> blocks;
+      for (int32_t b0 = g0; b0 < g1; b0 += R)
+        blocks.push_back(Block{b0, std::min(g1, b0 + R), std::vector<int32_t>(1, 0), std::vector<int32_t>(1, 0)});
+      run_blocks(blocks, cut, nullptr, decide);
     }
     g0 = g1;
   }
