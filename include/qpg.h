@@ -162,8 +162,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
  * the checks that follow two checks in a row without a 1% gain in the worse normalised residual),
  * or max_iter is reached. After ten such checks the PCG tolerance is divided by 10 at every second
  * check (a stall guard, not in the paper: infeasible problems keep the residuals, and with them
- * the tolerance of Section 6.3.3, large). The status is in qpg_info; reaching max_iter or
- * detecting infeasibility is not an error. */
+ * the tolerance of Section 6.3.3, large). The ‖b‖∞ of each PCG stopping test is formed from the
+ * previous PCG solve's residual and right-hand side (an identity of the reduced system), and
+ * directly at a solve's first iteration and every 50th. The status is in qpg_info; reaching
+ * max_iter or detecting infeasibility is not an error. */
 int qpg_solve(qpg_solver* h);
 
 /* Infeasibility certificate of the last solve (status QPG_PRIMAL_INFEASIBLE or

@@ -331,6 +331,18 @@ def test_unconstrained_without_constraints():
         np.testing.assert_allclose(s.x(), -np.linalg.solve(P, p.q), rtol=1e-6, atol=1e-6)
 
 
+def test_verbose_reports_setup_phases_and_checks(capfd):
+    say("verbose output")
+    p = problem("lasso_small")
+    with qpg.Solver.from_qp(p, verbose=1, max_iter=5) as s:
+        s.solve()
+    err = capfd.readouterr().err
+    for phase in ("host checks", "index uploads", "value uploads", "equilibration (device)", "work lists",
+                  "work-list uploads", "values into SELL order", "vectors, preconditioner"):
+        assert f"qpg setup  {phase}" in err, phase
+    assert "qpg     5  prim" in err
+
+
 def test_repeat_solves_are_bitwise_identical():
     say("determinism")
     p = problem("lasso_small")
