@@ -76,3 +76,25 @@ def test_scalar_case_matches_the_oracle_operator():
     b_rec = sigma * x - q + (rho / rho_old) * ((r_prev + b_prev) - s1 - sigma * xt) - s2
     b_def = o_pcg.reduced_rhs(A, q, sigma, rho, x, z, y)
     assert np.abs(b_rec - b_def).max() <= 1e-12 * max(1.0, np.abs(b_def).max())
+
+
+def test_planted_mistakes_fail_the_identity():
+    """Plausible slips in the formula (γ dropped, σx̃ dropped, γ applied to the Āᵀ term as well,
+    the Āᵀ term's sign flipped) each miss the defined b by far more than the tolerance above."""
+    P, A, _, q, x, xt, z, y = random_problem(3)
+    sigma, rho_old, rho = 1e-6, 0.3, 0.7
+    R_old, R = rho_old * np.ones(A.shape[0]), rho * np.ones(A.shape[0])
+    gamma = rho / rho_old
+    b_prev = rhs(A, q, sigma, R_old, x + 0.1, z - 0.2, y + 0.3)
+    r_prev = kkt(P, A, sigma, R_old) @ xt - b_prev
+    s1, s2 = P @ xt, A.T @ (R * (A @ xt - z) + y)
+    b_def = rhs(A, q, sigma, R, x, z, y)
+    size = np.abs(b_def).max() + np.abs(gamma * (r_prev + b_prev)).max() + np.abs(s2).max()
+    slips = {
+        "gamma dropped": sigma * x - q + ((r_prev + b_prev) - s1 - sigma * xt) - s2,
+        "sigma*xt dropped": sigma * x - q + gamma * ((r_prev + b_prev) - s1) - s2,
+        "gamma on s2": sigma * x - q + gamma * ((r_prev + b_prev) - s1 - sigma * xt) - gamma * s2,
+        "s2 sign": sigma * x - q + gamma * ((r_prev + b_prev) - s1 - sigma * xt) + s2,
+    }
+    for name, b in slips.items():
+        assert np.abs(b - b_def).max() > 1e3 * 1e-13 * size, name
