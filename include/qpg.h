@@ -79,7 +79,7 @@ typedef struct {
   double alpha;           /* relaxation α ∈ (0, 2) (Section 3.4), default 1.6 */
   double eps_abs;         /* absolute tolerance of the termination test, default 1e-3 */
   double eps_rel;         /* relative tolerance of the termination test, default 1e-3 */
-  int32_t max_iter;       /* ADMM iteration cap, default 4000 */
+  int32_t max_iter;       /* ADMM iteration cap, default 100000 */
   int32_t check_every;    /* residual/termination check cadence (Section 6.3.3), default 5 */
   int32_t rho_update_every; /* ρ̄ update cadence in iterations (Section 6.3.2), default 10; 0 = fixed ρ̄ */
   double rho_update_gate; /* apply a ρ̄ estimate only if it differs by more than this factor; default 1 (always) */
@@ -117,6 +117,12 @@ typedef struct {
                              pcg_eps_min, refreshed at every check); 1: a tolerance decreasing with
                              the ADMM iteration k, max(pcg_lambda·(k + 1)^(−3/2), pcg_eps_min), the
                              kind of rule Section 6.3.3 attributes to SCS (an ablation) */
+  int32_t speculate;      /* 1 (default): the ADMM iterations between two checks are launched
+                             without waiting for their PCG solves; the first PCG solve that is not
+                             done after the predicted number of iterations (or breaks down, or hits
+                             the cap) raises a device flag that skips the rest, and the host resumes
+                             there at the next read. 0: the host waits for every PCG solve (the
+                             synchronous loop of Section 6.3.3). Both give bitwise the same iterates. */
 } qpg_settings;
 
 typedef struct {
@@ -140,6 +146,7 @@ typedef struct {
   int32_t precond_switches; /* runtime switches from learned to Jacobi (capped or broken-down PCG) */
   int32_t infeas_checks;   /* checks that ran the infeasibility passes: those after two checks in a
                               row without a 1% gain in the worse normalised residual */
+  int32_t spec_resumes;    /* speculative iterations whose PCG solve the host had to finish */
 } qpg_info;
 
 typedef struct qpg_solver qpg_solver;
@@ -237,13 +244,15 @@ int qpg_time_kernel(qpg_solver* h, int32_t kernel, int32_t precision, int32_t re
  * per launch (sum over tiles); out[6] segment slots; out[7] segment chunks. */
 int qpg_spmv_layout(const qpg_solver* h, int32_t matrix, int64_t out[8]);
 
-/* K_ii = diag(P̄)_i + σ + ρ̄‖Ā_i‖² of the scaled reduced KKT matrix (Section 6.3.1), n values. */
+/* K_ii = diag(P̄)_i + σ + ρ̄‖Ā_i‖² of the scaled reduced KKT matrix (Section 6.3.1), n values.
+ * QPG_ERR_STATE for a handle set up with settings.rho_vector (K is taken with R = ρ̄I here). */
 int qpg_get_kdiag(const qpg_solver* h, double rho, double* kdiag);
 
 /* Hutchinson estimate of diag(K⁻¹) for K = P̄ + σI + ρ̄ĀᵀĀ: (1/s) Σ_k z_k ∘ K⁻¹z_k over the s
  * probes z_k given in `signs` (s×n, row-major, entries ±1 only; the caller draws them), each
  * K⁻¹z_k by the solver's own Jacobi PCG (Algorithm 3) from 0 to ‖r‖∞ ≤ eps‖z‖∞ or max_iter.
- * Writes n values to diag. Not part of the paper: training targets of QPG_PRECOND_LEARNED. */
+ * Writes n values to diag. Not part of the paper: training targets of QPG_PRECOND_LEARNED.
+ * QPG_ERR_STATE for a handle set up with settings.rho_vector (K is taken with R = ρ̄I here). */
 int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho, double eps,
                    int32_t max_iter, double* diag);
 

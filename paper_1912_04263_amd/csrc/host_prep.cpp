@@ -175,7 +175,8 @@ int validate_settings(const qpg_settings* s, std::string* msg) {
             s->spmv_tile_nnz >= 0 && s->spmv_plain_nnz >= 0 && s->eps_prim_inf >= 0 &&
             s->eps_dual_inf >= 0 && std::isfinite(s->eps_prim_inf) && std::isfinite(s->eps_dual_inf) &&
             (s->rho_vector == 0 || (s->rho_vector == 1 && s->precond == QPG_PRECOND_JACOBI)) &&
-            (s->pcg_eps_schedule == 0 || s->pcg_eps_schedule == 1);
+            (s->pcg_eps_schedule == 0 || s->pcg_eps_schedule == 1) &&
+            (s->speculate == 0 || s->speculate == 1);
   if (!ok) {
     *msg = "settings: value out of range";
     return QPG_ERR_ARG;

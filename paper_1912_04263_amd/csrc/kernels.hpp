@@ -175,11 +175,13 @@ __global__ void k_mirror(const S* st, S* mirror) {
   if (threadIdx.x == 0) *mirror = *st;
 }
 
-// After the PCG iterations launched for speculative ADMM iteration k (run by workgroup 0 of the
-// last launched k_pcg_dir, after it has stored the iteration's scalars): when the solve has not
+// After the PCG iterations launched for speculative ADMM iteration k: when the solve has not
 // finished, broke down or hit the cap, set the abort flag (which gates every later kernel of the
-// speculation, and the PCG kernels through `done`) so that the host takes over from iteration k;
-// otherwise count the iterations.
+// speculation) and `done` (which gates the PCG kernels), so that the host takes over from
+// iteration k; otherwise count the iterations. It runs in a launch of its own, after the last
+// k_pcg_dir of the iteration has completed: that kernel is itself gated on `done`, so a write of
+// `done` from inside it could make its later workgroups skip their share of the direction update
+// that the resumed solve still needs.
 template <class S>
 __device__ __forceinline__ void after_pcg(S* st, int k) {
   if (st->abort) return;
@@ -202,6 +204,10 @@ __device__ __forceinline__ void after_pcg(S* st, int k) {
   }
 }
 
+template <class S>
+__global__ void k_after_pcg(S* st, int k) {
+  if (threadIdx.x == 0) after_pcg(st, k);
+}
 
 // The host resumes after an abort: clear it, and reopen the PCG solve when it was cut short.
 template <class S>
@@ -844,21 +850,18 @@ __global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__
 // p = −M⁻¹r + βp. Workgroup 0 stores the new rᵀy under the next parity, β, ‖r‖∞, the iteration
 // count and the stopping flag, and mirrors the scalars to the host when asked (also when the
 // iteration is gated off). Other workgroups read only the previous parity's rᵀy, so no value is
-// read while it is written; one that sees the stopping flag already set skips its share of p,
-// which is not used once the solve has stopped. spec_k ≥ 0: this is the last PCG iteration
-// launched for speculative ADMM iteration spec_k (see after_pcg).
+// read while it is written. `done` is written here only when the solve has ended (converged,
+// capped or broken down); a workgroup that sees it already set skips its share of p, which is
+// not used once the solve has ended.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
                                                     const T* __restrict__ r,
                                                     const T* __restrict__ dinv,
                                                     DevState* st, const double* __restrict__ partials,
                                                     int count, const int32_t* __restrict__ gate, int it,
-                                                    DevState* mirror, int spec_k) {
+                                                    DevState* mirror) {
   if (gate && *gate) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      if (spec_k >= 0) after_pcg(st, spec_k);
-      if (mirror) *mirror = *st;
-    }
+    if (mirror && blockIdx.x == 0 && threadIdx.x == 0) *mirror = *st;
     return;
   }
   double t[2];
@@ -874,7 +877,6 @@ __global__ __launch_bounds__(kBlock) void k_pcg_dir(int n, T* __restrict__ p,
     st->iter = it + 1;
     if (rz_new != rz_new) st->breakdown = 1;
     st->done = (t[1] <= st->thresh || it + 1 >= st->maxit || st->breakdown || !(st->kappa > 0.0)) ? 1 : 0;
-    if (spec_k >= 0) after_pcg(st, spec_k);
     if (mirror) *mirror = *st;
   }
 }

@@ -332,6 +332,7 @@ extern "C" {
 
 int qpg_get_kdiag(const qpg_solver* h, double rho, double* kdiag) {
   if (!h || !kdiag || !(rho > 0)) return QPG_ERR_ARG;
+  if (h->s.rho_vector) return QPG_ERR_STATE;  // K is defined here with R = ρ̄I
   for (int i = 0; i < h->n; ++i) kdiag[i] = h->diagP_h[i] + h->s.sigma + rho * h->colsq_h[i];
   return QPG_OK;
 }
@@ -340,6 +341,10 @@ int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double r
                    int32_t max_iter, double* diag) {
   if (!h || !signs || nprobes < 1 || !diag || !(rho > 0) || !(eps >= 0) || max_iter < 1)
     return QPG_ERR_ARG;
+  if (h->s.rho_vector) {
+    h->err = "qpg_hutchinson: defined for R = rho*I (the handle was set up with rho_vector)";
+    return QPG_ERR_STATE;
+  }
   for (long k = 0; k < (long)nprobes * h->n; ++k)
     if (signs[k] != 1 && signs[k] != -1) {
       h->err = "qpg_hutchinson: probe entries must be +1 or -1";

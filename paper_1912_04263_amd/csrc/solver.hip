@@ -203,6 +203,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // update) and return the iteration to continue from; −1 when the ADMM loop must stop
   auto resume = [&]() {
     const int j = st_host->abort_k, reason = st_host->abort_reason;
+    info.spec_resumes++;
     hipLaunchKernelGGL(k_resume<DevState>, dim3(1), dim3(64), 0, stream, st, reason == 1 ? 1 : 0);
     const int it = reason == 1 ? pcg_loop<T>(rho, s.pcg_max_iter, true, st_host->iter) : st_host->iter;
     pending = false;
@@ -276,7 +277,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       info.pcg_iter_total += it_l;
       trial = false;
       if (after_pcg(k, it)) return finish(k);
-    } else if (!check) {
+    } else if (!check && s.speculate) {
       // speculative: PCG with the predicted iteration count, no host read
       rhs(agate, k);
       const int b = std::max(1, std::min(last_pcg, s.pcg_max_iter));
@@ -419,6 +420,7 @@ int qpg_solver::solve() {
   info.precond_learned_chosen = 0;
   info.precond_switches = 0;
   info.infeas_checks = 0;
+  info.spec_resumes = 0;
   info.prim_res = info.dual_res = INFINITY;
   info.obj_val = NAN;
   double rho = s.rho;
@@ -618,7 +620,7 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
       default:
         hipLaunchKernelGGL((k_pcg_dir<T>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, h->n, V.p,
                            (const T*)V.r, (const T*)V.dinv, h->st, (const double*)h->rb.vpartials, h->vgrid,
-                           (const int32_t*)nullptr, 0, (DevState*)nullptr, -1);
+                           (const int32_t*)nullptr, 0, (DevState*)nullptr);
     }
   };
   hipEvent_t e0, e1;
@@ -799,7 +801,7 @@ int qpg_default_settings(qpg_settings* s) {
   s->alpha = 1.6;
   s->eps_abs = 1e-3;
   s->eps_rel = 1e-3;
-  s->max_iter = 4000;
+  s->max_iter = 100000;
   s->check_every = 5;
   s->rho_update_every = 10;
   s->rho_update_gate = 1.0;
@@ -822,6 +824,7 @@ int qpg_default_settings(qpg_settings* s) {
   s->eps_dual_inf = 1e-4;
   s->rho_vector = 0;
   s->pcg_eps_schedule = 0;
+  s->speculate = 1;
   return QPG_OK;
 }
 

@@ -264,7 +264,8 @@ struct qpg_solver {
                        (track_zt && !eqrow) ? V.zt : (T*)nullptr, (const T*)V.w, (T)(1.0 / rho), it);
     hipLaunchKernelGGL((k_pcg_dir<T>), dim3(vgrid), dim3(kBlock), 0, stream, n, V.p, (const T*)V.r,
                        (const T*)V.dinv, st, (const double*)rb.vpartials, vgrid, gate, it,
-                       mirror ? st_mirror_dev : (DevState*)nullptr, spec_k);
+                       mirror ? st_mirror_dev : (DevState*)nullptr);
+    if (spec_k >= 0) hipLaunchKernelGGL(k_after_pcg<DevState>, dim3(1), dim3(64), 0, stream, st, spec_k);
   }
 
   // Run PCG iterations after the initialisation kernel until st->done. The first batch is one

@@ -49,7 +49,7 @@ class Settings(C.Structure):
                 ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32),
                 ("spmv_tile_nnz", C.c_int32), ("spmv_plain_nnz", C.c_int32),
                 ("eps_prim_inf", C.c_double), ("eps_dual_inf", C.c_double), ("rho_vector", C.c_int32),
-                ("pcg_eps_schedule", C.c_int32)]
+                ("pcg_eps_schedule", C.c_int32), ("speculate", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -60,7 +60,8 @@ class Info(C.Structure):
                 ("precision_used", C.c_int32), ("precond_used", C.c_int32),
                 ("fallback_events", C.c_int32), ("scaling_passes", C.c_int32),
                 ("precond_trials", C.c_int32), ("precond_learned_chosen", C.c_int32),
-                ("precond_switches", C.c_int32), ("infeas_checks", C.c_int32)]
+                ("precond_switches", C.c_int32), ("infeas_checks", C.c_int32),
+                ("spec_resumes", C.c_int32)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -174,6 +175,7 @@ class SolveInfo:
     precond_learned_chosen: int = 0
     precond_switches: int = 0
     infeas_checks: int = 0
+    spec_resumes: int = 0
 
 
 class _CscArrays:
@@ -228,7 +230,8 @@ class Solver:
                          i.solve_time, "mixed" if i.precision_used == QPG_MIXED else "fp64",
                          i.fallback_events, i.scaling_passes,
                          "learned" if i.precond_used == QPG_PRECOND_LEARNED else "jacobi",
-                         i.precond_trials, i.precond_learned_chosen, i.precond_switches, i.infeas_checks)
+                         i.precond_trials, i.precond_learned_chosen, i.precond_switches, i.infeas_checks,
+                         i.spec_resumes)
 
     def x(self):
         out = np.empty(self.n)

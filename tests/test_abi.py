@@ -46,6 +46,7 @@ int main(void) {
   printf("%zu %zu %zu %zu\n", offsetof(qpg_settings, eps_prim_inf), offsetof(qpg_settings, eps_dual_inf),
          offsetof(qpg_settings, rho_vector), offsetof(qpg_settings, pcg_eps_schedule));
   printf("%zu %d %d\n", offsetof(qpg_info, infeas_checks), QPG_PRIMAL_INFEASIBLE, QPG_DUAL_INFEASIBLE);
+  printf("%zu %zu\n", offsetof(qpg_settings, speculate), offsetof(qpg_info, spec_resumes));
   printf("%d\n", QPG_NET_NPARAMS);
   return 0;
 }
@@ -63,7 +64,8 @@ int main(void) {
             I.obj_val.offset, I.solve_time.offset, I.scaling_passes.offset, I.precond_switches.offset,
             S.precond_weights.offset, S.precond_trial.offset, S.spmv_plain_nnz.offset,
             S.eps_prim_inf.offset, S.eps_dual_inf.offset, S.rho_vector.offset, S.pcg_eps_schedule.offset,
-            I.infeas_checks.offset, qpg.QPG_PRIMAL_INFEASIBLE, qpg.QPG_DUAL_INFEASIBLE, qpg.QPG_NET_NPARAMS]
+            I.infeas_checks.offset, qpg.QPG_PRIMAL_INFEASIBLE, qpg.QPG_DUAL_INFEASIBLE,
+            S.speculate.offset, I.spec_resumes.offset, qpg.QPG_NET_NPARAMS]
     assert got == want
 
 
