@@ -2,16 +2,25 @@
 
 One step = one complete solve (Algorithm 1 with the reduced-KKT PCG step, every kernel of the
 hot path) of the device-resident problem from a cold start (x = z = y = 0, initial ρ̄) to
-eps_abs = eps_rel = 1e-3. The problem is set up (validated, equilibrated, copied to HBM) once,
-before the timed region. Prints one JSON line.
+eps_abs = eps_rel = 1e-3. The problem is set up (validated, converted, equilibrated, copied to
+HBM) once, before the timed region. Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload lasso_c1] [--precision fp64]
+Headline: the SVM workload (10⁶ points × 10⁴ features at 1%, 1.02·10⁸ matrix entries), the
+largest of the five benchmark configurations and the one whose matrices (1.2–2.5 GB) cannot sit
+in the 256 MB last-level cache, in FP32-bulk / FP64-reduction arithmetic with the Jacobi
+preconditioner. Beside it, one entry per benchmark configuration (random 200×400, Lasso, large
+random, portfolio, SVM) with every precision/preconditioner variant, its objective error against
+a tight FP64 solve, and the time to reach a stated objective error.
+
+  python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload svm_c4] [--precision mixed]
+                  [--configs all|none|name,name,...]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -22,6 +31,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QP time-to-solution & ADMM iter/s at eps 1e-3; PCG HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
+CONFIGS = ["random_c0", "lasso_c1", "random_c2", "portfolio_c3", "svm_c4"]
+VARIANTS = (("fp64", "jacobi"), ("mixed", "jacobi"), ("mixed", "learned"), ("fp64", "learned"))
+# objective error that counts as "solved" when variants are compared at equal answer quality
+EQUAL_QUALITY = 1e-3
+QUALITY_EPS = (1e-3, 1e-4, 1e-5, 1e-6)
+REF_EPS = {"portfolio_c3": 1e-7}  # tight FP64 reference solve per workload (default 1e-6)
 
 
 def log(*a):
@@ -88,30 +103,65 @@ def measured_traffic(workload, precision):
     return d["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(problem, iters):
-    """The oracle timed on this host: ADMM with its float64 reduced-KKT PCG solves."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(problem, iters, small):
+    """The oracle timed on this host: ADMM iterations/s on a bounded sample of the headline
+    workload (its float64 reduced-KKT PCG route; the direct factorisation does not fit a bounded
+    sample at this size), and the time-to-solution at eps 1e-3 of the 200×400 random QP with the
+    direct KKT solve (factorisation included)."""
     import scipy.sparse as sp
 
     from oracle import admm as o_admm
 
+    t = time.perf_counter()
     r = o_admm.solve(problem.P_full(), problem.q, sp.csr_matrix(problem.A), problem.l, problem.u,
                      eps_abs=0.0, eps_rel=0.0, max_iter=iters, linsys="pcg", adaptive_rho=False)
-    rate = r.iters / r.iter_time
-    return {"value": rate, "unit": "ADMM iter/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{r.iters} ADMM iterations of the float64 oracle (numpy/scipy, one thread; linear "
-                       f"step = reduced KKT system by its own PCG to 1e-12 relative, warm-started) on the "
-                       f"same {problem.name} instance; Ruiz scaling not timed; {r.iter_time:.1f} s")}
+    total = time.perf_counter() - t
+    t = time.perf_counter()
+    r0 = o_admm.solve(small.P_full(), small.q, sp.csr_matrix(small.A), small.l, small.u,
+                      eps_abs=1e-3, eps_rel=1e-3)
+    tts0 = time.perf_counter() - t
+    return {"value": r.iters / r.iter_time, "unit": "ADMM iter/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{r.iters} ADMM iterations of the float64 oracle (numpy/scipy, one thread; "
+                       f"linear step = reduced KKT system by its own PCG to 1e-12 relative, "
+                       f"warm-started) on the same {problem.name} instance: {r.iter_time:.1f} s of "
+                       f"iterations ({total:.1f} s with Ruiz scaling, which the rate excludes)"),
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model(),
+            "random_c0_tts_s": tts0, "random_c0_status": r0.status, "random_c0_admm_iters": r0.iters,
+            "random_c0_note": "oracle with its direct KKT solve (sparse LU, factorisation included), "
+                              "eps_abs = eps_rel = 1e-3, one thread"}
+
+
+def weights_for(workload, default):
+    """Trained parameters of the learned preconditioner for a workload's problem family, or the
+    given default set when that family has none."""
+    from paper_1912_04263_amd import qpg
+    family = workload.split("_")[0]
+    path = os.path.join(qpg.WEIGHTS_DIR, f"{family}_h32.f32")
+    name = f"{family}_h32" if os.path.exists(path) else default
+    return name, qpg.load_weights(name)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="lasso_c1")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="svm_c4")
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "learned"])
-    ap.add_argument("--weights", default="portfolio_h32", help="learned-preconditioner weights name")
+    ap.add_argument("--weights", default="portfolio_h32",
+                    help="learned-preconditioner weights when the workload's family has none")
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--rho-update-every", type=int, default=10,
                     help="ρ̄ update cadence in ADMM iterations (0: constant ρ̄), for the cadence ablation")
@@ -119,13 +169,12 @@ def main():
     ap.add_argument("--rho-vector", type=int, default=0, help="1: R = diag(ρ_i) (ablation)")
     ap.add_argument("--pcg-eps-schedule", type=int, default=0,
                     help="1: PCG tolerance decreasing with k instead of the residual rule (ablation)")
-    ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--kernel-reps", type=int, default=100)
+    ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--ref-eps", type=float, default=0.0,
-                    help="also solve to this tolerance (FP64/Jacobi, untimed) and report each "
-                         "variant's objective error against it")
+    ap.add_argument("--configs", default="all",
+                    help="per-configuration entries: all, none, or a comma-separated list")
+    ap.add_argument("--config-reps", type=int, default=3, help="timed solves per variant (median)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (reference for counter scaling)")
     args = ap.parse_args()
@@ -143,30 +192,57 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
-    t0 = time.perf_counter()
-    p = problems.make(args.workload)
-    log(f"[bench] generated {args.workload}: n={p.n} m={p.m} nnz(P)={p.meta['nnz_P_full']} "
-        f"nnz(A)={p.meta['nnz_A']} in {time.perf_counter() - t0:.1f}s")
 
-    weights = qpg.load_weights(args.weights)
+    def make(name):
+        t0 = time.perf_counter()
+        p = problems.make(name)
+        log(f"[bench] generated {name}: n={p.n} m={p.m} nnz(P)={p.meta['nnz_P_full']} "
+            f"nnz(A)={p.meta['nnz_A']} in {time.perf_counter() - t0:.1f}s")
+        return p
 
-    def run(precision, steps, warmup, precond=None):
-        precond = precond or args.precond
+    def solver(p, precision, precond, eps, weights=None, **kw):
         extra = dict(precond="learned", precond_weights=weights) if precond == "learned" else {}
-        s = qpg.Solver.from_qp(p, eps_abs=args.eps, eps_rel=args.eps, precision=precision,
-                               stream=stream, device=0, max_iter=20000,
-                               rho_update_every=args.rho_update_every, check_every=args.check_every,
-                               rho_vector=args.rho_vector, pcg_eps_schedule=args.pcg_eps_schedule,
-                               **extra)
-        setup = s.info().setup_time
+        kw.setdefault("max_iter", 100000)
+        return qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, precision=precision, stream=stream,
+                                  device=0, **extra, **kw)
+
+    def timed(s, steps, warmup):
         for _ in range(warmup):
             s.solve()
         torch.cuda.synchronize()
         t = time.perf_counter()
         infos = [s.solve() for _ in range(steps)]
         torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        return s, setup, infos, el
+        return infos, time.perf_counter() - t
+
+    def pcg_kernels(s, p, precision):
+        prec_id = qpg.QPG_MIXED if precision == "mixed" else qpg.QPG_FP64
+        sz = 4 if precision == "mixed" else 8
+        n, m = p.n, p.m
+        nnz_a = p.meta["nnz_A"]
+        nnz_b = p.meta["nnz_P_full"] + nnz_a
+        kernels = {}
+        for kid, name, nbytes in ((qpg.QPG_KERNEL_SPMV_B, "spmv_B_Kp", spmv_b_bytes(n, m, nnz_b, sz)),
+                                  (qpg.QPG_KERNEL_SPMV_A, "spmv_A_w", spmv_a_bytes(n, m, nnz_a, sz)),
+                                  (qpg.QPG_KERNEL_PCG_UPDATE, "pcg_update", pcg_update_bytes(n, m, sz)),
+                                  (qpg.QPG_KERNEL_PCG_DIR, "pcg_dir", pcg_dir_bytes(n, sz))):
+            us = s.time_kernel(kid, args.kernel_reps, prec_id)
+            kernels[name] = {"avg_us": us, "bytes": nbytes, "GBs": nbytes / us / 1e3,
+                             "frac": nbytes / us / 1e3 / HBM_PEAK_GBS}
+        pcg_bytes = sum(k["bytes"] for k in kernels.values())
+        pcg_us = sum(k["avg_us"] for k in kernels.values())
+        it = {"bytes": pcg_bytes, "kernel_us": pcg_us, "GBs": pcg_bytes / pcg_us / 1e3,
+              "frac": pcg_bytes / pcg_us / 1e3 / HBM_PEAK_GBS}
+        layout_b = s.spmv_layout(1)
+        us = s.time_kernel(qpg.QPG_KERNEL_SPMV_B_STREAM, args.kernel_reps, prec_id)
+        nbytes = spmv_b_stream_bytes(n, m, nnz_b, sz)
+        moved = stream_bytes_moved(layout_b, sz)
+        kernels["spmv_B_stream"] = {"avg_us": us, "bytes": nbytes, "GBs": nbytes / us / 1e3,
+                                    "frac": nbytes / us / 1e3 / HBM_PEAK_GBS,
+                                    "bytes_moved": moved, "GBs_moved": moved / us / 1e3, "layout": layout_b}
+        us_a = s.time_kernel(qpg.QPG_KERNEL_SPMV_A_STREAM, args.kernel_reps, prec_id)
+        kernels["spmv_A_stream"] = {"avg_us": us_a, "layout": s.spmv_layout(0)}
+        return kernels, it
 
     if args.copy_calibration_mb > 0:
         nel = args.copy_calibration_mb * (1 << 20) // 8
@@ -177,38 +253,22 @@ def main():
         log(f"[bench] copy calibration: {args.copy_calibration_mb} MiB read + written")
         del a, b
 
-    s, setup_s, infos, elapsed = run(args.precision, args.steps, args.warmup)
+    # ------------------------------------------------------------------ headline
+    p = make(args.workload)
+    wname, weights = weights_for(args.workload, args.weights)
+    s = solver(p, args.precision, args.precond, args.eps, weights,
+               rho_update_every=args.rho_update_every, check_every=args.check_every,
+               rho_vector=args.rho_vector, pcg_eps_schedule=args.pcg_eps_schedule)
+    setup_s = s.info().setup_time
+    infos, elapsed = timed(s, args.steps, args.warmup)
     steps = max(1, args.steps)
     last = infos[-1] if infos else s.info()
     admm_iters = sum(i.iter for i in infos)
-    log(f"[bench] {args.precision}/{args.precond}: {last.status} in {last.iter} ADMM / {last.pcg_iter_total} PCG "
-        f"iterations ({last.infeas_checks} infeasibility checks), solve {elapsed / steps * 1e3:.2f} ms, "
-        f"setup {setup_s:.2f} s, obj {last.obj_val:.10g}")
-
-    prec_id = qpg.QPG_MIXED if args.precision == "mixed" else qpg.QPG_FP64
-    sz = 4 if args.precision == "mixed" else 8
-    n, m = p.n, p.m
-    nnz_a = p.meta["nnz_A"]
-    nnz_b = p.meta["nnz_P_full"] + nnz_a
-    kernels = {}
-    pcg_steps = ((qpg.QPG_KERNEL_SPMV_B, "spmv_B_Kp", spmv_b_bytes(n, m, nnz_b, sz)),
-             (qpg.QPG_KERNEL_SPMV_A, "spmv_A_w", spmv_a_bytes(n, m, nnz_a, sz)),
-             (qpg.QPG_KERNEL_PCG_UPDATE, "pcg_update", pcg_update_bytes(n, m, sz)),
-             (qpg.QPG_KERNEL_PCG_DIR, "pcg_dir", pcg_dir_bytes(n, sz)))
-    for kid, name, nbytes in pcg_steps:
-        us = s.time_kernel(kid, args.kernel_reps, prec_id)
-        kernels[name] = {"avg_us": us, "bytes": nbytes, "GBs": nbytes / us / 1e3}
-    pcg_bytes = sum(k["bytes"] for k in kernels.values())
-    pcg_us = sum(k["avg_us"] for k in kernels.values())
-    # the dominant kernel: the stream kernel of the B pass, timed alone
-    layout_b = s.spmv_layout(1)
-    us = s.time_kernel(qpg.QPG_KERNEL_SPMV_B_STREAM, args.kernel_reps, prec_id)
-    nbytes = spmv_b_stream_bytes(n, m, nnz_b, sz)
-    moved = stream_bytes_moved(layout_b, sz)
-    kernels["spmv_B_stream"] = {"avg_us": us, "bytes": nbytes, "GBs": nbytes / us / 1e3,
-                                "bytes_moved": moved, "GBs_moved": moved / us / 1e3, "layout": layout_b}
-    us_a = s.time_kernel(qpg.QPG_KERNEL_SPMV_A_STREAM, args.kernel_reps, prec_id)
-    kernels["spmv_A_stream"] = {"avg_us": us_a, "layout": s.spmv_layout(0)}
+    tts = elapsed / steps
+    log(f"[bench] {args.workload} {args.precision}/{args.precond}: {last.status} in {last.iter} ADMM / "
+        f"{last.pcg_iter_total} PCG iterations, solve {tts * 1e3:.2f} ms, setup {setup_s:.3f} s, "
+        f"obj {last.obj_val:.10g}")
+    kernels, pcg_it = pcg_kernels(s, p, args.precision)
     dom = kernels["spmv_B_stream"]
     prec_tag = "float" if args.precision == "mixed" else "double"
     roofline = {"bound": "hbm", "achieved": dom["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -216,49 +276,66 @@ def main():
                 "traffic": measured_traffic(args.workload, args.precision),
                 "kernel": f"k_spmv<{prec_tag}, OpKp<{prec_tag}>> (segment sums of [P̄ | Āᵀ][p; w])",
                 "bytes_per_launch": dom["bytes"], "avg_us": dom["avg_us"],
-                "bytes_moved_per_launch": moved, "achieved_moved": dom["GBs_moved"],
-                "pass_B": kernels["spmv_B_Kp"],
-                "pcg_iteration": {"bytes": pcg_bytes, "kernel_us": pcg_us, "GBs": pcg_bytes / pcg_us / 1e3}}
+                "bytes_moved_per_launch": dom["bytes_moved"], "achieved_moved": dom["GBs_moved"],
+                "pass_B": kernels["spmv_B_Kp"], "pass_A": kernels["spmv_A_w"],
+                "pcg_iteration": pcg_it}
     s.close()
+    log(f"[bench] dominant kernel {dom['avg_us']:.1f} us = {dom['GBs']:.0f} GB/s ({roofline['frac']:.3f}); "
+        f"PCG iteration {pcg_it['kernel_us']:.1f} us = {pcg_it['GBs']:.0f} GB/s ({pcg_it['frac']:.3f})")
 
-    variants = []
-    if not args.no_compare:
-        for prec, pc in (("fp64", "jacobi"), ("mixed", "jacobi"), ("mixed", "learned"), ("fp64", "learned")):
-            if (prec, pc) == (args.precision, args.precond):
-                continue
-            s2, su2, inf2, el2 = run(prec, max(1, args.steps // 2), 1, pc)
-            last2 = inf2[-1]
-            v = {"precision": prec, "precond": pc, "tts_ms": el2 / len(inf2) * 1e3,
-                 "admm_iter_per_s": sum(i.iter for i in inf2) / el2, "admm_iters": last2.iter,
-                 "pcg_iters": last2.pcg_iter_total, "infeas_checks": last2.infeas_checks,
-                 "status": last2.status, "obj": last2.obj_val,
-                 "precision_used": last2.precision_used, "precond_used": last2.precond_used,
-                 "precond_trials_won": [last2.precond_learned_chosen, last2.precond_trials],
-                 "setup_s": su2,
-                 "obj_rel_diff_vs_main": abs(last2.obj_val - last.obj_val) / max(1.0, abs(last.obj_val))}
-            variants.append(v)
-            log(f"[bench] {prec}/{pc}: {v['status']} tts {v['tts_ms']:.2f} ms, {v['admm_iters']} ADMM / "
-                f"{v['pcg_iters']} PCG, {v['infeas_checks']} infeasibility checks, obj {v['obj']:.10g}")
-            s2.close()
-
-    ref = None
-    if args.ref_eps > 0:
-        sr = qpg.Solver.from_qp(p, eps_abs=args.ref_eps, eps_rel=args.ref_eps, stream=stream, device=0,
-                                max_iter=100000)
-        ir = sr.solve()
-        sr.close()
-        ref = {"eps": args.ref_eps, "obj": ir.obj_val, "status": ir.status, "iters": ir.iter}
-        scale = max(1.0, abs(ir.obj_val))
-        for v in variants:
-            v["obj_rel_err_vs_ref"] = abs(v["obj"] - ir.obj_val) / scale
-        log(f"[bench] reference at eps {args.ref_eps}: {ir.status}, obj {ir.obj_val:.10g}")
+    # ------------------------------------------------------------------ per configuration
+    names = CONFIGS if args.configs == "all" else ([] if args.configs == "none" else args.configs.split(","))
+    configs = {}
+    for name in names:
+        q = p if name == args.workload else make(name)
+        wn, w = weights_for(name, args.weights)
+        ref_eps = REF_EPS.get(name, 1e-6)
+        with solver(q, "fp64", "jacobi", ref_eps) as sr:
+            ir = sr.solve()
+        fref = ir.obj_val
+        scale = max(1.0, abs(fref))
+        log(f"[bench] {name}: reference FP64/Jacobi at eps {ref_eps:g}: {ir.status}, {ir.iter} ADMM, obj {fref:.10g}")
+        entry = {"n": q.n, "m": q.m, "nnz_P": q.meta["nnz_P_full"], "nnz_A": q.meta["nnz_A"],
+                 "reference": {"eps": ref_eps, "obj": fref, "status": ir.status, "admm_iters": ir.iter},
+                 "learned_weights": wn, "variants": {}}
+        for prec, pc in VARIANTS:
+            v = {}
+            for eps in QUALITY_EPS:
+                with solver(q, prec, pc, eps, w) as sv:
+                    inf, el = timed(sv, args.config_reps, 1)
+                    setup = sv.info().setup_time
+                    if eps == args.eps and pc == "jacobi":
+                        kern, it = pcg_kernels(sv, q, prec)
+                        v["pcg_iteration"] = it
+                        v["spmv_B_stream"] = {k: kern["spmv_B_stream"][k] for k in ("avg_us", "GBs", "frac")}
+                i = inf[-1]
+                err = abs(i.obj_val - fref) / scale
+                t_solve = el / len(inf)
+                rec = {"status": i.status, "tts_s": t_solve, "setup_s": setup, "tts_with_setup_s": t_solve + setup,
+                       "admm_iters": i.iter, "pcg_iters": i.pcg_iter_total, "admm_iter_per_s": i.iter / t_solve,
+                       "obj": i.obj_val, "obj_rel_err_vs_ref": err, "precision_used": i.precision_used,
+                       "precond_used": i.precond_used, "precond_trials_won": [i.precond_learned_chosen, i.precond_trials]}
+                if eps == args.eps:
+                    v.update(rec)
+                log(f"[bench]   {prec}/{pc} eps {eps:g}: {i.status} {i.iter} ADMM / {i.pcg_iter_total} PCG, "
+                    f"solve {t_solve * 1e3:.2f} ms, setup {setup:.3f} s, obj err {err:.2e}")
+                if err <= EQUAL_QUALITY or eps == QUALITY_EPS[-1]:
+                    v["equal_quality"] = {"obj_rel_err_target": EQUAL_QUALITY, "reached": err <= EQUAL_QUALITY,
+                                          "eps": eps, "tts_s": t_solve, "tts_with_setup_s": t_solve + setup,
+                                          "obj_rel_err_vs_ref": err, "admm_iters": i.iter}
+                    break
+            entry["variants"][f"{prec}/{pc}"] = v
+        configs[name] = entry
+        if q is not p:
+            del q
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host ...")
-        cpu = cpu_baseline(p, args.cpu_iters)
-        log(f"[bench] cpu_baseline {cpu['value']:.3f} ADMM iter/s")
+        cpu = cpu_baseline(p, args.cpu_iters, problems.make("random_c0"))
+        log(f"[bench] cpu_baseline {cpu['value']:.4f} ADMM iter/s; random_c0 TTS {cpu['random_c0_tts_s']:.2f} s")
 
+    n, m = p.n, p.m
     out = {
         "metric": METRIC,
         "value": admm_iters / elapsed if admm_iters else None,
@@ -266,30 +343,29 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / steps * 1e3 if args.steps else None,
+        "ms_per_step": tts * 1e3 if args.steps else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "nnz_P": p.meta["nnz_P_full"], "nnz_A": nnz_a,
-                   "eps_abs": args.eps, "eps_rel": args.eps, "precision": args.precision,
-                   "preconditioner": args.precond, "rho_update_every": args.rho_update_every,
-                   "check_every": args.check_every, "rho_vector": args.rho_vector,
-                   "pcg_eps_schedule": args.pcg_eps_schedule,
+        "config": {"workload": args.workload, "n": n, "m": m, "nnz_P": p.meta["nnz_P_full"],
+                   "nnz_A": p.meta["nnz_A"], "eps_abs": args.eps, "eps_rel": args.eps,
+                   "precision": args.precision, "preconditioner": args.precond,
+                   "learned_weights": wname if args.precond == "learned" else None,
+                   "rho_update_every": args.rho_update_every, "check_every": args.check_every,
+                   "rho_vector": args.rho_vector, "pcg_eps_schedule": args.pcg_eps_schedule,
                    "step": "one full solve from a cold start"},
-        "tts_s": elapsed / steps if args.steps else None,
+        "tts_s": tts,
         "setup_s": setup_s,
+        "tts_with_setup_s": tts + setup_s,
         "status": last.status,
         "admm_iters": last.iter,
         "pcg_iters": last.pcg_iter_total,
-        "infeas_checks": last.infeas_checks,
         "obj": last.obj_val,
         "kernels": kernels,
         "roofline": roofline,
-        "variants": variants,
-        "reference": ref,
-        "obj_rel_err_vs_ref": (abs(last.obj_val - ref["obj"]) / max(1.0, abs(ref["obj"]))) if ref else None,
+        "configs": configs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

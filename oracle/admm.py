@@ -184,7 +184,9 @@ def rho_vector(l, u, rho_bar, mode):
 def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, eps_rel=1e-9,
           max_iter=20000, scaling_iters=10, r_mode="scalar", adaptive_rho=True, rho_interval=100,
           check_every=1, record=0, x0=None, z0=None, y0=None, linsys="direct",
-          pcg_tol=1e-12, eps_pinf=1e-4, eps_dinf=1e-4) -> AdmmResult:
+          pcg_tol=1e-12, eps_pinf=1e-4, eps_dinf=1e-4, progress=None) -> AdmmResult:
+    """``progress``, if given, is called as progress(k, prim, dual, eps_prim, eps_dual, rho) after
+    every residual check (reporting only; it does not change the iteration)."""
     import time
 
     P_full = sp.csr_matrix(P_full, dtype=np.float64)
@@ -249,6 +251,8 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
         nq = float(np.max(np.abs(qb / D))) / c
         eps_p = eps_abs + eps_rel * max(nAx, nz)
         eps_d = eps_abs + eps_rel * max(nPx, nAty, nq)
+        if progress is not None:
+            progress(it, pr, dr, eps_p, eps_d, rho_bar)
         if pr <= eps_p and dr <= eps_d:
             status = "solved"
             break

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <limits>
 #include <thread>
 
@@ -348,3 +349,39 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
 }
 
 }  // namespace qpg
+
+// Defaults of the settings (include/qpg.h lists them with their sources in the paper).
+extern "C" int qpg_default_settings(qpg_settings* s) {
+  if (!s) return QPG_ERR_ARG;
+  std::memset(s, 0, sizeof(*s));
+  s->rho = 0.1;
+  s->sigma = 1e-6;
+  s->alpha = 1.6;
+  s->eps_abs = 1e-3;
+  s->eps_rel = 1e-3;
+  s->max_iter = 100000;
+  s->check_every = 5;
+  s->rho_update_every = 10;
+  s->rho_update_gate = 1.0;
+  s->pcg_lambda = 0.15;
+  s->pcg_eps_min = 1e-7;
+  s->pcg_eps_fixed = 0.0;
+  s->pcg_max_iter = 100;
+  s->pcg_rel_test = 1;
+  s->scaling_iters = 10;
+  s->precision = QPG_FP64;
+  s->precond = QPG_PRECOND_JACOBI;
+  s->device = 0;
+  s->stream = nullptr;
+  s->verbose = 0;
+  s->precond_weights = nullptr;
+  s->precond_trial = 1;
+  s->spmv_tile_nnz = qpg::kTileNnz;
+  s->spmv_plain_nnz = qpg::kPlainNnz;
+  s->eps_prim_inf = 1e-4;
+  s->eps_dual_inf = 1e-4;
+  s->rho_vector = 0;
+  s->pcg_eps_schedule = 0;
+  s->speculate = 1;
+  return QPG_OK;
+}

@@ -183,10 +183,13 @@ struct qpg_solver {
 
   // ----------------------------------------------------------------- launches
   // SpMV launches (k_spmv, then k_combine); the returned count is the number of workgroup
-  // partials a finalize must combine.
+  // partials a finalize must combine. Segment sums go to the plan's slots and reduction partials
+  // to rb.partials unless other buffers of the same sizes are given.
   template <typename T, class Op>
   int spmv(const DevPlan& pl, int nsplit, int planes, const Op& op, const int32_t* gate,
-           bool combine = true) {
+           bool combine = true, void* slots = nullptr, double* partials = nullptr) {
+    T* sl = static_cast<T*>(slots ? slots : pl.slots);
+    double* pa = partials ? partials : rb.partials;
     using G = typename Gathered<Op, T>::type;
     const size_t shmem = (size_t)pl.max_wlen * sizeof(G);
     // The dynamic LDS limit is a per-device attribute of each instantiation: raise it once per
@@ -205,11 +208,10 @@ struct qpg_solver {
     }
     const T* val = std::is_same<T, double>::value ? (const T*)pl.val64 : (const T*)pl.val32;
     hipLaunchKernelGGL((k_spmv<T, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles, pl.chunks,
-                       pl.segslot, pl.col16, pl.col32, val, nsplit, op, static_cast<T*>(pl.slots), pl.nslot,
-                       planes, gate);
+                       pl.segslot, pl.col16, pl.col32, val, nsplit, op, sl, pl.nslot, planes, gate);
     if (!combine) return 0;
     hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
-                       (const T*)static_cast<T*>(pl.slots), pl.nslot, planes, op, rb.partials, gate);
+                       (const T*)sl, pl.nslot, planes, op, pa, gate);
     return pl.ncomb;
   }
   template <typename T, class Op>

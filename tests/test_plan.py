@@ -19,10 +19,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1912_04263_amd", "csrc")
 
 
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+
+
 @functools.lru_cache(maxsize=None)
-def checker(tmpdir):
-    exe = os.path.join(tmpdir, "plan_check")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "native", "plan_check.cpp"),
+def checker(tmpdir, sanitize=False):
+    exe = os.path.join(tmpdir, "plan_check_asan" if sanitize else "plan_check")
+    opt = SANITIZE if sanitize else ["-O2"]
+    subprocess.run(["g++", *opt, "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "native", "plan_check.cpp"),
                     os.path.join(CSRC, "tiles.cpp"), os.path.join(CSRC, "host_parallel.cpp"), "-lpthread", "-o", exe],
                    check=True)
     return exe
@@ -31,6 +35,14 @@ def checker(tmpdir):
 @pytest.fixture(scope="module")
 def exe(tmp_path_factory):
     return checker(str(tmp_path_factory.mktemp("plan")))
+
+
+@pytest.fixture(scope="module")
+def exe_sanitized(tmp_path_factory):
+    """The same checker built with AddressSanitizer and UndefinedBehaviorSanitizer: an
+    out-of-bounds access, an overflow of the 16-bit window offsets' arithmetic or any other
+    undefined behaviour in the planner aborts it."""
+    return checker(str(tmp_path_factory.mktemp("plan_asan")), sanitize=True)
 
 
 def stats(out):
@@ -66,6 +78,25 @@ def test_work_lists_of_the_generated_workloads(exe, tmp_path, name, wcap):
     A, B = reduced_pair(p)
     run(exe, tmp_path, A, wcap=wcap)
     run(exe, tmp_path, B, nsplit=p.n, wcap=wcap)
+
+
+@pytest.mark.parametrize("name", ["random_c0", "lasso_small", "portfolio_small", "random2_small"])
+def test_work_lists_under_sanitizers(exe_sanitized, tmp_path, name):
+    p = pr.make(name)
+    A, B = reduced_pair(p)
+    for wcap in (1024, 8192):
+        run(exe_sanitized, tmp_path, A, wcap=wcap)
+        run(exe_sanitized, tmp_path, B, nsplit=p.n, wcap=wcap)
+
+
+def test_edge_matrices_under_sanitizers(exe_sanitized, tmp_path):
+    run(exe_sanitized, tmp_path, sp.csr_matrix((5, 7)))
+    run(exe_sanitized, tmp_path, sp.csr_matrix(([2.0], ([3], [6])), shape=(5, 7)), nsplit=4)
+    rng = np.random.default_rng(4)
+    M = sp.random(500, 400000, density=100 / 400000, random_state=rng, format="csr")
+    run(exe_sanitized, tmp_path, M, nsplit=50000)
+    M = sp.random(100, 100000, density=0.02, random_state=rng, format="csr")
+    run(exe_sanitized, tmp_path, M, nsplit=30000, tile_nnz=1024, plain_nnz=1024, wcap=2048)
 
 
 def test_wide_rows_take_the_multi_range_layout(exe, tmp_path):
