@@ -169,6 +169,10 @@ def main():
     ap.add_argument("--rho-vector", type=int, default=0, help="1: R = diag(ρ_i) (ablation)")
     ap.add_argument("--pcg-eps-schedule", type=int, default=0,
                     help="1: PCG tolerance decreasing with k instead of the residual rule (ablation)")
+    ap.add_argument("--spmv-tile-nnz", type=int, default=0,
+                    help="matrix entries per SpMV workgroup with an LDS window (0: library default)")
+    ap.add_argument("--spmv-plain-nnz", type=int, default=0,
+                    help="matrix entries per SpMV workgroup without a window (0: library default)")
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -203,6 +207,8 @@ def main():
     def solver(p, precision, precond, eps, weights=None, **kw):
         extra = dict(precond="learned", precond_weights=weights) if precond == "learned" else {}
         kw.setdefault("max_iter", 100000)
+        kw.setdefault("spmv_tile_nnz", args.spmv_tile_nnz)
+        kw.setdefault("spmv_plain_nnz", args.spmv_plain_nnz)
         return qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, precision=precision, stream=stream,
                                   device=0, **extra, **kw)
 
@@ -355,6 +361,7 @@ def main():
                    "learned_weights": wname if args.precond == "learned" else None,
                    "rho_update_every": args.rho_update_every, "check_every": args.check_every,
                    "rho_vector": args.rho_vector, "pcg_eps_schedule": args.pcg_eps_schedule,
+                   "spmv_tile_nnz": args.spmv_tile_nnz, "spmv_plain_nnz": args.spmv_plain_nnz,
                    "step": "one full solve from a cold start"},
         "tts_s": tts,
         "setup_s": setup_s,

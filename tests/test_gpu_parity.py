@@ -373,14 +373,36 @@ def sampled_spmv_check(p, rows=200, seed=7):
 
 
 def kkt_certificate(p, eps, **kw):
+    """The optimality conditions (eq. opt_cond) at the returned point, measured by the oracle on the
+    unscaled data:
+    * primal and dual residuals within the termination test (1.01·eps_prim, 1.01·eps_dual);
+    * l ≤ z ≤ u, and complementarity y₋ᵀ(z − l) = y₊ᵀ(z − u) = 0, up to the rounding of the
+      projection (z is a projection and y changes sign only where z sits on a bound): 1e-9
+      relative in FP64, 1e-6 in mixed precision (z and the bounds held in float);
+    * no multiplier on an infinite bound;
+    * the duality gap xᵀPx + qᵀx + uᵀy₊ + lᵀy₋, which equals xᵀr_dual − yᵀr_prim when
+      complementarity holds exactly, within ‖x‖₁·eps_dual + ‖y‖₁·eps_prim (with the same 1%
+      slack and a rounding term);
+    * the reported objective equal to ½xᵀPx + qᵀx of the returned x."""
     with qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, max_iter=40000, **kw) as s:
         info = s.solve()
         say("full size", p.name, kw, info)
         assert info.status == "solved"
-        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, s.x(), s.y(), s.z())
+        x, y, z = s.x(), s.y(), s.z()
+        rep = o_kkt.kkt_report(p.P_full(), p.q, sp.csr_matrix(p.A), p.l, p.u, x, y, z)
         eps_p = eps + eps * max(rep["norms"]["Ax"], rep["norms"]["z"])
         eps_d = eps + eps * max(rep["norms"]["Px"], rep["norms"]["Aty"], rep["norms"]["q"])
+        say("certificate", p.name, {k: v for k, v in rep.items() if k != "norms"})
         assert rep["prim"] <= 1.01 * eps_p and rep["dual"] <= 1.01 * eps_d
+        rnd = 1e-6 if kw.get("precision") == "mixed" else 1e-9
+        zs = max(1.0, float(np.max(np.abs(z))) if z.size else 1.0)
+        ys = max(1.0, float(np.max(np.abs(y))) if y.size else 1.0)
+        assert rep["box"] <= rnd * zs
+        assert rep["comp"] <= rnd * zs * ys
+        assert rep["inf_mult"] <= rnd * ys
+        gap_tol = 1.01 * (float(np.sum(np.abs(x))) * eps_d + float(np.sum(np.abs(y))) * eps_p) \
+            + rnd * zs * float(np.sum(np.abs(y))) + 1e-9 * max(1.0, abs(rep["obj"]))
+        assert rep["gap"] <= gap_tol, (rep["gap"], gap_tol)
         assert abs(info.obj_val - rep["obj"]) <= 1e-6 * max(1.0, abs(rep["obj"]))
         return info, rep
 

@@ -487,3 +487,24 @@ def test_method_stopped_at_eps_1e5_against_the_parity_bars(name, f_off, x_off):
     if f_off or x_off:
         f7, x7 = errs(1e-7)
         assert f7 <= 1e-5 and x7 <= 1e-4, (f7, x7)
+
+
+@pytest.mark.parametrize("name", ["random_small", "portfolio_small", "lasso_small"])
+def test_degree_ordered_factorisation_gives_the_same_iterates(name):
+    """The direct route with the static ascending-degree order (used where the library's own
+    ordering does not finish) against the library-ordered route: both factor the same
+    quasi-definite KKT matrix of eq. kkt, so the ADMM iterates agree to round-off."""
+    from paper_1912_04263_amd import problems as pr
+    p = pr.make(name)
+    P, A = p.P_full(), sp.csr_matrix(p.A)
+    a = admm.solve(P, p.q, A, p.l, p.u, eps_abs=1e-7, eps_rel=1e-7, max_iter=50000, record=30)
+    b = admm.solve(P, p.q, A, p.l, p.u, eps_abs=1e-7, eps_rel=1e-7, max_iter=50000, record=30,
+                   ordering="degree")
+    assert a.iters == b.iters
+    for (xa, za, ya), (xb, zb, yb) in zip(a.trace, b.trace):
+        for u, v in ((xa, xb), (za, zb), (ya, yb)):
+            assert np.max(np.abs(u - v)) <= 1e-12 * max(1.0, np.max(np.abs(u)))
+    assert abs(a.obj - b.obj) <= 1e-12 * max(1.0, abs(a.obj))
+    # the order really differs from the identity on these instances
+    K = admm.kkt_matrix(sp.identity(p.n, format="csr"), A, 1e-6, np.full(p.m, 0.1))
+    assert not np.array_equal(admm.degree_order(K), np.arange(K.shape[0]))
