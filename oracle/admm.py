@@ -20,7 +20,8 @@ R is ρ̄I (the choice Section 6.3 makes for the GPU solver) or OSQP's vector
 ρ_i = ρ̄ on inequalities and 10³ρ̄ on equalities (eq. rho_vec); the solution
 does not depend on R. The KKT matrix is factored once and again only when ρ̄
 changes (Section 3.2, 3.4). The sparse LU used for the factorisation is a
-library primitive; no ordering or factorisation is re-implemented here.
+library primitive; no ordering or factorisation is re-implemented here (``dense_degree`` only
+eliminates the densest rows last, by block elimination with the library's sparse and dense LU).
 
 Scaled variables (Section 3.3): x̄ = D⁻¹x, ȳ = cE⁻¹y, and z̄ = Ez. (The paper
 prints z̄ = E⁻¹z, which contradicts Ā = EAD and l̄ = El; z̄ = Āx̄ = EAx = Ez is
@@ -112,53 +113,69 @@ def kkt_matrix(Pb, Ab, sigma, rvec):
                     [Ab, -sp.diags(1.0 / rvec)]], format="csc")
 
 
-def degree_order(K):
-    """A static minimum-degree ordering: the nodes of the symmetric pattern of K by ascending
-    number of neighbours (ties by index)."""
-    deg = np.diff(sp.csr_matrix(K).indptr)
-    return np.argsort(deg, kind="stable")
-
-
 class KKTSolver:
     """Factor the quasi-definite KKT matrix once; solve many right-hand sides.
 
-    ``ordering="mmd"`` lets the library order the matrix (minimum degree on AᵀA + A);
-    ``ordering="degree"`` hands it the static ascending-degree order of ``degree_order`` instead,
-    for matrices with dense rows on which the library's ordering runs for hours (the portfolio
-    class: its factor rows hold 5·10⁴ entries). Either way the factorisation and the triangular
-    solves are the library's, and quasi-definiteness makes every symmetric order factorisable with
-    diagonal pivots (Section 3.2)."""
+    With ``dense_degree`` = 0 the whole matrix goes to the library's sparse LU (its minimum-degree
+    order on AᵀA + A, diagonal pivots). With ``dense_degree`` > 0 the nodes of more than that many
+    neighbours (the dense rows of the portfolio class, 5·10⁴ and 10⁵ entries, on which the
+    library's ordering and symbolic factorisation do not finish) are eliminated last, by block
+    Gaussian elimination of the same matrix:
+        K = [K_SS  K_SD; K_DS  K_DD],   C = K_DD − K_DS K_SS⁻¹ K_SD  (dense),
+        K_SS u = r_S,  C x_D = r_D − K_DS u,  x_S = u − K_SS⁻¹ K_SD x_D,
+    with K_SS by the library's sparse LU and C by a dense LU. Both are exact solves of eq. kkt up to
+    round-off (quasi-definiteness makes K_SS and C nonsingular, Section 3.2)."""
 
-    def __init__(self, Pb, Ab, sigma, rvec, ordering="mmd"):
+    def __init__(self, Pb, Ab, sigma, rvec, dense_degree=0):
         K = kkt_matrix(Pb, Ab, sigma, rvec)
         self.K = K
-        self.perm = None
-        if ordering == "degree":
-            self.perm = degree_order(K)
-            Kp = K[self.perm][:, self.perm].tocsc()
-            self.lu = spla.splu(Kp, permc_spec="NATURAL", diag_pivot_thresh=0.0,
-                                options=dict(SymmetricMode=True))
-            return
-        try:
-            self.lu = spla.splu(K, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
-                                options=dict(SymmetricMode=True))
-            t = np.ones(K.shape[0])
-            if not np.all(np.isfinite(self.lu.solve(t))):
-                raise RuntimeError
-        except Exception:
-            self.lu = spla.splu(K)
+        self.dense = None
+        if dense_degree > 0:
+            deg = np.diff(sp.csr_matrix(K).indptr)
+            D = np.nonzero(deg > dense_degree)[0]
+            if D.size:
+                S = np.nonzero(deg <= dense_degree)[0]
+                Kr = sp.csr_matrix(K)
+                self.dense = (S, D)
+                self.lu = self._splu(Kr[S][:, S].tocsc())
+                K_SD = np.ascontiguousarray(Kr[S][:, D].toarray())
+                self.K_DS = Kr[D][:, S].tocsr()
+                self.W = np.ascontiguousarray(self.lu.solve(K_SD))   # K_SS⁻¹ K_SD, |S|×|D|
+                C = Kr[D][:, D].toarray() - K_SD.T @ self.W          # K_DS = K_SDᵀ (K symmetric)
+                del K_SD
+                import scipy.linalg as sla
+                self.C = sla.lu_factor(C)
+                self._lu_solve_dense = sla.lu_solve
+                return
+        self.lu = self._splu(K)
 
-    def _lu_solve(self, rhs):
-        if self.perm is None:
+    @staticmethod
+    def _splu(K):
+        try:
+            lu = spla.splu(K, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                           options=dict(SymmetricMode=True))
+            t = np.ones(K.shape[0])
+            if not np.all(np.isfinite(lu.solve(t))):
+                raise RuntimeError
+            return lu
+        except Exception:
+            return spla.splu(K)
+
+    def _solve_once(self, rhs):
+        if self.dense is None:
             return self.lu.solve(rhs)
+        S, D = self.dense
+        u = self.lu.solve(rhs[S])
+        xd = self._lu_solve_dense(self.C, rhs[D] - self.K_DS @ u)
         out = np.empty_like(rhs)
-        out[self.perm] = self.lu.solve(rhs[self.perm])
+        out[D] = xd
+        out[S] = u - self.W @ xd
         return out
 
     def solve(self, rhs):
-        sol = self._lu_solve(rhs)
+        sol = self._solve_once(rhs)
         # one step of iterative refinement keeps the solve at round-off level
-        return sol - self._lu_solve(self.K @ sol - rhs)
+        return sol - self._solve_once(self.K @ sol - rhs)
 
 
 class ReducedPCGSolver:
@@ -212,7 +229,7 @@ def rho_vector(l, u, rho_bar, mode):
 def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, eps_rel=1e-9,
           max_iter=20000, scaling_iters=10, r_mode="scalar", adaptive_rho=True, rho_interval=100,
           check_every=1, record=0, x0=None, z0=None, y0=None, linsys="direct",
-          pcg_tol=1e-12, eps_pinf=1e-4, eps_dinf=1e-4, progress=None, ordering="mmd") -> AdmmResult:
+          pcg_tol=1e-12, eps_pinf=1e-4, eps_dinf=1e-4, progress=None, dense_degree=0) -> AdmmResult:
     """``progress``, if given, is called as progress(k, prim, dual, eps_prim, eps_dual, rho) after
     every residual check (reporting only; it does not change the iteration)."""
     import time
@@ -244,7 +261,7 @@ def solve(P_full, q, A, l, u, *, rho=0.1, sigma=1e-6, alpha=1.6, eps_abs=1e-9, e
     def factor(rv):
         if linsys == "pcg":
             return ReducedPCGSolver(Pb, Ab, sigma, rv, pcg_tol)
-        return KKTSolver(Pb, Ab, sigma, rv, ordering)
+        return KKTSolver(Pb, Ab, sigma, rv, dense_degree)
 
     t0 = time.perf_counter()
     kkt = factor(rvec)
