@@ -490,21 +490,39 @@ def test_method_stopped_at_eps_1e5_against_the_parity_bars(name, f_off, x_off):
 
 
 @pytest.mark.parametrize("name", ["random_small", "portfolio_small", "lasso_small"])
-def test_degree_ordered_factorisation_gives_the_same_iterates(name):
-    """The direct route with the static ascending-degree order (used where the library's own
-    ordering does not finish) against the library-ordered route: both factor the same
-    quasi-definite KKT matrix of eq. kkt, so the ADMM iterates agree to round-off."""
+def test_dense_rows_eliminated_last_give_the_same_iterates(name):
+    """The direct route with the densest KKT rows eliminated last by block elimination (used where
+    the library's own ordering does not finish on the portfolio class's dense rows) against the
+    plain library route: both are exact solves of eq. kkt, so the ADMM iterates agree to
+    round-off."""
     from paper_1912_04263_amd import problems as pr
     p = pr.make(name)
     P, A = p.P_full(), sp.csr_matrix(p.A)
+    K = admm.kkt_matrix(P, A, 1e-6, np.full(p.m, 0.1))
+    deg = np.diff(sp.csr_matrix(K).indptr)
+    cut = int(np.quantile(deg, 0.9))
+    # the split is real on these instances: some rows go to the dense block, most stay sparse
+    assert 0 < int(np.sum(deg > cut)) < K.shape[0] // 2
     a = admm.solve(P, p.q, A, p.l, p.u, eps_abs=1e-7, eps_rel=1e-7, max_iter=50000, record=30)
     b = admm.solve(P, p.q, A, p.l, p.u, eps_abs=1e-7, eps_rel=1e-7, max_iter=50000, record=30,
-                   ordering="degree")
+                   dense_degree=cut)
     assert a.iters == b.iters
     for (xa, za, ya), (xb, zb, yb) in zip(a.trace, b.trace):
         for u, v in ((xa, xb), (za, zb), (ya, yb)):
             assert np.max(np.abs(u - v)) <= 1e-12 * max(1.0, np.max(np.abs(u)))
     assert abs(a.obj - b.obj) <= 1e-12 * max(1.0, abs(a.obj))
-    # the order really differs from the identity on these instances
-    K = admm.kkt_matrix(sp.identity(p.n, format="csr"), A, 1e-6, np.full(p.m, 0.1))
-    assert not np.array_equal(admm.degree_order(K), np.arange(K.shape[0]))
+
+
+def test_block_elimination_solves_the_kkt_system():
+    """One block-eliminated solve against a dense solve of the same quasi-definite matrix."""
+    from paper_1912_04263_amd import problems as pr
+    p = pr.make("portfolio_small")
+    P, A = p.P_full(), sp.csr_matrix(p.A)
+    rv = np.full(p.m, 0.1)
+    K = admm.kkt_matrix(P, A, 1e-6, rv)
+    deg = np.diff(sp.csr_matrix(K).indptr)
+    solver = admm.KKTSolver(P, A, 1e-6, rv, dense_degree=int(np.quantile(deg, 0.95)))
+    assert solver.dense is not None
+    rhs = np.random.default_rng(7).standard_normal(K.shape[0])
+    ref = np.linalg.solve(K.toarray(), rhs)
+    assert np.max(np.abs(solver.solve(rhs) - ref)) <= 1e-9 * np.max(np.abs(ref))
