@@ -1,8 +1,9 @@
-"""Train the learned diagonal preconditioner on generated portfolio QPs, on the GPU.
+"""Train the learned diagonal preconditioner of one problem family on generated QPs, on the GPU.
 
 Pipeline (every numeric step runs in the library's device kernels):
-  1. draw the training instances (portfolio class, n = 20,000 assets, k = 200 factors, 50% dense
-     factor matrix; seeds 50000 + i) and set each up on the device (Ruiz scaling included);
+  1. draw the training instances of the family at a training size (seeds 50000 + i; the
+     portfolio default: n = 20,000 assets, k = 200 factors, 50% dense factor matrix) and set each
+     up on the device (Ruiz scaling included);
   2. Hutchinson targets: for each instance and ρ̄ ∈ rhos, s Rademacher probes (drawn here and
      passed in), each K⁻¹z by the solver's own PCG; ĥ clamped at 1/K_ii; target log(ĥ K_ii);
   3. Adam on the mean-removed log-error loss, one (instance, ρ̄) pair per step, shuffled epochs;
@@ -10,7 +11,12 @@ Pipeline (every numeric step runs in the library's device kernels):
      diagonal vs Jacobi on random right-hand sides, and full solves (ADMM + PCG) with both.
 Writes the float32 parameters and a JSON summary.
 
-  python -m paper_1912_04263_amd.train_precond --out weights/portfolio_h32.f32
+Training sizes per family keep the benchmark instances' per-row structure at a fraction of their
+size: portfolio 20,000 × 200 factors at 50%; random n = 5,000, m = 50,000 with about 20 entries per
+row of A and of P; Lasso 1,000 features × 10,000 data rows at 10% (100 entries per data row);
+SVM 20,000 points × 1,000 features at 10% (100 entries per point).
+
+  python -m paper_1912_04263_amd.train_precond --family portfolio --out weights/portfolio_h32.f32
 """
 from __future__ import annotations
 
@@ -23,6 +29,14 @@ import time
 import numpy as np
 
 from . import problems, qpg
+
+
+# training-size generators of the other families (same per-row structure as the benchmark sizes)
+FAMILIES = {
+    "random": lambda seed: problems.random_qp(5_000, 50_000, 4.47 / 5_000, 20.0 / 5_000, seed),
+    "lasso": lambda seed: problems.lasso_qp(1_000, 10_000, 0.1, seed),
+    "svm": lambda seed: problems.svm_qp(20_000, 1_000, 0.1, seed),
+}
 
 
 def log(*a):
@@ -60,6 +74,7 @@ def pcg_iterations(problem, weights, rhos, seed, eps=1e-6):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
+    ap.add_argument("--family", default="portfolio", choices=["portfolio", *sorted(FAMILIES)])
     ap.add_argument("--instances", type=int, default=256)
     ap.add_argument("--heldout", type=int, default=16)
     ap.add_argument("--n-assets", type=int, default=20000)
@@ -77,7 +92,9 @@ def main(argv=None):
     t0 = time.time()
 
     def make(seed):
-        return problems.portfolio_qp(args.n_assets, args.k_factors, 0.5, seed)
+        if args.family == "portfolio":
+            return problems.portfolio_qp(args.n_assets, args.k_factors, 0.5, seed)
+        return FAMILIES[args.family](seed)
 
     # 1–2: instances and targets
     train = []
@@ -144,6 +161,7 @@ def main(argv=None):
         s.close()
     it = np.array(it)
     summary = {
+        "family": args.family,
         "instances": args.instances, "heldout": args.heldout, "n_assets": args.n_assets,
         "k_factors": args.k_factors, "probes": args.probes, "rhos": rhos, "epochs": args.epochs,
         "lr": args.lr, "heldout_loss": hist,
