@@ -256,6 +256,23 @@ int qpg_get_kdiag(const qpg_solver* h, double rho, double* kdiag);
 int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho, double eps,
                    int32_t max_iter, double* diag);
 
+/* qpg_hutchinson without any allocation, for callers that cannot allocate device memory (code
+ * under stream capture, tight loops, harnesses that forbid hipMalloc): the same computation with
+ * the same kernels, bitwise the same diag, but the accumulator and the probe live in a static
+ * device array of QPG_NOALLOC_SCRATCH_BYTES that every device the library runs on holds for the
+ * life of the process (its address is looked up once per device, in qpg_setup). It allocates no
+ * device memory and builds none of the learned preconditioner's graph data, which qpg_hutchinson
+ * creates on first use. The handle, the probes and diag are the caller's, as for qpg_hutchinson.
+ * Limit: n ≤ QPG_NOALLOC_MAX_N (8n rounded up to 256 bytes, plus n, within the scratch), else
+ * QPG_ERR_SIZE before any device work. All calls on one device share the one scratch array:
+ * calls that overlap on a device (several host threads, several streams) race and give wrong
+ * results; the accumulator is cleared at the start of every call, so a call never sees the last
+ * call's contents. Other errors as for qpg_hutchinson. */
+#define QPG_NOALLOC_SCRATCH_BYTES 16777216 /* 16 MiB */
+#define QPG_NOALLOC_MAX_N 1864128
+int qpg_hutchinson_noalloc(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho,
+                           double eps, int32_t max_iter, double* diag);
+
 /* Network of the learned preconditioner, its evaluation on a solver's problem and its training
  * (forward, loss, backward and Adam all run on the device). Not part of the paper.
  *   create:    params = QPG_NET_NPARAMS floats, or NULL for the seeded initialisation (output

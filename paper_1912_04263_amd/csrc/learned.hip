@@ -5,6 +5,8 @@
 // PCG of Algorithm 3 is unchanged; only the Jacobi diagonal of Section 6.3.1 is replaced. The
 // message-passing trunk does not depend on ρ̄ and runs once per setup; the head is re-evaluated
 // when ρ̄ changes (Section 6.3.2 updates ρ̄ every 10 iterations).
+#include <mutex>
+
 #include "mpnn.hpp"
 #include "solver_internal.hpp"
 
@@ -326,6 +328,104 @@ void qpg_solver::learned_dinv(double rho) {
 template void qpg_solver::learned_dinv<double>(double);
 template void qpg_solver::learned_dinv<float>(double);
 
+// ------------------------------------------------------------ Hutchinson targets
+
+namespace {
+
+// Scratch of qpg_hutchinson_noalloc: the accumulator Σ_k z_k ∘ K⁻¹z_k (n doubles, then padding
+// to 256 bytes) followed by one probe (n bytes). Every device the library runs on holds one copy
+// for the life of the process; calls that overlap on one device share it and race.
+__device__ __align__(256) unsigned char scratch[QPG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+std::atomic<void*> g_scratch_addr[kScratchDevices];  // device address of `scratch`, per ordinal
+std::mutex g_scratch_mu;
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  return g_scratch_addr[device].load(std::memory_order_acquire);
+}
+
+int hutchinson_check(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho, double eps,
+                     int32_t max_iter, double* diag) {
+  if (!h || !signs || nprobes < 1 || !diag || !(rho > 0) || !(eps >= 0) || max_iter < 1)
+    return QPG_ERR_ARG;
+  if (h->s.rho_vector) {
+    h->err = "qpg_hutchinson: defined for R = rho*I (the handle was set up with rho_vector)";
+    return QPG_ERR_STATE;
+  }
+  for (long k = 0; k < (long)nprobes * h->n; ++k)
+    if (signs[k] != 1 && signs[k] != -1) {
+      h->err = "qpg_hutchinson: probe entries must be +1 or -1";
+      return QPG_ERR_ARG;
+    }
+  return QPG_OK;
+}
+
+// (1/s) Σ_k z_k ∘ K⁻¹z_k with K⁻¹z_k by the solver's Jacobi PCG from 0; acc (n doubles) and probe
+// (n bytes) are device buffers the caller provides. ρ̄ and the Jacobi diagonal are restored.
+int hutchinson_run(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho, double eps,
+                   int32_t max_iter, double* diag, double* acc, int8_t* probe) {
+  Prec<double>& V = h->p64;
+  const int n = h->n;
+  const double rho_saved = h->rho_cur;
+  struct Restore {  // ρ̄ of the handle is restored on every way out
+    qpg_solver* h;
+    double rho;
+    ~Restore() { h->rho_cur = rho; }
+  } restore{h, rho_saved};
+  h->rho_cur = rho;
+  h->jacobi<double>(rho);
+  h->fill(acc, n, 0.0);
+  for (int k = 0; k < nprobes; ++k) {
+    HIPCHK(hipMemcpyAsync(probe, signs + (size_t)k * n, n, hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL((k_probe_load<double>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, n,
+                       (const int8_t*)probe, V.b);
+    h->fill(V.xt, n, 0.0);
+    hipLaunchKernelGGL((k_absmax<double>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, n,
+                       (const double*)V.b, h->rb.partials);
+    h->finalize_fn<1, 1u>(FinThresh{h->st, eps, 1}, h->vgrid);
+    h->last_pcg = 1;
+    h->pcg_solve<double>(rho, max_iter);
+    hipLaunchKernelGGL((k_probe_acc<double>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, n,
+                       (const int8_t*)probe, (const double*)V.xt, acc);
+  }
+  HIPCHK(hipMemcpyAsync(diag, acc, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < n; ++i) diag[i] /= nprobes;
+  h->jacobi<double>(rho_saved);
+  HIPCHK(hipGetLastError());
+  return QPG_OK;
+}
+
+int hutchinson_device_error(qpg_solver* h, const HipError& e) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s failed: %s", e.what, hipGetErrorString(e.code));
+  h->err = buf;
+  (void)hipGetLastError();
+  return QPG_ERR_DEVICE;
+}
+
+}  // namespace
+
+namespace qpg {
+
+// Device address of the no-alloc scratch for the current device, looked up once per device at
+// setup. Ordinals beyond the table keep no address (qpg_hutchinson_noalloc then fails with
+// QPG_ERR_STATE on them).
+hipError_t resolve_noalloc_scratch(int device) {
+  if (device < 0 || device >= kScratchDevices) return hipSuccess;
+  if (g_scratch_addr[device].load(std::memory_order_acquire)) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device].load(std::memory_order_relaxed)) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch_addr[device].store(ptr, std::memory_order_release);
+  return e;
+}
+
+}  // namespace qpg
+
 // ================================================================================== C ABI
 
 extern "C" {
@@ -339,55 +439,39 @@ int qpg_get_kdiag(const qpg_solver* h, double rho, double* kdiag) {
 
 int qpg_hutchinson(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho, double eps,
                    int32_t max_iter, double* diag) {
-  if (!h || !signs || nprobes < 1 || !diag || !(rho > 0) || !(eps >= 0) || max_iter < 1)
-    return QPG_ERR_ARG;
-  if (h->s.rho_vector) {
-    h->err = "qpg_hutchinson: defined for R = rho*I (the handle was set up with rho_vector)";
-    return QPG_ERR_STATE;
-  }
-  for (long k = 0; k < (long)nprobes * h->n; ++k)
-    if (signs[k] != 1 && signs[k] != -1) {
-      h->err = "qpg_hutchinson: probe entries must be +1 or -1";
-      return QPG_ERR_ARG;
-    }
-  const double rho_restore = h->rho_cur;
+  const int rc = hutchinson_check(h, signs, nprobes, rho, eps, max_iter, diag);
+  if (rc) return rc;
   try {
     HIPCHK(hipSetDevice(h->device));
     LearnedState* L = ensure_graph(h);
-    Prec<double>& V = h->p64;
-    const int n = h->n;
-    const double rho_saved = h->rho_cur;
-    h->rho_cur = rho;
-    h->jacobi<double>(rho);
-    HIPCHK(hipMemsetAsync(L->acc, 0, n * sizeof(double), h->stream));
-    for (int k = 0; k < nprobes; ++k) {
-      HIPCHK(hipMemcpyAsync(L->probe, signs + (size_t)k * n, n, hipMemcpyHostToDevice, h->stream));
-      hipLaunchKernelGGL((k_probe_load<double>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, n,
-                         (const int8_t*)L->probe, V.b);
-      h->fill(V.xt, n, 0.0);
-      hipLaunchKernelGGL((k_absmax<double>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, n,
-                         (const double*)V.b, h->rb.partials);
-      h->finalize_fn<1, 1u>(FinThresh{h->st, eps, 1}, h->vgrid);
-      h->last_pcg = 1;
-      h->pcg_solve<double>(rho, max_iter);
-      hipLaunchKernelGGL((k_probe_acc<double>), dim3(h->vgrid), dim3(kBlock), 0, h->stream, n,
-                         (const int8_t*)L->probe, (const double*)V.xt, L->acc);
-    }
-    HIPCHK(hipMemcpyAsync(diag, L->acc, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    for (int i = 0; i < n; ++i) diag[i] /= nprobes;
-    h->rho_cur = rho_saved;
-    h->jacobi<double>(rho_saved);
-    HIPCHK(hipGetLastError());
+    return hutchinson_run(h, signs, nprobes, rho, eps, max_iter, diag, L->acc, L->probe);
   } catch (const HipError& e) {
-    char buf[512];
-    std::snprintf(buf, sizeof(buf), "%s failed: %s", e.what, hipGetErrorString(e.code));
-    h->err = buf;
-    (void)hipGetLastError();
-    h->rho_cur = rho_restore;
-    return QPG_ERR_DEVICE;
+    return hutchinson_device_error(h, e);
   } QPG_CATCH_HOST(h->err)
-  return QPG_OK;
+}
+
+int qpg_hutchinson_noalloc(qpg_solver* h, const int8_t* signs, int32_t nprobes, double rho,
+                           double eps, int32_t max_iter, double* diag) {
+  const int rc = hutchinson_check(h, signs, nprobes, rho, eps, max_iter, diag);
+  if (rc) return rc;
+  const size_t acc_bytes = ((size_t)h->n * sizeof(double) + 255) / 256 * 256;
+  if (acc_bytes + (size_t)h->n > (size_t)QPG_NOALLOC_SCRATCH_BYTES) {
+    h->err = "qpg_hutchinson_noalloc: n exceeds the static scratch (QPG_NOALLOC_MAX_N)";
+    return QPG_ERR_SIZE;
+  }
+  void* base = noalloc_scratch(h->device);
+  if (!base) {
+    h->err = "qpg_hutchinson_noalloc: no scratch address for this device";
+    return QPG_ERR_STATE;
+  }
+  try {
+    HIPCHK(hipSetDevice(h->device));
+    unsigned char* b = static_cast<unsigned char*>(base);
+    return hutchinson_run(h, signs, nprobes, rho, eps, max_iter, diag, reinterpret_cast<double*>(b),
+                          reinterpret_cast<int8_t*>(b + acc_bytes));
+  } catch (const HipError& e) {
+    return hutchinson_device_error(h, e);
+  } QPG_CATCH_HOST(h->err)
 }
 
 int qpg_net_create(qpg_net** out, const float* params, uint64_t seed, int32_t bf16, int32_t device) {

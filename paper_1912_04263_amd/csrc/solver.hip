@@ -839,6 +839,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
   h->stream = static_cast<hipStream_t>(settings->stream);
   try {
     HIPCHK(hipSetDevice(h->device));
+    HIPCHK(resolve_noalloc_scratch(h->device));
     // SpMV work lists: the window is sized so that a window of FP64 pairs fits in one
     // workgroup's LDS. They depend on the sparsity pattern only, so a host thread builds them
     // while the device equilibrates the values.

@@ -97,6 +97,7 @@ struct DevPlan {
 
 struct LearnedState;  // learned-preconditioner data of a solver (learned.hip)
 void destroy_learned(LearnedState* L);
+hipError_t resolve_noalloc_scratch(int device);  // learned.hip: scratch of qpg_hutchinson_noalloc
 
 }  // namespace qpg
 

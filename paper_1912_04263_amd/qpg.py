@@ -24,6 +24,7 @@ QPG_PRIMAL_INFEASIBLE, QPG_DUAL_INFEASIBLE = 4, 5
 QPG_FP64, QPG_MIXED = 0, 1
 QPG_PRECOND_JACOBI, QPG_PRECOND_LEARNED = 0, 1
 QPG_NET_NPARAMS = 16705
+QPG_NOALLOC_SCRATCH_BYTES, QPG_NOALLOC_MAX_N = 16777216, 1864128
 QPG_OP_A, QPG_OP_AT, QPG_OP_P, QPG_OP_K = 0, 1, 2, 3
 QPG_KERNEL_SPMV_A, QPG_KERNEL_SPMV_B, QPG_KERNEL_PCG_UPDATE, QPG_KERNEL_PCG_DIR = 0, 1, 2, 3
 QPG_KERNEL_SPMV_A_STREAM, QPG_KERNEL_SPMV_B_STREAM = 4, 5
@@ -91,6 +92,8 @@ SIGNATURES = {
     "qpg_cleanup": (C.c_int, [C.c_void_p]),
     "qpg_get_kdiag": (C.c_int, [C.c_void_p, C.c_double, _PD]),
     "qpg_hutchinson": (C.c_int, [C.c_void_p, _PB, C.c_int32, C.c_double, C.c_double, C.c_int32, _PD]),
+    "qpg_hutchinson_noalloc": (C.c_int, [C.c_void_p, _PB, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                         _PD]),
     "qpg_net_create": (C.c_int, [C.POINTER(C.c_void_p), _PF, C.c_uint64, C.c_int32, C.c_int32]),
     "qpg_net_get_params": (C.c_int, [C.c_void_p, _PF]),
     "qpg_net_set_params": (C.c_int, [C.c_void_p, _PF]),
@@ -310,6 +313,16 @@ class Solver:
         out = np.empty(self.n)
         self._check(lib().qpg_hutchinson(self._h, z.ctypes.data_as(_PB), z.shape[0], float(rho), float(eps),
                                          int(max_iter), _dptr(out)))
+        return out
+
+    def hutchinson_noalloc(self, signs, rho: float, eps: float = 1e-10, max_iter: int = 5000):
+        """qpg_hutchinson_noalloc: the same estimate with the library's static device scratch."""
+        z = np.ascontiguousarray(signs, dtype=np.int8)
+        if z.ndim != 2 or z.shape[1] != self.n:
+            raise ValueError("signs must be s×n")
+        out = np.empty(self.n)
+        self._check(lib().qpg_hutchinson_noalloc(self._h, z.ctypes.data_as(_PB), z.shape[0], float(rho),
+                                                 float(eps), int(max_iter), _dptr(out)))
         return out
 
     def set_rho(self, rho: float):
