@@ -6,6 +6,7 @@ which gives the same iterates) and the seeded generators. Nothing here comes fro
 
 For each workload it stores, in tests/golden/fullsize_<workload>.npz:
   x      the independent block of the minimiser (float32; the rest follows from it):
+           random_c0     all of x
            lasso_c1      the 10⁴ feature weights (y = Ad·x − b and t = |x| at the optimum)
            random_c2     all of x
            portfolio_c3  the 10⁵ asset weights (the factor block is y = Fᵀx)
@@ -34,8 +35,8 @@ sys.path.insert(0, ROOT)
 from oracle import admm  # noqa: E402
 from paper_1912_04263_amd import problems  # noqa: E402
 
-BLOCK = {"lasso_c1": 10_000, "random_c2": None, "portfolio_c3": 100_000, "svm_c4": 10_000}
-ROUTE = {"lasso_c1": "direct", "random_c2": "pcg", "portfolio_c3": "direct", "svm_c4": "pcg"}
+BLOCK = {"random_c0": None, "lasso_c1": 10_000, "random_c2": None, "portfolio_c3": 100_000, "svm_c4": 10_000}
+ROUTE = {"random_c0": "direct", "lasso_c1": "direct", "random_c2": "pcg", "portfolio_c3": "direct", "svm_c4": "pcg"}
 # the library's own fill-reducing order does not finish on the portfolio class's dense KKT rows
 # (the 10³ factor rows of 5·10⁴ entries and the budget row): those nodes are eliminated last,
 # by block elimination (oracle.admm.KKTSolver)
