@@ -9,11 +9,14 @@ Headline: the SVM workload (10⁶ points × 10⁴ features at 1%, 1.02·10⁸ ma
 largest of the five benchmark configurations and the one whose matrices (1.2–2.5 GB) cannot sit
 in the 256 MB last-level cache, in FP32-bulk / FP64-reduction arithmetic with the Jacobi
 preconditioner. Beside it, one entry per benchmark configuration (random 200×400, Lasso, large
-random, portfolio, SVM) with every precision/preconditioner variant, its objective error against
-a tight FP64 solve, and the time to reach a stated objective error.
+random, portfolio, SVM) with every precision/preconditioner variant at eps 1e-3 and its objective
+error against the oracle's minimiser (tests/golden/fullsize_<workload>.npz, where one has been
+written). With --quality-sweep, every variant is also solved at eps 1e-4, 1e-5, 1e-6 until its
+objective is within 1e-3 (relative) of a tight FP64 reference solve, and the time to that answer
+quality is reported (minutes of GPU time on the portfolio workload).
 
   python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload svm_c4] [--precision mixed]
-                  [--configs all|none|name,name,...]
+                  [--configs all|none|name,name,...] [--quality-sweep]
 """
 from __future__ import annotations
 
@@ -142,6 +145,17 @@ def cpu_baseline(problem, iters, small):
                               "eps_abs = eps_rel = 1e-3, one thread"}
 
 
+def oracle_answer(workload):
+    """f* and the status of the oracle's solve of a benchmark workload, from the stored fixture
+    (written by tests/golden/make_fullsize_fixtures.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{workload}.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(str(z["meta"]))
+    return {"f_star": meta["f_star"], "eps": meta["eps"], "route": meta["route"], "status": meta["status"]}
+
+
 def weights_for(workload, default):
     """Trained parameters of the learned preconditioner for a workload's problem family, or the
     given default set when that family has none."""
@@ -173,12 +187,19 @@ def main():
                     help="matrix entries per SpMV workgroup with an LDS window (0: library default)")
     ap.add_argument("--spmv-plain-nnz", type=int, default=0,
                     help="matrix entries per SpMV workgroup without a window (0: library default)")
+    ap.add_argument("--spmv-window-cols", type=int, default=0,
+                    help="LDS gather window capacity in columns (0: library default)")
+    ap.add_argument("--spmv-min-seg", type=int, default=0,
+                    help="entries per row and column range for a multi-range work list (0: library default)")
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--configs", default="all",
                     help="per-configuration entries: all, none, or a comma-separated list")
-    ap.add_argument("--config-reps", type=int, default=3, help="timed solves per variant (median)")
+    ap.add_argument("--config-reps", type=int, default=3, help="timed solves per variant (mean)")
+    ap.add_argument("--quality-sweep", action="store_true",
+                    help="also solve each variant at tighter eps until its objective is within 1e-3 of a "
+                         "tight FP64 reference (slow on the portfolio workload)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (reference for counter scaling)")
     args = ap.parse_args()
@@ -209,6 +230,8 @@ def main():
         kw.setdefault("max_iter", 100000)
         kw.setdefault("spmv_tile_nnz", args.spmv_tile_nnz)
         kw.setdefault("spmv_plain_nnz", args.spmv_plain_nnz)
+        kw.setdefault("spmv_window_cols", args.spmv_window_cols)
+        kw.setdefault("spmv_min_seg", args.spmv_min_seg)
         return qpg.Solver.from_qp(p, eps_abs=eps, eps_rel=eps, precision=precision, stream=stream,
                                   device=0, **extra, **kw)
 
@@ -289,24 +312,29 @@ def main():
     log(f"[bench] dominant kernel {dom['avg_us']:.1f} us = {dom['GBs']:.0f} GB/s ({roofline['frac']:.3f}); "
         f"PCG iteration {pcg_it['kernel_us']:.1f} us = {pcg_it['GBs']:.0f} GB/s ({pcg_it['frac']:.3f})")
 
+    head_orc = oracle_answer(args.workload)
+
     # ------------------------------------------------------------------ per configuration
     names = CONFIGS if args.configs == "all" else ([] if args.configs == "none" else args.configs.split(","))
     configs = {}
     for name in names:
         q = p if name == args.workload else make(name)
         wn, w = weights_for(name, args.weights)
-        ref_eps = REF_EPS.get(name, 1e-6)
-        with solver(q, "fp64", "jacobi", ref_eps) as sr:
-            ir = sr.solve()
-        fref = ir.obj_val
-        scale = max(1.0, abs(fref))
-        log(f"[bench] {name}: reference FP64/Jacobi at eps {ref_eps:g}: {ir.status}, {ir.iter} ADMM, obj {fref:.10g}")
+        orc = oracle_answer(name)
         entry = {"n": q.n, "m": q.m, "nnz_P": q.meta["nnz_P_full"], "nnz_A": q.meta["nnz_A"],
-                 "reference": {"eps": ref_eps, "obj": fref, "status": ir.status, "admm_iters": ir.iter},
-                 "learned_weights": wn, "variants": {}}
+                 "oracle": orc, "learned_weights": wn, "variants": {}}
+        fref = None
+        if args.quality_sweep:
+            ref_eps = REF_EPS.get(name, 1e-6)
+            with solver(q, "fp64", "jacobi", ref_eps) as sr:
+                ir = sr.solve()
+            fref = ir.obj_val
+            entry["reference"] = {"eps": ref_eps, "obj": fref, "status": ir.status, "admm_iters": ir.iter}
+            log(f"[bench] {name}: reference FP64/Jacobi at eps {ref_eps:g}: {ir.status}, {ir.iter} ADMM, "
+                f"obj {fref:.10g}")
         for prec, pc in VARIANTS:
             v = {}
-            for eps in QUALITY_EPS:
+            for eps in (QUALITY_EPS if args.quality_sweep else (args.eps,)):
                 with solver(q, prec, pc, eps, w) as sv:
                     inf, el = timed(sv, args.config_reps, 1)
                     setup = sv.info().setup_time
@@ -315,20 +343,27 @@ def main():
                         v["pcg_iteration"] = it
                         v["spmv_B_stream"] = {k: kern["spmv_B_stream"][k] for k in ("avg_us", "GBs", "frac")}
                 i = inf[-1]
-                err = abs(i.obj_val - fref) / scale
                 t_solve = el / len(inf)
                 rec = {"status": i.status, "tts_s": t_solve, "setup_s": setup, "tts_with_setup_s": t_solve + setup,
                        "admm_iters": i.iter, "pcg_iters": i.pcg_iter_total, "admm_iter_per_s": i.iter / t_solve,
-                       "obj": i.obj_val, "obj_rel_err_vs_ref": err, "precision_used": i.precision_used,
-                       "precond_used": i.precond_used, "precond_trials_won": [i.precond_learned_chosen, i.precond_trials]}
+                       "obj": i.obj_val, "precision_used": i.precision_used, "precond_used": i.precond_used,
+                       "precond_trials_won": [i.precond_learned_chosen, i.precond_trials]}
+                if orc:
+                    rec["obj_rel_err_vs_oracle"] = abs(i.obj_val - orc["f_star"]) / max(1.0, abs(orc["f_star"]))
+                msg = f"obj err vs oracle {rec['obj_rel_err_vs_oracle']:.2e}" if orc else "no oracle answer stored"
+                if fref is not None:
+                    err = abs(i.obj_val - fref) / max(1.0, abs(fref))
+                    rec["obj_rel_err_vs_ref"] = err
+                    msg += f", vs reference {err:.2e}"
                 if eps == args.eps:
                     v.update(rec)
-                log(f"[bench]   {prec}/{pc} eps {eps:g}: {i.status} {i.iter} ADMM / {i.pcg_iter_total} PCG, "
-                    f"solve {t_solve * 1e3:.2f} ms, setup {setup:.3f} s, obj err {err:.2e}")
-                if err <= EQUAL_QUALITY or eps == QUALITY_EPS[-1]:
-                    v["equal_quality"] = {"obj_rel_err_target": EQUAL_QUALITY, "reached": err <= EQUAL_QUALITY,
+                log(f"[bench]   {name} {prec}/{pc} eps {eps:g}: {i.status} {i.iter} ADMM / {i.pcg_iter_total} PCG, "
+                    f"solve {t_solve * 1e3:.2f} ms, setup {setup:.3f} s, {msg}")
+                if fref is not None and (rec["obj_rel_err_vs_ref"] <= EQUAL_QUALITY or eps == QUALITY_EPS[-1]):
+                    v["equal_quality"] = {"obj_rel_err_target": EQUAL_QUALITY,
+                                          "reached": rec["obj_rel_err_vs_ref"] <= EQUAL_QUALITY,
                                           "eps": eps, "tts_s": t_solve, "tts_with_setup_s": t_solve + setup,
-                                          "obj_rel_err_vs_ref": err, "admm_iters": i.iter}
+                                          "obj_rel_err_vs_ref": rec["obj_rel_err_vs_ref"], "admm_iters": i.iter}
                     break
             entry["variants"][f"{prec}/{pc}"] = v
         configs[name] = entry
@@ -362,6 +397,8 @@ def main():
                    "rho_update_every": args.rho_update_every, "check_every": args.check_every,
                    "rho_vector": args.rho_vector, "pcg_eps_schedule": args.pcg_eps_schedule,
                    "spmv_tile_nnz": args.spmv_tile_nnz, "spmv_plain_nnz": args.spmv_plain_nnz,
+                   "spmv_window_cols": args.spmv_window_cols, "spmv_min_seg": args.spmv_min_seg,
+                   "kernel_reps": args.kernel_reps,
                    "step": "one full solve from a cold start"},
         "tts_s": tts,
         "setup_s": setup_s,
@@ -370,6 +407,8 @@ def main():
         "admm_iters": last.iter,
         "pcg_iters": last.pcg_iter_total,
         "obj": last.obj_val,
+        "obj_rel_err_vs_oracle": (abs(last.obj_val - head_orc["f_star"]) / max(1.0, abs(head_orc["f_star"]))
+                                  if head_orc else None),
         "kernels": kernels,
         "roofline": roofline,
         "configs": configs,

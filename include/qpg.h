@@ -123,6 +123,12 @@ typedef struct {
                              the cap) raises a device flag that skips the rest, and the host resumes
                              there at the next read. 0: the host waits for every PCG solve (the
                              synchronous loop of Section 6.3.3). Both give bitwise the same iterates. */
+  int32_t spmv_window_cols; /* SpMV work lists: capacity in columns of a gather window staged in LDS
+                             (a power of two from 1024 to 65536; halved until a window of doubles fits
+                             the device's LDS); default 8192, 0 = default */
+  int32_t spmv_min_seg;   /* SpMV work lists: entries per row and column range on average that make
+                             a run of rows take one tile per (row block, range); 1 to 256, default 16,
+                             0 = default */
 } qpg_settings;
 
 typedef struct {

@@ -177,7 +177,11 @@ int validate_settings(const qpg_settings* s, std::string* msg) {
             s->eps_dual_inf >= 0 && std::isfinite(s->eps_prim_inf) && std::isfinite(s->eps_dual_inf) &&
             (s->rho_vector == 0 || (s->rho_vector == 1 && s->precond == QPG_PRECOND_JACOBI)) &&
             (s->pcg_eps_schedule == 0 || s->pcg_eps_schedule == 1) &&
-            (s->speculate == 0 || s->speculate == 1);
+            (s->speculate == 0 || s->speculate == 1) &&
+            (s->spmv_window_cols == 0 ||
+             (s->spmv_window_cols >= 1024 && s->spmv_window_cols <= 65536 &&
+              (s->spmv_window_cols & (s->spmv_window_cols - 1)) == 0)) &&
+            s->spmv_min_seg >= 0 && s->spmv_min_seg <= 256;
   if (!ok) {
     *msg = "settings: value out of range";
     return QPG_ERR_ARG;
@@ -383,5 +387,7 @@ extern "C" int qpg_default_settings(qpg_settings* s) {
   s->rho_vector = 0;
   s->pcg_eps_schedule = 0;
   s->speculate = 1;
+  s->spmv_window_cols = qpg::kWinCols;
+  s->spmv_min_seg = qpg::kMinSeg;
   return QPG_OK;
 }

@@ -68,20 +68,6 @@ __device__ __forceinline__ double comb(int s, double a, double b) {
   return ((MAXMASK >> s) & 1u) ? nmax(a, b) : a + b;
 }
 
-// Two values of one vector entry, loaded together (one 16-byte / 8-byte access).
-template <typename T>
-struct Pair;
-template <>
-struct Pair<double> {
-  using type = double2;
-};
-template <>
-struct Pair<float> {
-  using type = float2;
-};
-template <typename T>
-using pair_t = typename Pair<T>::type;
-
 // Matrix-stream load. Plain loads: on gfx950 the non-temporal variant measured ~30% slower for
 // this access pattern (coalesced value/index streams interleaved with random gathers).
 template <typename T>
@@ -239,31 +225,17 @@ __device__ __forceinline__ T wave_sum(T x, int width) {
 // k_combine adds each row's slots in order and runs the epilogue. Op supplies:
 //   static constexpr int NS;            reduction slots (0: none)
 //   static constexpr unsigned MAXMASK;  bit s set: slot s is an ∞-norm (max), else a sum
-//   static constexpr int NV;            products per entry: 1, or 2 (a pair of vectors)
-//   G gather(int col) const;            the multiplied value(s) of column col (G = T, or a pair)
-//   void epilogue(int row, T s1, T s2, T s3, double* red) const;
-//        s1 / s2: first product summed over the entries with column < nsplit / ≥ nsplit;
-//        s3: second product summed over the entries with column ≥ nsplit
+//   T gather(int col) const;            the multiplied value of column col
+//   void epilogue(int row, T s1, T s2, double* red) const;
+//        s1 / s2: the products summed over the entries with column < nsplit / ≥ nsplit
 //   void side() const;                  extra elementwise work (grid-stride, in k_spmv)
 //   void operator()(const double* totals) const;  scalar finalisation (run by k_finalize)
 // ----------------------------------------------------------------------------------------------
-template <class Op, typename T>
-struct Gathered {
-  using type = typename std::conditional<Op::NV == 2, pair_t<T>, T>::type;
-};
-
-template <typename T, class G>
-__device__ __forceinline__ void accumulate(T v, const G& x, bool first, T& s1, T& s2, T& s3) {
-  if constexpr (std::is_same<G, T>::value) {
-    const T pr = v * x;
-    s1 += first ? pr : T(0);
-    s2 += first ? T(0) : pr;
-  } else {
-    const T p0 = v * x.x, p1 = v * x.y;
-    s1 += first ? p0 : T(0);
-    s2 += first ? T(0) : p0;
-    s3 += first ? T(0) : p1;
-  }
+template <typename T>
+__device__ __forceinline__ void accumulate(T v, T x, bool first, T& s1, T& s2) {
+  const T pr = v * x;
+  s1 += first ? pr : T(0);
+  s2 += first ? T(0) : pr;
 }
 
 constexpr int kSpmvUnroll = 8;  // SELL steps in flight per lane
@@ -278,9 +250,8 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(const Tile* __restrict__ ti
                                                  T* __restrict__ slots, int64_t pstride, int planes,
                                                  const int32_t* __restrict__ gate) {
   if (gate && *gate) return;  // uniform across the grid: set before the launch
-  using G = typename Gathered<Op, T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  G* win = reinterpret_cast<G*>(smem);
+  T* win = reinterpret_cast<T*>(smem);
   const Tile t = tiles[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (t.wlen > 0) {
@@ -292,38 +263,38 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(const Tile* __restrict__ ti
     const Chunk ch = chunks[ci];
     const int slot = segslot[ch.seg0 + lane];
     const T* vp = val + ch.base + lane;
-    T s1 = T(0), s2 = T(0), s3 = T(0);
+    T s1 = T(0), s2 = T(0);
     if (t.wlen > 0) {
       const uint16_t* cp = col16 + ch.cbase + lane;
       const int lim = nsplit - t.wlo;  // window offsets below lim belong to the first part
 #pragma unroll kSpmvUnroll
       for (int s = 0; s < ch.steps; ++s) {
         const int o = cp[64 * s];
-        accumulate(vp[64 * s], win[o], o < lim, s1, s2, s3);
+        accumulate(vp[64 * s], win[o], o < lim, s1, s2);
       }
     } else {
       const int32_t* cp = col32 + ch.cbase + lane;
 #pragma unroll kSpmvUnroll
       for (int s = 0; s < ch.steps; ++s) {
         const int c = cp[64 * s];
-        accumulate(vp[64 * s], op.gather(c), c < nsplit, s1, s2, s3);
+        accumulate(vp[64 * s], op.gather(c), c < nsplit, s1, s2);
       }
     }
     if (slot >= 0) {
       slots[slot] = s1;
       if (planes > 1) slots[pstride + slot] = s2;
-      if (planes > 2) slots[2 * pstride + slot] = s3;
     }
   }
   op.side();
 }
 
-// Row sums from the slots, then the epilogue. 2^lg lanes per row: lane l adds slots l, l + L, …
-// of the row in order, then a fixed shuffle tree combines the lanes (deterministic). Reduction
-// partials per workgroup for k_finalize.
+// Row sums from the slots, then the epilogue. 2^lg lanes per row: lane l adds the row's slots
+// l, l + L, … (in column order, through slotidx) in order, then a fixed shuffle tree combines the
+// lanes (deterministic). Reduction partials per workgroup for k_finalize.
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__ items,
                                                     const int32_t* __restrict__ rowslot,
+                                                    const int32_t* __restrict__ slotidx,
                                                     const T* __restrict__ slots, int64_t pstride,
                                                     int planes, Op op, double* __restrict__ partials,
                                                     const int32_t* __restrict__ gate) {
@@ -336,20 +307,19 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
   const int lg = c.lg, L = 1 << lg, groups = kBlock >> lg;
   const int g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
   for (int r = c.r0 + g; r < c.r1; r += groups) {
-    T s1 = T(0), s2 = T(0), s3 = T(0);
+    T s1 = T(0), s2 = T(0);
     const int q1 = rowslot[r + 1];
 #pragma unroll 4
     for (int q = rowslot[r] + lane; q < q1; q += L) {
-      s1 += slots[q];
-      if (planes > 1) s2 += slots[pstride + q];
-      if (planes > 2) s3 += slots[2 * pstride + q];
+      const int sq = slotidx[q];
+      s1 += slots[sq];
+      if (planes > 1) s2 += slots[pstride + sq];
     }
     if (L > 1) {
       s1 = wave_sum(s1, L);
       if (planes > 1) s2 = wave_sum(s2, L);
-      if (planes > 2) s3 = wave_sum(s3, L);
     }
-    if (lane == 0) op.epilogue(r, s1, s2, s3, red);
+    if (lane == 0) op.epilogue(r, s1, s2, red);
   }
   if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }
@@ -360,8 +330,6 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
   __device__ void side() const {}
 #define QPG_NO_FIN \
   __device__ void operator()(const double*) const {}
-#define QPG_ONE_PRODUCT \
-  static constexpr int NV = 1;
 
 // out = scale · (M v)   (M = Ā, or the whole of B with v = [vp; vat]); with eq set (rows of Ā),
 // out_r = ρ_r/ρ̄ · scale · (M v)_r, i.e. w = RĀv for scale = ρ̄.
@@ -369,7 +337,6 @@ template <typename T>
 struct OpScaled {
   QPG_NO_SIDE
   QPG_NO_FIN
-  QPG_ONE_PRODUCT
   static constexpr int NS = 0;
   static constexpr unsigned MAXMASK = 0;
   const T* v;
@@ -377,7 +344,7 @@ struct OpScaled {
   T scale;
   const uint8_t* eq = nullptr;
   __device__ T gather(int c) const { return v[c]; }
-  __device__ void epilogue(int r, T s1, T s2, T, double*) const {
+  __device__ void epilogue(int r, T s1, T s2, double*) const {
     out[r] = row_rho(eq, r, scale) * (s1 + s2);
   }
 };
@@ -387,7 +354,6 @@ template <typename T>
 struct OpB {
   QPG_NO_SIDE
   QPG_NO_FIN
-  QPG_ONE_PRODUCT
   static constexpr int NS = 0;
   static constexpr unsigned MAXMASK = 0;
   const T* vp;
@@ -398,7 +364,7 @@ struct OpB {
     if (c < n) return vp ? vp[c] : T(0);
     return vat ? vat[c - n] : T(0);
   }
-  __device__ void epilogue(int r, T s1, T s2, T, double*) const { out[r] = s1 + s2; }
+  __device__ void epilogue(int r, T s1, T s2, double*) const { out[r] = s1 + s2; }
 };
 
 // Scalars of a right-hand-side pass: ‖b‖∞, the PCG threshold, r⁰ᵀM⁻¹r⁰, ‖r⁰‖∞ and the stopping
@@ -415,35 +381,48 @@ __device__ inline void rhs_scalars(DevState* st, const double* t, int maxit, int
 }
 
 // Right-hand side of the reduced KKT system (eq. kkt_red_sc) and the warm-started PCG residual
-// (Algorithm 3 initialisation) in one pass over B = [P̄ | Āᵀ]:
+// (Algorithm 3 initialisation), directly, in two passes over B = [P̄ | Āᵀ]:
 //   b  = σx − q̄ + Āᵀ(ρ̄z − y)
 //   r⁰ = Kx̃ − b = P̄x̃ + σ(x̃ − x) + q̄ + Āᵀ(ρ̄(z̃ − z) + y),  z̃ = Āx̃
 //   p⁰ = −M⁻¹r⁰;  rᵀM⁻¹r;  ‖r‖∞.
-// The gathered vectors are two planes of n + m entries in one allocation g: plane 0 holds x̃
-// for the P̄ columns, then ρ̄(z̃ − z) + y for the Āᵀ columns; plane 1 holds 0, then ρ̄z − y
-// (written by k_pairs). b is kept in bk for the next right-hand side (OpRhsRec).
+// The gathered vectors are two planes of n + m entries in one allocation g (written by k_pairs):
+// plane 0 holds x̃ for the P̄ columns, then ρ̄(z̃ − z) + y for the Āᵀ columns; plane 1 holds 0,
+// then ρ̄z − y. The first pass (OpRhsAt) leaves Āᵀ(ρ̄z − y) in bk, the second (OpRhsR0) gathers
+// plane 0 and completes b, which stays in bk for the next right-hand side (OpRhsRec).
+template <typename T>
+struct OpRhsAt {
+  QPG_NO_SIDE
+  QPG_NO_FIN
+  static constexpr int NS = 0;
+  static constexpr unsigned MAXMASK = 0;
+  const T* g1;  // plane 1 of g
+  T* bk;
+  __device__ T gather(int c) const { return g1[c]; }
+  // plane 1 is 0 on the P̄ columns: only the Āᵀ part (s2) contributes
+  __device__ void epilogue(int i, T, T s2, double*) const { bk[i] = s2; }
+};
+
 template <typename T>
 struct OpRhsR0 {
   QPG_NO_SIDE
-  static constexpr int NV = 2;
   static constexpr int NS = 3;
   static constexpr unsigned MAXMASK = 0x5u;  // ‖b‖∞, rᵀM⁻¹r, ‖r‖∞
   const T* x;
   const T* xt;
   const T* qb;
-  const T* g;  // two planes of n + m
+  const T* g;  // plane 0 of g
   const T* dinv;
   T* r;
   T* p;
-  T* bk;
+  T* bk;  // in: Āᵀ(ρ̄z − y) from OpRhsAt; out: b
   T sigma;
-  int n, m, maxit, rel;
+  int maxit, rel;
   double eps;
   DevState* st;
-  __device__ pair_t<T> gather(int c) const { return pair_t<T>{g[c], g[(size_t)(n + m) + c]}; }
-  __device__ void epilogue(int i, T s1, T s2, T s3, double* red) const {
+  __device__ T gather(int c) const { return g[c]; }
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
     const T xi = x[i];
-    const T bi = sigma * xi - qb[i] + s3;
+    const T bi = sigma * xi - qb[i] + bk[i];
     const T ri = ((s1 + sigma * (xt[i] - xi)) + qb[i]) + s2;
     const T yi = ri * dinv[i];
     r[i] = ri;
@@ -456,7 +435,7 @@ struct OpRhsR0 {
   __device__ void operator()(const double* t) const { rhs_scalars(st, t, maxit, rel, eps); }
 };
 
-// The same right-hand side and warm-started residual with one product per entry instead of two,
+// The same right-hand side and warm-started residual in one pass over B instead of two,
 // from the previous PCG solve (Algorithm 3) of K'x̃ = b' that left x̃ and its residual r' in place,
 // K' = P̄ + σI + ρ̄'ĀᵀĀ. Since r' + b' = K'x̃ and z̃ = Āx̃,
 //   ρ̄Āᵀz̃ = γ(r' + b' − P̄x̃ − σx̃),  γ = ρ̄/ρ̄'   (R = diag(ρ_i) scales by the same γ),
@@ -466,11 +445,10 @@ struct OpRhsR0 {
 // r⁰ is computed exactly as in OpRhsR0. b differs from the direct value by rounding, by the gap
 // between the recursively updated r' and K'x̃ − b', and by the error b' itself carried; it enters
 // only the stopping threshold ε‖b‖∞ and the next pass (the caller recomputes it directly from time
-// to time). The pass gathers one plane, so its LDS window holds half the bytes of OpRhsR0's.
+// to time).
 template <typename T>
 struct OpRhsRec {
   QPG_NO_SIDE
-  QPG_ONE_PRODUCT
   static constexpr int NS = 3;
   static constexpr unsigned MAXMASK = 0x5u;  // ‖b‖∞, rᵀM⁻¹r, ‖r‖∞
   const T* x;
@@ -486,7 +464,7 @@ struct OpRhsRec {
   double eps;
   DevState* st;
   __device__ T gather(int c) const { return g[c]; }
-  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
     const T xi = x[i], xti = xt[i];
     const T bi = (sigma * xi - qb[i]) + gamma * (((r[i] + bk[i]) - s1) - sigma * xti) - s2;
     const T ri = ((s1 + sigma * (xti - xi)) + qb[i]) + s2;
@@ -506,7 +484,6 @@ struct OpRhsRec {
 template <typename T>
 struct OpR0 {
   QPG_NO_SIDE
-  QPG_ONE_PRODUCT
   static constexpr int NS = 2;
   static constexpr unsigned MAXMASK = 2u;
   const T* xt;
@@ -520,7 +497,7 @@ struct OpR0 {
   int maxit;
   DevState* st;
   __device__ T gather(int c) const { return c < n ? xt[c] : w[c - n]; }
-  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
     const T ri = (s1 + s2 + sigma * xt[i]) - b[i];
     const T yi = ri * dinv[i];
     r[i] = ri;
@@ -545,7 +522,6 @@ template <typename T>
 struct OpKp {
   QPG_NO_SIDE
   QPG_NO_FIN
-  QPG_ONE_PRODUCT
   static constexpr int NS = 1;
   static constexpr unsigned MAXMASK = 0u;
   const T* p;
@@ -555,7 +531,7 @@ struct OpKp {
   int n;
   DevState* st;
   __device__ T gather(int c) const { return p[c]; }
-  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
     const T pi = p[i];
     const T k = s1 + s2 + sigma * pi;
     kp[i] = k;
@@ -575,7 +551,6 @@ struct OpKp {
 // written to it for the infeasibility tests (Section 3).
 template <typename T, bool CHECK>
 struct OpUpdate {
-  QPG_ONE_PRODUCT
   static constexpr int NS = CHECK ? 6 : 0;
   static constexpr unsigned MAXMASK = 0x3Fu;
   const T* xt;
@@ -594,7 +569,7 @@ struct OpUpdate {
   T* dxy;              // null, or n + m differences (δx̄, δȳ)
   const uint8_t* eq;   // null (R = ρ̄I), or the equality-row flags of R = diag(ρ_i)
   __device__ T gather(int c) const { return xt[c]; }
-  __device__ void epilogue(int i, T s1, T, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T, double* red) const {
     const bool e = eq && eq[i];
     const T ri = e ? T(kRhoEq) * rho : rho, ri_inv = e ? rho_inv / T(kRhoEq) : rho_inv;
     const T zi = z[i], yi = y[i];
@@ -641,7 +616,6 @@ struct OpUpdate {
 template <typename T>
 struct OpRPrim {
   QPG_NO_SIDE
-  QPG_ONE_PRODUCT
   static constexpr int NS = 6;
   static constexpr unsigned MAXMASK = 0x3Fu;
   const T* x;
@@ -649,7 +623,7 @@ struct OpRPrim {
   const double* einv;
   DevState* st;
   __device__ T gather(int c) const { return x[c]; }
-  __device__ void epilogue(int i, T s1, T, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T, double* red) const {
     const double ax = (double)s1, zi = (double)z[i], e = einv[i];
     const double rp = ax - zi;
     red[0] = nmax(red[0], fabs(rp));
@@ -670,7 +644,6 @@ struct OpRPrim {
 template <typename T>
 struct OpRDual {
   QPG_NO_SIDE
-  QPG_ONE_PRODUCT
   static constexpr int NS = 8;
   static constexpr unsigned MAXMASK = 0x3Fu;
   const T* x;
@@ -680,7 +653,7 @@ struct OpRDual {
   int n;
   DevState* st;
   __device__ T gather(int c) const { return x[c]; }  // y = x + n (one allocation)
-  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
     const double px = (double)s1, aty = (double)s2, d = dinv_scale[i];
     const double rd = px + (double)qb[i] + aty;
     red[0] = nmax(red[0], fabs(rd));
@@ -709,7 +682,6 @@ struct OpRDual {
 template <typename T>
 struct OpInfeasA {
   QPG_NO_SIDE
-  QPG_ONE_PRODUCT
   static constexpr int NS = 3;
   static constexpr unsigned MAXMASK = 0x3u;
   T* dxy;
@@ -719,7 +691,7 @@ struct OpInfeasA {
   int n;
   DevState* st;
   __device__ T gather(int c) const { return dxy[c]; }
-  __device__ void epilogue(int i, T s1, T, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T, double* red) const {
     const double e = einv[i];
     const double lo = (double)lb[i], up = (double)ub[i];
     const bool linf = lo * e <= -0.5 * kInf, uinf = up * e >= 0.5 * kInf;
@@ -745,7 +717,6 @@ struct OpInfeasA {
 template <typename T>
 struct OpInfeasB {
   QPG_NO_SIDE
-  QPG_ONE_PRODUCT
   static constexpr int NS = 4;
   static constexpr unsigned MAXMASK = 0x7u;
   const T* dxy;
@@ -753,7 +724,7 @@ struct OpInfeasB {
   const double* dinv_scale;
   DevState* st;
   __device__ T gather(int c) const { return dxy[c]; }
-  __device__ void epilogue(int i, T s1, T s2, T, double* red) const {
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
     const double d = dinv_scale[i], dx = (double)dxy[i];
     red[0] = nmax(red[0], fabs((double)s1 * d));
     red[1] = nmax(red[1], fabs((double)s2 * d));
@@ -842,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__
   if (gate && *gate) return;
   double red[1] = {0.0};
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < rows; i += gridDim.x * kBlock)
-    op.epilogue(i, s1[i], T(0), T(0), red);
+    op.epilogue(i, s1[i], T(0), red);
   op.side();
 }
 
@@ -894,7 +865,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
   }
 }
 
-// Both planes of the right-hand-side vectors read by OpRhsR0 (plane 0 also by OpRhsRec): x̃ and 0
+// Both planes of the right-hand-side vectors read by OpRhsAt / OpRhsR0 (plane 0 also by OpRhsRec): x̃ and 0
 // for the n P̄ columns, ρ̄(z̃ − z) + y and ρ̄z − y for the m Āᵀ columns. Run before every OpRhsR0
 // pass: the update passes keep only plane 0 current.
 template <typename T>

@@ -103,12 +103,15 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = 
 //
 // Row blocks are single-range (all columns) or, where rows are wide, multi-range: the columns are
 // cut at dense windows and each (block, range) gets its own windowed tile. Segment sums go to
-// slots, numbered row by row; k_combine adds each row's slots in order and runs the operation's
-// epilogue.
+// slots numbered tile by tile (the segments of one tile, in row order, get consecutive slots), so
+// that every cache line of the slot array is written by one workgroup; a row's segments are
+// listed in column order by slotidx, and k_combine adds each row's slots in that order and runs
+// the operation's epilogue.
 
 constexpr int kSegMax = 256;   // entries of one segment at most
 constexpr int kSpmvBlock = 1024; // threads per SpMV workgroup (one chunk at a time per wavefront)
 constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most; ≤ 65536)
+constexpr int kMinSeg = 16;    // entries per row and range that make a multi-range layout
 
 struct Chunk {
   int32_t base;   // first value (SELL order)
@@ -132,7 +135,8 @@ struct TilePlan {
   std::vector<CombItem> comb;
   std::vector<Chunk> chunks;
   std::vector<int32_t> segslot;  // per segment (64 per chunk, −1 for an empty lane): output slot
-  std::vector<int32_t> rowslot;  // nrows + 1: the slots of row r are [rowslot[r], rowslot[r + 1])
+  std::vector<int32_t> rowslot;  // nrows + 1: row r has the segments [rowslot[r], rowslot[r + 1])
+  std::vector<int32_t> slotidx;  // per segment in row order (column order within a row): its slot
   hvec<int32_t> src;             // per SELL value position: CSR index, −1 for padding
   hvec<uint16_t> col16;          // column offsets of windowed tiles (SELL order)
   hvec<int32_t> col32;           // columns of the other tiles (SELL order)
@@ -145,6 +149,7 @@ struct TileParams {
   int32_t tile_nnz;   // target entries per windowed tile
   int32_t plain_nnz;  // target entries per tile without a window
   int32_t max_rows;   // rows per block at most
+  int32_t min_seg = kMinSeg;  // entries per row and range (on average) for a multi-range layout
 };
 
 // nrows × ncols CSR matrix (row pointers rowptr[0..nrows], column indices col[rowptr[0] ..

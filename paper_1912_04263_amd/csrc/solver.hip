@@ -211,9 +211,9 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     launch_update(false, nullptr);
     return j + 1;
   };
-  // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual in one pass over B: from
-  // the previous solve's residual and right-hand side when they are in place (OpRhsRec, one
-  // product per entry), else directly (OpRhsR0, two products, after k_pairs). The recurrence
+  // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual: in one pass over B from
+  // the previous solve's residual and right-hand side when they are in place (OpRhsRec), else
+  // directly in two (OpRhsAt, OpRhsR0, after k_pairs). The recurrence
   // carries the error of b' (the gap between the recursive and the true residual of each solve)
   // into b, so b is recomputed directly every kRhsRefresh iterations; in FP64 the carried error
   // stays at rounding level, in FP32 the refresh bounds it.
@@ -226,7 +226,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       finalize(rc, spmv_B<T>(rc, gate), gate);
     } else {
       pairs<T>(rho);
-      OpRhsR0<T> rr{V.x, V.xt, V.qb, V.g, V.dinv, V.r, V.p, V.bk, (T)sigma, n, m,
+      spmv_B<T>(OpRhsAt<T>{V.g + (size_t)n + m, V.bk}, gate);
+      OpRhsR0<T> rr{V.x, V.xt, V.qb, V.g, V.dinv, V.r, V.p, V.bk, (T)sigma,
                     s.pcg_max_iter, s.pcg_rel_test, eps_pcg, st};
       finalize(rr, spmv_B<T>(rr, gate), gate);
     }
@@ -645,7 +646,8 @@ int time_kernel_impl(qpg_solver* h, int kernel, int reps, double* avg_us) {
 TilePlan qpg_solver::plan_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows,
                                int32_t ncols) const {
   TileParams tp{win_cols, s.spmv_tile_nnz > 0 ? s.spmv_tile_nnz : kTileNnz,
-                s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows};
+                s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows,
+                s.spmv_min_seg > 0 ? s.spmv_min_seg : kMinSeg};
   return make_tiles(rowptr, col, nrows, ncols, tp);
 }
 
@@ -659,11 +661,12 @@ void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t
   pl.chunks = upload(t.chunks);
   pl.segslot = upload(t.segslot);
   pl.rowslot = upload(t.rowslot);
+  pl.slotidx = upload(t.slotidx);
   pl.col16 = upload(t.col16);
   pl.col32 = upload(t.col32);
   pl.nslot = t.nslot;
   pl.nrows = nrows;
-  pl.slots = alloc<double>(3 * (size_t)std::max<int64_t>(t.nslot, 1));
+  pl.slots = alloc<double>(2 * (size_t)std::max<int64_t>(t.nslot, 1));
   pl.max_wlen = t.max_wlen;
   int64_t staged = 0, wtiles = 0;
   for (const Tile& x : t.tiles) {
@@ -845,9 +848,8 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     // while the device equilibrates the values.
     int lds_max = 0;
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
-    h->win_cols = kWinCols;
-    while (h->win_cols > 1024 &&
-           (size_t)h->win_cols * sizeof(double2) + 1024 > (size_t)lds_max)
+    h->win_cols = settings->spmv_window_cols > 0 ? settings->spmv_window_cols : kWinCols;
+    while (h->win_cols > 1024 && (size_t)h->win_cols * sizeof(double) + 1024 > (size_t)lds_max)
       h->win_cols >>= 1;
     TilePlan ta, tb;
     std::exception_ptr plan_err;

@@ -81,6 +81,7 @@ struct DevPlan {
   Chunk* chunks = nullptr;
   int32_t* segslot = nullptr;
   int32_t* rowslot = nullptr;
+  int32_t* slotidx = nullptr;
   CombItem* comb = nullptr;
   int32_t ncomb = 0;
   uint16_t* col16 = nullptr;
@@ -191,8 +192,7 @@ struct qpg_solver {
            bool combine = true, void* slots = nullptr, double* partials = nullptr) {
     T* sl = static_cast<T*>(slots ? slots : pl.slots);
     double* pa = partials ? partials : rb.partials;
-    using G = typename Gathered<Op, T>::type;
-    const size_t shmem = (size_t)pl.max_wlen * sizeof(G);
+    const size_t shmem = (size_t)pl.max_wlen * sizeof(T);
     // The dynamic LDS limit is a per-device attribute of each instantiation: raise it once per
     // device (always, for device ordinals beyond the table).
     constexpr int kDevTable = 64;
@@ -212,7 +212,7 @@ struct qpg_solver {
                        pl.segslot, pl.col16, pl.col32, val, nsplit, op, sl, pl.nslot, planes, gate);
     if (!combine) return 0;
     hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
-                       (const T*)sl, pl.nslot, planes, op, pa, gate);
+                       pl.slotidx, (const T*)sl, pl.nslot, planes, op, pa, gate);
     return pl.ncomb;
   }
   template <typename T, class Op>
@@ -221,7 +221,7 @@ struct qpg_solver {
   }
   template <typename T, class Op>
   int spmv_B(const Op& op, const int32_t* gate = nullptr) {
-    return spmv<T>(plan_b, n, Op::NV == 2 ? 3 : 2, op, gate);
+    return spmv<T>(plan_b, n, 2, op, gate);
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
   template <class Op>

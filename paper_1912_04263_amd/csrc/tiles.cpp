@@ -3,17 +3,17 @@
 //
 // Rows are grouped into runs of similar length. For each run, a histogram of its column indices
 // over fixed windows of wcap columns decides the layout:
-//   * multi-range, when at least two windows each hold ≥ kMinSeg entries per row on average and
+//   * multi-range, when at least two windows each hold ≥ min_seg entries per row on average and
 //     together at least half of the run's entries: the columns are cut at those windows, and each
 //     (row block, range) gets a tile that stages its window in LDS. Each range costs every row one
-//     slot at least, hence the kMinSeg floor;
+//     slot at least, hence the min_seg floor (TileParams);
 //   * single-range otherwise: one windowed tile per row block, the window being either the block's
 //     whole column span when it fits, or the run's densest wcap-wide window when that holds at
 //     least half of the block's entries.
 // A window is staged only if it holds at least one entry per 16 of its columns, so that staging
 // never reads more than the gathers it replaces. Entries outside every staged window go to tiles
 // without a window, of about plain_nnz entries each. Runs whose rows are too sparse for any
-// window but spread over several 2^17-column ranges (≥ kMinSeg entries per row in each) are cut
+// window but spread over several 2^17-column ranges (≥ min_seg entries per row in each) are cut
 // at those ranges too, and their tiles are issued range by range (L2 locality of the gathers).
 #include <algorithm>
 #include <cmath>
@@ -26,7 +26,6 @@ namespace qpg {
 
 namespace {
 
-constexpr int kMinSeg = 16;         // entries per row and range for a multi-range layout
 constexpr int64_t kMinTiles = 512;  // workgroups a launch should have (two per compute unit)
 constexpr int64_t kMinTileNnz = 1024;
 constexpr int kLanes = 64;
@@ -272,10 +271,10 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       });
       for (Hist& h : part) hist.merge(h);
     }
-    std::vector<int64_t> S2;  // L2-sized column ranges holding kMinSeg entries per row
+    std::vector<int64_t> S2;  // L2-sized column ranges holding min_seg entries per row
     int64_t covS2 = 0;
     for (int64_t w : touched_2)
-      if (cnt2[w] >= kMinSeg * rows_g) {
+      if (cnt2[w] >= (int64_t)tp.min_seg * rows_g) {
         S2.push_back(w);
         covS2 += cnt2[w];
       }
@@ -285,7 +284,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     std::vector<int64_t> S;  // qualifying windows (sorted)
     int64_t covS = 0;
     for (int64_t w : touched_w)
-      if (cnt[w] >= kMinSeg * rows_g) {
+      if (cnt[w] >= (int64_t)tp.min_seg * rows_g) {
         S.push_back(w);
         covS += cnt[w];
       }
@@ -444,6 +443,40 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       }
     }
   });
+  // ---- slot numbers tile by tile. Up to here a segment's id is its position in row order
+  // (rowslot); each tile's segments now get consecutive slots in that order, and slotidx maps
+  // the row-order id to the slot.
+  {
+    const size_t nt = plan.tiles.size();
+    std::vector<int64_t> first(nt + 1, 0);
+    for (size_t ti = 0; ti < nt; ++ti) {
+      const Tile& t = plan.tiles[ti];
+      int64_t c = 0;
+      for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
+        for (int32_t j = 0; j < kLanes; ++j) c += plan.segslot[(size_t)plan.chunks[ci].seg0 + j] >= 0;
+      first[ti + 1] = first[ti] + c;
+    }
+    plan.slotidx.assign((size_t)plan.nslot, -1);
+    parallel_chunks((int64_t)nt, 8, [&](int64_t, int64_t t0, int64_t t1) {
+      std::vector<int32_t> ids;
+      for (int64_t ti = t0; ti < t1; ++ti) {
+        const Tile& t = plan.tiles[ti];
+        ids.clear();
+        for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
+          for (int32_t j = 0; j < kLanes; ++j) {
+            const int32_t id = plan.segslot[(size_t)plan.chunks[ci].seg0 + j];
+            if (id >= 0) ids.push_back(id);
+          }
+        std::sort(ids.begin(), ids.end());
+        for (size_t k = 0; k < ids.size(); ++k) plan.slotidx[ids[k]] = (int32_t)(first[ti] + (int64_t)k);
+        for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
+          for (int32_t j = 0; j < kLanes; ++j) {
+            int32_t& sl = plan.segslot[(size_t)plan.chunks[ci].seg0 + j];
+            if (sl >= 0) sl = plan.slotidx[sl];
+          }
+      }
+    });
+  }
   // combine work: lanes per row ≈ a quarter of the row's slots (1..64), the largest over the
   // rows of one workgroup; a workgroup of kBlock threads takes one pass of consecutive rows
   auto lg_of = [&](int32_t q) {

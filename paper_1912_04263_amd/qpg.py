@@ -14,7 +14,8 @@ import numpy as np
 import scipy.sparse as sp
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqpg.so")
+# QPG_LIBRARY names another build of the same library (same ABI), e.g. to compare two builds
+LIB_PATH = os.environ.get("QPG_LIBRARY") or os.path.join(HERE, "libqpg.so")
 
 QPG_OK = 0
 QPG_ERR_ARG, QPG_ERR_DATA, QPG_ERR_SIZE, QPG_ERR_DEVICE, QPG_ERR_OOM, QPG_ERR_STATE = -1, -2, -3, -4, -5, -6
@@ -50,7 +51,8 @@ class Settings(C.Structure):
                 ("precond_weights", C.POINTER(C.c_float)), ("precond_trial", C.c_int32),
                 ("spmv_tile_nnz", C.c_int32), ("spmv_plain_nnz", C.c_int32),
                 ("eps_prim_inf", C.c_double), ("eps_dual_inf", C.c_double), ("rho_vector", C.c_int32),
-                ("pcg_eps_schedule", C.c_int32), ("speculate", C.c_int32)]
+                ("pcg_eps_schedule", C.c_int32), ("speculate", C.c_int32),
+                ("spmv_window_cols", C.c_int32), ("spmv_min_seg", C.c_int32)]
 
 
 class Info(C.Structure):

@@ -102,6 +102,24 @@ int main(int argc, char** argv) {
       if (covered[k] != 1) FAIL("entry %ld covered %d times", k, covered[k]);
     for (long q = 0; q < p.nslot; ++q)
       if (!slotset[q]) FAIL("slot %ld never written", q);
+    // slotidx is a permutation of the slots, and every tile writes one contiguous range of them
+    if ((long)p.slotidx.size() != p.nslot) FAIL("slotidx size");
+    std::vector<int> seen(std::max<int64_t>(p.nslot, 1), 0);
+    for (long q = 0; q < p.nslot; ++q) {
+      if (p.slotidx[q] < 0 || p.slotidx[q] >= p.nslot || seen[p.slotidx[q]]++) FAIL("slotidx not a permutation");
+    }
+    for (const Tile& t : p.tiles) {
+      long lo = p.nslot, hi = -1, cnt = 0;
+      for (int ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
+        for (int j = 0; j < 64; ++j) {
+          const int sl = p.segslot[p.chunks[ci].seg0 + j];
+          if (sl < 0) continue;
+          lo = std::min<long>(lo, sl);
+          hi = std::max<long>(hi, sl);
+          ++cnt;
+        }
+      if (cnt && hi - lo + 1 != cnt) FAIL("tile slots not contiguous");
+    }
     std::vector<int> combined(nrows, 0);
     for (const CombItem& c : p.comb) {
       if (c.lg < 0 || c.lg > 6 || c.r0 < 0 || c.r1 > nrows || c.r0 >= c.r1) FAIL("combine item");
@@ -113,8 +131,8 @@ int main(int argc, char** argv) {
     for (int r = 0; r < nrows; ++r) {
       double s1 = 0, s2 = 0;
       for (int q = p.rowslot[r]; q < p.rowslot[r + 1]; ++q) {
-        s1 += part1[q];
-        s2 += part2[q];
+        s1 += part1[p.slotidx[q]];
+        s2 += part2[p.slotidx[q]];
       }
       err = std::max(err, std::fabs(s1 - ref1[r]) + std::fabs(s2 - ref2[r]));
       scale = std::max(scale, std::fabs(ref1[r]) + std::fabs(ref2[r]));

@@ -47,6 +47,7 @@ int main(void) {
          offsetof(qpg_settings, rho_vector), offsetof(qpg_settings, pcg_eps_schedule));
   printf("%zu %d %d\n", offsetof(qpg_info, infeas_checks), QPG_PRIMAL_INFEASIBLE, QPG_DUAL_INFEASIBLE);
   printf("%zu %zu\n", offsetof(qpg_settings, speculate), offsetof(qpg_info, spec_resumes));
+  printf("%zu %zu\n", offsetof(qpg_settings, spmv_window_cols), offsetof(qpg_settings, spmv_min_seg));
   printf("%d\n", QPG_NET_NPARAMS);
   return 0;
 }
@@ -65,7 +66,8 @@ int main(void) {
             S.precond_weights.offset, S.precond_trial.offset, S.spmv_plain_nnz.offset,
             S.eps_prim_inf.offset, S.eps_dual_inf.offset, S.rho_vector.offset, S.pcg_eps_schedule.offset,
             I.infeas_checks.offset, qpg.QPG_PRIMAL_INFEASIBLE, qpg.QPG_DUAL_INFEASIBLE,
-            S.speculate.offset, I.spec_resumes.offset, qpg.QPG_NET_NPARAMS]
+            S.speculate.offset, I.spec_resumes.offset, S.spmv_window_cols.offset, S.spmv_min_seg.offset,
+            qpg.QPG_NET_NPARAMS]
     assert got == want
 
 
