@@ -103,7 +103,8 @@ typedef struct {
                              solve. 0: always learned. In both cases a capped or broken-down learned
                              solve switches to Jacobi. */
   int32_t spmv_tile_nnz;  /* SpMV work-list granularity: matrix entries per workgroup when it stages
-                             a gather window in LDS; default 32768, 0 = default */
+                             a gather window in LDS; default 65536 (fewer on matrices with fewer than
+                             512 such tiles' worth of entries), 0 = default */
   int32_t spmv_plain_nnz; /* the same for workgroups without a window; default 8192, 0 = default */
   double eps_prim_inf;    /* ε_pinf of the primal infeasibility test (Section 3.1), relative to
                              ‖δy‖∞; default 1e-4; 0 disables the test */
@@ -125,7 +126,8 @@ typedef struct {
                              synchronous loop of Section 6.3.3). Both give bitwise the same iterates. */
   int32_t spmv_window_cols; /* SpMV work lists: capacity in columns of a gather window staged in LDS
                              (a power of two from 1024 to 65536; halved until a window of doubles fits
-                             the device's LDS); default 8192, 0 = default */
+                             the device's LDS, and on each matrix until it is at most half the entries
+                             of a windowed tile); default 16384, 0 = default */
   int32_t spmv_min_seg;   /* SpMV work lists: entries per row and column range on average that make
                              a run of rows take one tile per (row block, range); 1 to 256, default 16,
                              0 = default */

@@ -101,14 +101,15 @@ int check_csc(const qpg_csc* M, int32_t nrows, int32_t ncols, bool upper, const 
 }
 
 // Builds a CSR matrix (nrows rows) from entries produced column by column: emit(j, put) calls
-// put(row, column, value) for the entries of column j in order. Rows come out in the order a
+// put(row, column, payload) for the entries of column j in order (the payload is the entry's value,
+// or its index in the source arrays). Rows come out in the order a
 // serial pass over the columns would produce. The columns are cut into parts of about equal work
 // (work[j] = number of entries column j emits, as a prefix array); each part counts its entries
 // per row, the counts give each part its own write position in every row, and a second pass
 // writes them. The result does not depend on the number of parts.
-template <class Emit>
+template <class Emit, typename V>
 void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& work, Emit emit,
-                     std::vector<int32_t>& ptr, hvec<int32_t>& col, hvec<double>& val) {
+                     std::vector<int32_t>& ptr, hvec<int32_t>& col, hvec<V>& val) {
   const int64_t total = work[ncols];
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   const int T = total < (1 << 18) ? 1 : std::min(16, hw);
@@ -121,7 +122,7 @@ void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& w
   parallel_chunks(T, 1, [&](int64_t t, int64_t, int64_t) {
     auto& c = pos[t];
     c.assign(nrows, 0);
-    for (int32_t j = cut[t]; j < cut[t + 1]; ++j) emit(j, [&](int32_t r, int32_t, double) { c[r]++; });
+    for (int32_t j = cut[t]; j < cut[t + 1]; ++j) emit(j, [&](int32_t r, int32_t, V) { c[r]++; });
   });
   ptr.assign((size_t)nrows + 1, 0);
   parallel_chunks(nrows, 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
@@ -147,7 +148,7 @@ void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& w
   parallel_chunks(T, 1, [&](int64_t t, int64_t, int64_t) {
     auto& o = pos[t];
     for (int32_t j = cut[t]; j < cut[t + 1]; ++j)
-      emit(j, [&](int32_t r, int32_t c, double v) {
+      emit(j, [&](int32_t r, int32_t c, V v) {
         col[o[r]] = c;
         val[o[r]++] = v;
       });
@@ -286,9 +287,7 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
   // ---- full P in CSR from its upper triangle in CSC (Section 6.2). Visiting the triangle's
   // columns in order emits, for row i, first the entries (i, k < i) and the diagonal (from
   // column i), then (i, j > i) from later columns: each row comes out sorted.
-  std::vector<int32_t> p_ptr;
   hvec<int32_t> p_col;
-  hvec<double> p_val;
   columns_to_rows(
       n, n, p_work,
       [&](int32_t j, auto&& put) {
@@ -299,38 +298,32 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
           put(i, j, v);              // (i, j), i ≤ j
         }
       },
-      p_ptr, p_col, p_val);
-  // ---- A in CSR (visiting the CSC columns in order keeps each row's columns sorted)
+      H.p_ptr, p_col, H.p_val);
+  // ---- A in CSR: the pattern, and each entry's index in the CSC arrays (visiting the CSC columns
+  // in order keeps each row's columns sorted); the values follow on the device
   columns_to_rows(
       n, m, a_work,
       [&](int32_t j, auto&& put) {
-        for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k) put(A->rowidx[k], j, A->val[k]);
+        for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k) put(A->rowidx[k], j, (int32_t)k);
       },
-      H.a_ptr, H.a_col, H.a_val);
+      H.a_ptr, H.a_col, H.a_src);
+  H.a_csc_val = A->val;
+  H.a_colptr = A->colptr;
   // ---- B = [P | Aᵀ]: row i is row i of the full P, then column i of A (CSC of A = CSR of Aᵀ)
   constexpr int64_t kRows = 1 << 13;  // rows or columns per parallel chunk
   H.b_ptr.assign(n + 1, 0);
   H.b_split.resize(n);
   for (int32_t i = 0; i < n; ++i)
-    H.b_ptr[i + 1] = H.b_ptr[i] + (p_ptr[i + 1] - p_ptr[i]) + (A->colptr[i + 1] - A->colptr[i]);
+    H.b_ptr[i + 1] = H.b_ptr[i] + (H.p_ptr[i + 1] - H.p_ptr[i]) + (A->colptr[i + 1] - A->colptr[i]);
   H.b_col.resize(H.b_ptr[n]);
-  H.b_val.resize(H.b_ptr[n]);
   parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
     for (int64_t i = lo; i < hi; ++i) {
       int32_t o = H.b_ptr[i];
-      for (int32_t k = p_ptr[i]; k < p_ptr[i + 1]; ++k, ++o) {
-        H.b_col[o] = p_col[k];
-        H.b_val[o] = p_val[k];
-      }
+      for (int32_t k = H.p_ptr[i]; k < H.p_ptr[i + 1]; ++k, ++o) H.b_col[o] = p_col[k];
       H.b_split[i] = o;
-      for (int32_t k = A->colptr[i]; k < A->colptr[i + 1]; ++k, ++o) {
-        H.b_col[o] = n + A->rowidx[k];
-        H.b_val[o] = A->val[k];
-      }
+      for (int32_t k = A->colptr[i]; k < A->colptr[i + 1]; ++k, ++o) H.b_col[o] = n + A->rowidx[k];
     }
   });
-  hvec<int32_t>().swap(p_col);
-  hvec<double>().swap(p_val);
 
   // ---- q, and the bounds with infinities clamped to ±kInf (Ruiz equilibration, Algorithm 2,
   // runs on the device on these raw values)

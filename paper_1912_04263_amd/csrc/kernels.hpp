@@ -290,11 +290,14 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(const Tile* __restrict__ ti
 
 // Row sums from the slots, then the epilogue. 2^lg lanes per row: lane l adds the row's slots
 // l, l + L, … (in column order, through slotidx) in order, then a fixed shuffle tree combines the
-// lanes (deterministic). Reduction partials per workgroup for k_finalize.
+// lanes (deterministic). A grid item (lg < 0) gives each row one lane, which adds the row's K
+// slots tbase[t0 + j] + row in order: consecutive lanes read consecutive slots. Reduction
+// partials per workgroup for k_finalize.
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__ items,
                                                     const int32_t* __restrict__ rowslot,
                                                     const int32_t* __restrict__ slotidx,
+                                                    const int32_t* __restrict__ tbase,
                                                     const T* __restrict__ slots, int64_t pstride,
                                                     int planes, Op op, double* __restrict__ partials,
                                                     const int32_t* __restrict__ gate) {
@@ -304,6 +307,22 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
   const CombItem c = items[blockIdx.x];
+  if (c.lg < 0) {
+    const int r = c.r0 + threadIdx.x;
+    if (r < c.r1) {
+      T s1 = T(0), s2 = T(0);
+      const int32_t* tb = tbase + c.t0;
+#pragma unroll 8
+      for (int j = 0; j < -c.lg; ++j) {
+        const int64_t q = (int64_t)tb[j] + r;
+        s1 += slots[q];
+        if (planes > 1) s2 += slots[pstride + q];
+      }
+      op.epilogue(r, s1, s2, red);
+    }
+    if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
+    return;
+  }
   const int lg = c.lg, L = 1 << lg, groups = kBlock >> lg;
   const int g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
   for (int r = c.r0 + g; r < c.r1; r += groups) {
@@ -862,6 +881,24 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(int n, T* __restrict__ dinv,
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
     const double c = colsq_eq ? colsq[i] + (kRhoEq - 1.0) * colsq_eq[i] : colsq[i];
     dinv[i] = (T)(1.0 / (diagP[i] + sigma + rho * c));
+  }
+}
+
+// The unscaled iterates of a solve (Section 3.3): x = D x̄, y = E ȳ / c, z = E⁻¹ z̄, in double,
+// into out = [x; y; z]; de holds D (n) then E (m).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_unscale(int n, int m, const T* __restrict__ x, const T* __restrict__ y,
+                                                    const T* __restrict__ z, const double* __restrict__ de,
+                                                    double c, double* __restrict__ out) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n + m; i += gridDim.x * kBlock) {
+    if (i < n) {
+      out[i] = (double)x[i] * de[i];
+    } else {
+      const int j = i - n;
+      const double e = de[i];
+      out[i] = e * (double)y[j] / c;
+      out[(size_t)n + m + j] = (double)z[j] / e;
+    }
   }
 }
 

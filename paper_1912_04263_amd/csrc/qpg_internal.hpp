@@ -63,7 +63,7 @@ constexpr int kBlock = 256;         // threads per workgroup (4 wavefronts of 64
 constexpr int kStreamCap = 2048;    // nnz staged through LDS by one workgroup (rows fully inside)
 constexpr int kLongCap = 65536;     // a longer row is split into chunks of at most kChunk nnz
 constexpr int kChunk = 32768;
-constexpr int kTileNnz = 32768;    // SpMV entries per workgroup with an LDS gather window
+constexpr int kTileNnz = 65536;    // SpMV entries per workgroup with an LDS gather window
 constexpr int kPlainNnz = 8192;    // SpMV entries per workgroup without one
 constexpr int kTileMaxRows = 4096; // rows per SpMV row block at most
 
@@ -110,8 +110,11 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap = 
 
 constexpr int kSegMax = 256;   // entries of one segment at most
 constexpr int kSpmvBlock = 1024; // threads per SpMV workgroup (one chunk at a time per wavefront)
-constexpr int kWinCols = 8192; // LDS gather window capacity in columns (at most; ≤ 65536)
+constexpr int kWinCols = 16384; // LDS gather window capacity in columns (at most; ≤ 65536)
 constexpr int kMinSeg = 16;    // entries per row and range that make a multi-range layout
+constexpr int kGridMinSeg = 2; // entries per row and window that make a grid layout (see tiles.cpp)
+constexpr int kGridMaxRows = 16384;  // rows of a grid block at most
+constexpr int kGridRound = 512;      // grid tiles that run at once (two 1024-thread workgroups per CU)
 
 struct Chunk {
   int32_t base;   // first value (SELL order)
@@ -125,9 +128,11 @@ struct Tile {
   int32_t chunk0, nchunk, wlo, wlen;
 };
 
-// k_combine work: rows [r0, r1), 2^lg lanes per row (rows with many slots share them out).
+// k_combine work: rows [r0, r1), 2^lg lanes per row (rows with many slots share them out); or,
+// with lg = −K < 0, rows of a grid block: one lane per row, whose K slots are tbase[t0 + j] + row
+// (j = 0..K−1, column order), t0 = the block's first tile.
 struct CombItem {
-  int32_t r0, r1, lg, pad;
+  int32_t r0, r1, lg, t0;
 };
 
 struct TilePlan {
@@ -137,6 +142,7 @@ struct TilePlan {
   std::vector<int32_t> segslot;  // per segment (64 per chunk, −1 for an empty lane): output slot
   std::vector<int32_t> rowslot;  // nrows + 1: row r has the segments [rowslot[r], rowslot[r + 1])
   std::vector<int32_t> slotidx;  // per segment in row order (column order within a row): its slot
+  std::vector<int32_t> tbase;    // per tile of a grid block: its first slot minus the block's first row
   hvec<int32_t> src;             // per SELL value position: CSR index, −1 for padding
   hvec<uint16_t> col16;          // column offsets of windowed tiles (SELL order)
   hvec<int32_t> col32;           // columns of the other tiles (SELL order)
@@ -150,6 +156,7 @@ struct TileParams {
   int32_t plain_nnz;  // target entries per tile without a window
   int32_t max_rows;   // rows per block at most
   int32_t min_seg = kMinSeg;  // entries per row and range (on average) for a multi-range layout
+  bool grid = true;           // the grid layout may be used (see tiles.cpp)
 };
 
 // nrows × ncols CSR matrix (row pointers rowptr[0..nrows], column indices col[rowptr[0] ..
@@ -163,18 +170,25 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
 // in chunk order are the same on every machine.
 void parallel_chunks(int64_t n, int64_t chunk, const std::function<void(int64_t, int64_t, int64_t)>& f);
 
-// The problem after validation and format conversion on the host, values unscaled.
+// The problem after validation and format conversion on the host, values unscaled. The host
+// converts the sparsity patterns; the values are placed on the device (qpg_solver::place_raw).
 struct HostProblem {
   int32_t n = 0, m = 0;
-  // A in CSR (m rows, n columns)
+  // A in CSR (m rows, n columns): pattern, and for each entry its index in A's CSC arrays
   std::vector<int32_t> a_ptr;
   hvec<int32_t> a_col;
-  hvec<double> a_val;
+  hvec<int32_t> a_src;
   // B = [P | Aᵀ] in CSR (n rows, n + m columns): row i holds row i of the full P (columns
   // 0..n−1) followed by row i of Aᵀ (columns n + j); b_split[i] is where the Aᵀ part starts.
   std::vector<int32_t> b_ptr, b_split;
   hvec<int32_t> b_col;
-  hvec<double> b_val;
+  // values: the full P in CSR (row i is the first part of B's row i); A's CSC values and column
+  // pointers, the caller's arrays, read during setup (column i of A is the second part of B's
+  // row i, in the same order)
+  std::vector<int32_t> p_ptr;
+  hvec<double> p_val;
+  const double* a_csc_val = nullptr;
+  const int32_t* a_colptr = nullptr;
   std::vector<double> qb, lb, ub;      // q, and l, u clamped to ±kInf
   std::vector<uint8_t> eqrow;          // l_i = u_i (eq. rho_vec); filled when settings.rho_vector
   double q_norm_unscaled = 0.0;        // ‖q‖∞ of the original data

@@ -274,6 +274,23 @@ __global__ __launch_bounds__(kBlock) void k_gather_values(int64_t count, const i
   }
 }
 
+// Values of B = [P | Aᵀ] in CSR (unscaled): row i is row i of the full P (p_val from p_ptr[i]),
+// then column i of A (A's CSC values from a_colptr[i]), both contiguous; one wavefront per row.
+__global__ __launch_bounds__(kBlock) void k_assemble_b(int n, const int32_t* __restrict__ b_ptr,
+                                                       const int32_t* __restrict__ b_split,
+                                                       const int32_t* __restrict__ p_ptr,
+                                                       const double* __restrict__ p_val,
+                                                       const int32_t* __restrict__ a_colptr,
+                                                       const double* __restrict__ a_csc_val,
+                                                       double* __restrict__ b_val) {
+  const int lane = threadIdx.x & 63;
+  for (int i = (blockIdx.x * kBlock + threadIdx.x) >> 6; i < n; i += (gridDim.x * kBlock) >> 6) {
+    const int32_t o = b_ptr[i], sp = b_split[i], p0 = p_ptr[i], a0 = a_colptr[i];
+    for (int32_t k = lane; k < sp - o; k += 64) b_val[o + k] = p_val[p0 + k];
+    for (int32_t k = lane; k < b_ptr[i + 1] - sp; k += 64) b_val[sp + k] = a_csc_val[a0 + k];
+  }
+}
+
 #undef QPG_ROW_LOOP
 
 }  // namespace qpg

@@ -15,8 +15,7 @@ thread_local std::string g_setup_error;
 
 void qpg_solver::alloc_prec64(const HostProblem& H) {
   Prec<double>& V = p64;
-  V.a_val = upload(H.a_val);
-  V.b_val = upload(H.b_val);
+  place_raw(H);
   V.qb = upload(H.qb);
   V.lb = upload(H.lb);
   V.ub = upload(H.ub);
@@ -36,6 +35,86 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.g = alloc<double>(2 * ((size_t)n + m));
   V.dxy = alloc<double>((size_t)n + m);
   V.ready = true;
+}
+
+constexpr size_t kStagingBytes = size_t(32) << 20;  // each of the two pinned staging buffers
+
+void qpg_solver::copy_h2d(void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return;
+  if (bytes < kStagingBytes / 4) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+    return;
+  }
+  for (int b = 0; b < 2; ++b)
+    if (!staging[b]) {
+      HIPCHK(hipHostMalloc(&staging[b], kStagingBytes, hipHostMallocDefault));
+      HIPCHK(hipEventCreateWithFlags(&staging_done[b], hipEventDisableTiming));
+    }
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  for (size_t off = 0; off < bytes; off += kStagingBytes) {
+    const size_t len = std::min(kStagingBytes, bytes - off);
+    const int b = staging_next;
+    staging_next ^= 1;
+    HIPCHK(hipEventSynchronize(staging_done[b]));  // the DMA of this buffer's last piece is done
+    char* buf = static_cast<char*>(staging[b]);
+    parallel_chunks((int64_t)len, int64_t(2) << 20, [&](int64_t, int64_t lo, int64_t hi) {
+      std::memcpy(buf + lo, s + off + lo, (size_t)(hi - lo));
+    });
+    HIPCHK(hipMemcpyAsync(d + off, buf, len, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipEventRecord(staging_done[b], stream));
+  }
+}
+
+void qpg_solver::release_staging() {
+  for (int b = 0; b < 2; ++b) {
+    if (staging_done[b]) {
+      (void)hipEventSynchronize(staging_done[b]);
+      (void)hipEventDestroy(staging_done[b]);
+      staging_done[b] = nullptr;
+    }
+    if (staging[b]) {
+      (void)hipHostFree(staging[b]);
+      staging[b] = nullptr;
+    }
+  }
+}
+
+// Raw (unscaled) values of Ā and B on the device, from the caller's CSC values of A and the full
+// P in CSR: Ā's values gathered through the CSR → CSC index map the host built with the pattern,
+// B's rows assembled from P's rows and A's columns. The staging buffers are freed on return.
+void qpg_solver::place_raw(const HostProblem& H) {
+  Prec<double>& V = p64;
+  const size_t nnz_a = H.a_src.size(), nnz_b = H.b_col.size();
+  V.a_val = alloc<double>(nnz_a);
+  V.b_val = alloc<double>(nnz_b);
+  std::vector<void*> tmp;
+  auto tmp_copy = [&](const void* src, size_t bytes) {
+    void* d = nullptr;
+    HIPCHK(hipMalloc(&d, std::max<size_t>(bytes, 1)));
+    tmp.push_back(d);
+    copy_h2d(d, src, bytes);
+    return d;
+  };
+  try {
+    const double* av = static_cast<const double*>(tmp_copy(H.a_csc_val, nnz_a * sizeof(double)));
+    const int32_t* src = static_cast<const int32_t*>(tmp_copy(H.a_src.data(), nnz_a * sizeof(int32_t)));
+    const int32_t* acp = static_cast<const int32_t*>(tmp_copy(H.a_colptr, ((size_t)n + 1) * sizeof(int32_t)));
+    const int32_t* pp = static_cast<const int32_t*>(tmp_copy(H.p_ptr.data(), ((size_t)n + 1) * sizeof(int32_t)));
+    const double* pv = static_cast<const double*>(tmp_copy(H.p_val.data(), H.p_val.size() * sizeof(double)));
+    if (nnz_a) {
+      const int g = (int)std::min<size_t>((nnz_a + kBlock - 1) / kBlock, 65536);
+      hipLaunchKernelGGL(k_gather_values, dim3(g), dim3(kBlock), 0, stream, (int64_t)nnz_a, src, av, V.a_val);
+    }
+    const int gb = std::max(1, std::min((n + 3) / 4, 16384));
+    hipLaunchKernelGGL(k_assemble_b, dim3(gb), dim3(kBlock), 0, stream, n, (const int32_t*)b_ptr,
+                       (const int32_t*)b_split, pp, pv, acp, av, V.b_val);
+    HIPCHK(hipStreamSynchronize(stream));
+  } catch (...) {
+    for (void* d : tmp) (void)hipFree(d);
+    throw;
+  }
+  for (void* d : tmp) HIPCHK(hipFree(d));
 }
 
 // FP32 copies of the equilibrated device data (matrix values in CSR; the SELL copies are placed
@@ -412,6 +491,7 @@ int qpg_solver::solve() {
   auto t0 = std::chrono::steady_clock::now();
   info.status = QPG_UNSOLVED;
   cert_valid = false;
+  have_out = false;
   info.iter = 0;
   info.pcg_iter_total = 0;
   info.pcg_iter_max = 0;
@@ -475,37 +555,20 @@ int qpg_solver::solve() {
   info.rho_final = rho;
   info.precond_used = last_precond_learned ? QPG_PRECOND_LEARNED : QPG_PRECOND_JACOBI;
   info.precision_used = use32 ? QPG_MIXED : QPG_FP64;
-  // unscaled iterates: x = D x̄, z = E⁻¹ z̄, y = E ȳ / c
-  x_out.assign(n, 0.0);
-  y_out.assign(m, 0.0);
-  z_out.assign(m, 0.0);
-  if (use32) {
-    std::vector<float> xf(n), yf(m), zf(m);
-    HIPCHK(hipMemcpyAsync(xf.data(), p32.x, n * sizeof(float), hipMemcpyDeviceToHost, stream));
-    if (m) {
-      HIPCHK(hipMemcpyAsync(yf.data(), p32.y, m * sizeof(float), hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipMemcpyAsync(zf.data(), p32.z, m * sizeof(float), hipMemcpyDeviceToHost, stream));
-    }
-    HIPCHK(hipStreamSynchronize(stream));
-    for (int i = 0; i < n; ++i) x_out[i] = xf[i];
-    for (int i = 0; i < m; ++i) {
-      y_out[i] = yf[i];
-      z_out[i] = zf[i];
-    }
-  } else {
-    HIPCHK(hipMemcpyAsync(x_out.data(), p64.x, n * sizeof(double), hipMemcpyDeviceToHost, stream));
-    if (m) {
-      HIPCHK(hipMemcpyAsync(y_out.data(), p64.y, m * sizeof(double), hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipMemcpyAsync(z_out.data(), p64.z, m * sizeof(double), hipMemcpyDeviceToHost, stream));
-    }
-    HIPCHK(hipStreamSynchronize(stream));
-  }
+  // unscaled iterates x = D x̄, z = E⁻¹ z̄, y = E ȳ / c, formed on the device and copied once into
+  // pinned host memory
+  const int gu = grid_for(n + m);
+  if (use32)
+    hipLaunchKernelGGL((k_unscale<float>), dim3(gu), dim3(kBlock), 0, stream, n, m, (const float*)p32.x,
+                       (const float*)p32.y, (const float*)p32.z, (const double*)de, c, out_dev);
+  else
+    hipLaunchKernelGGL((k_unscale<double>), dim3(gu), dim3(kBlock), 0, stream, n, m, (const double*)p64.x,
+                       (const double*)p64.y, (const double*)p64.z, (const double*)de, c, out_dev);
+  HIPCHK(hipMemcpyAsync(out_host, out_dev, ((size_t)n + 2 * (size_t)m) * sizeof(double), hipMemcpyDeviceToHost,
+                        stream));
+  HIPCHK(hipStreamSynchronize(stream));
   HIPCHK(hipGetLastError());
-  for (int i = 0; i < n; ++i) x_out[i] *= D[i];
-  for (int i = 0; i < m; ++i) {
-    y_out[i] = E[i] * y_out[i] / c;
-    z_out[i] = z_out[i] / E[i];
-  }
+  have_out = true;
   info.iter = k_end;
   info.solve_time = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return QPG_OK;
@@ -647,7 +710,10 @@ TilePlan qpg_solver::plan_tiles(const std::vector<int32_t>& rowptr, const int32_
                                int32_t ncols) const {
   TileParams tp{win_cols, s.spmv_tile_nnz > 0 ? s.spmv_tile_nnz : kTileNnz,
                 s.spmv_plain_nnz > 0 ? s.spmv_plain_nnz : kPlainNnz, kTileMaxRows,
-                s.spmv_min_seg > 0 ? s.spmv_min_seg : kMinSeg};
+                s.spmv_min_seg > 0 ? s.spmv_min_seg : kMinSeg,
+                // the grid layout stages windows of 16384 columns for short rows: it pays in float
+                // (64 KB of LDS per window), not in double (128 KB, one workgroup per CU)
+                s.precision == QPG_MIXED};
   return make_tiles(rowptr, col, nrows, ncols, tp);
 }
 
@@ -662,6 +728,7 @@ void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t
   pl.segslot = upload(t.segslot);
   pl.rowslot = upload(t.rowslot);
   pl.slotidx = upload(t.slotidx);
+  pl.tbase = upload(t.tbase);
   pl.col16 = upload(t.col16);
   pl.col32 = upload(t.col32);
   pl.nslot = t.nslot;
@@ -688,7 +755,7 @@ void qpg_solver::place_values(DevPlan& pl, const double* csr_val, bool fp32) {
   int32_t* src = nullptr;
   HIPCHK(hipMalloc((void**)&src, std::max<size_t>(count, 1) * sizeof(int32_t)));
   try {
-    if (count) HIPCHK(hipMemcpyAsync(src, pl.src.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    copy_h2d(src, pl.src.data(), count * sizeof(int32_t));
     pl.val64 = alloc<double>(count);
     if (count) {
       const int g = (int)std::min<size_t>((count + kBlock - 1) / kBlock, 65536);
@@ -758,6 +825,8 @@ void qpg_solver::equilibrate() {
     c = st_host->norms[kRuizC];
     qb_norm = st_host->norms[kRuizQmax];
     scaling_passes = passes;
+    de = alloc<double>((size_t)n + m);
+    HIPCHK(hipMemcpyAsync(de, Dd, ((size_t)n + m) * sizeof(double), hipMemcpyDeviceToDevice, stream));
     D.resize(n);
     E.resize(m);
     diagP_h.resize(n);
@@ -843,30 +912,38 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
   try {
     HIPCHK(hipSetDevice(h->device));
     HIPCHK(resolve_noalloc_scratch(h->device));
-    // SpMV work lists: the window is sized so that a window of FP64 pairs fits in one
-    // workgroup's LDS. They depend on the sparsity pattern only, so a host thread builds them
-    // while the device equilibrates the values.
+    // SpMV work lists: the window capacity is capped so that a window of doubles fits in one
+    // workgroup's LDS. They depend on the sparsity pattern only, so two host threads (Ā, B)
+    // build them while the device equilibrates the values.
     int lds_max = 0;
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->win_cols = settings->spmv_window_cols > 0 ? settings->spmv_window_cols : kWinCols;
     while (h->win_cols > 1024 && (size_t)h->win_cols * sizeof(double) + 1024 > (size_t)lds_max)
       h->win_cols >>= 1;
     TilePlan ta, tb;
-    std::exception_ptr plan_err;
-    std::thread planner([&]() {
+    std::exception_ptr plan_err_a, plan_err_b;
+    std::thread planner_a([&]() {
       try {
         ta = h->plan_tiles(H.a_ptr, H.a_col.data(), H.m, H.n);
-        tb = h->plan_tiles(H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
       } catch (...) {
-        plan_err = std::current_exception();
+        plan_err_a = std::current_exception();
       }
     });
-    struct Join {  // the planner reads H: it is joined on every way out of this block
-      std::thread& t;
-      ~Join() {
-        if (t.joinable()) t.join();
+    std::thread planner_b([&]() {
+      try {
+        tb = h->plan_tiles(H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
+      } catch (...) {
+        plan_err_b = std::current_exception();
       }
-    } join{planner};
+    });
+    struct Join {  // the planners read H: they are joined on every way out of this block
+      std::thread& a;
+      std::thread& b;
+      ~Join() {
+        if (a.joinable()) a.join();
+        if (b.joinable()) b.join();
+      }
+    } join{planner_a, planner_b};
     Plan pa = make_plan(H.a_ptr, H.m);
     Plan pb = make_plan(H.b_ptr, H.n);
     for (Plan* pl : {&pa, &pb})
@@ -892,6 +969,9 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     mark("index uploads", h->stream);
     h->dscale = h->alloc<double>(H.n);
     h->escale = h->alloc<double>(H.m);
+    h->out_dev = h->alloc<double>((size_t)H.n + 2 * (size_t)H.m);
+    HIPCHK(hipHostMalloc((void**)&h->out_host, ((size_t)H.n + 2 * (size_t)H.m) * sizeof(double),
+                         hipHostMallocDefault));
     // partials hold up to max(work lists, vector grids) workgroups; the work-list counts are
     // known once the planner is done, so size them for the vector grids first
     int maxgrid = std::max(1024, std::max(h->na_items, h->nb_items));
@@ -906,8 +986,10 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     mark("value uploads", h->stream);
     h->equilibrate();
     mark("equilibration (device)", h->stream);
-    planner.join();
-    if (plan_err) std::rethrow_exception(plan_err);
+    planner_a.join();
+    planner_b.join();
+    if (plan_err_a) std::rethrow_exception(plan_err_a);
+    if (plan_err_b) std::rethrow_exception(plan_err_b);
     mark("work lists (wait for the host thread)", nullptr);
     h->upload_plan(h->plan_a, ta, H.a_ptr, H.m);
     h->upload_plan(h->plan_b, tb, H.b_ptr, H.n);
@@ -936,6 +1018,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->stream));
+    h->release_staging();
     mark("vectors, preconditioner", nullptr);
   } catch (const HipError& e) {
     int code = device_error(nullptr, e);
@@ -968,22 +1051,22 @@ int qpg_solve(qpg_solver* h) {
 
 int qpg_get_x(const qpg_solver* h, double* x) {
   if (!h || !x) return QPG_ERR_ARG;
-  if (h->x_out.size() != (size_t)h->n) return QPG_ERR_STATE;
-  std::copy(h->x_out.begin(), h->x_out.end(), x);
+  if (!h->have_out) return QPG_ERR_STATE;
+  std::copy(h->out_host, h->out_host + h->n, x);
   return QPG_OK;
 }
 
 int qpg_get_y(const qpg_solver* h, double* y) {
   if (!h || (!y && h->m > 0)) return QPG_ERR_ARG;
-  if (h->y_out.size() != (size_t)h->m) return QPG_ERR_STATE;
-  std::copy(h->y_out.begin(), h->y_out.end(), y);
+  if (!h->have_out) return QPG_ERR_STATE;
+  std::copy(h->out_host + h->n, h->out_host + h->n + h->m, y);
   return QPG_OK;
 }
 
 int qpg_get_z(const qpg_solver* h, double* z) {
   if (!h || (!z && h->m > 0)) return QPG_ERR_ARG;
-  if (h->z_out.size() != (size_t)h->m) return QPG_ERR_STATE;
-  std::copy(h->z_out.begin(), h->z_out.end(), z);
+  if (!h->have_out) return QPG_ERR_STATE;
+  std::copy(h->out_host + h->n + h->m, h->out_host + h->n + 2 * (size_t)h->m, z);
   return QPG_OK;
 }
 

@@ -82,6 +82,7 @@ struct DevPlan {
   int32_t* segslot = nullptr;
   int32_t* rowslot = nullptr;
   int32_t* slotidx = nullptr;
+  int32_t* tbase = nullptr;
   CombItem* comb = nullptr;
   int32_t ncomb = 0;
   uint16_t* col16 = nullptr;
@@ -130,7 +131,11 @@ struct qpg_solver {
   Prec<float> p32;
 
   // host copies
-  std::vector<double> D, E, diagP_h, colsq_h, x_out, y_out, z_out;
+  std::vector<double> D, E, diagP_h, colsq_h;
+  double* de = nullptr;        // D (n) then E (m) on the device
+  double* out_dev = nullptr;   // unscaled x (n), y (m), z (m) of the last solve, on the device
+  double* out_host = nullptr;  // the same in pinned host memory
+  bool have_out = false;
   std::vector<double> cert_x, cert_y;  // normalised δx, δy of the last infeasibility check
   bool cert_valid = false;
   double c = 1.0, q_norm = 0.0, qb_norm = 0.0;
@@ -156,9 +161,18 @@ struct qpg_solver {
   template <typename T, class A>
   T* upload(const std::vector<T, A>& h) {
     T* d = alloc<T>(h.size());
-    if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+    copy_h2d(d, h.data(), h.size() * sizeof(T));
     return d;
   }
+  // Host → device copy on the stream. Large copies go through two pinned staging buffers (the
+  // next piece is copied into one by several host threads while the DMA engine reads the other);
+  // the source may be released on return. Small ones are queued directly from the source, which
+  // must then stay valid until the stream has reached them.
+  void copy_h2d(void* dst, const void* src, size_t bytes);
+  void release_staging();
+  void* staging[2] = {nullptr, nullptr};
+  hipEvent_t staging_done[2] = {nullptr, nullptr};
+  int staging_next = 0;
   template <typename T, typename S, class A>
   T* upload_as(const std::vector<S, A>& h) {
     qpg::hvec<T> t(h.size());
@@ -181,6 +195,8 @@ struct qpg_solver {
     if (learned) qpg::destroy_learned(learned);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
+    if (out_host) (void)hipHostFree(out_host);
+    release_staging();
   }
 
   // ----------------------------------------------------------------- launches
@@ -212,7 +228,7 @@ struct qpg_solver {
                        pl.segslot, pl.col16, pl.col32, val, nsplit, op, sl, pl.nslot, planes, gate);
     if (!combine) return 0;
     hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
-                       pl.slotidx, (const T*)sl, pl.nslot, planes, op, pa, gate);
+                       pl.slotidx, pl.tbase, (const T*)sl, pl.nslot, planes, op, pa, gate);
     return pl.ncomb;
   }
   template <typename T, class Op>
@@ -335,6 +351,7 @@ struct qpg_solver {
   void upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows);
   void place_values(DevPlan& pl, const double* csr_val, bool fp32);
   void alloc_prec64(const HostProblem& H);
+  void place_raw(const HostProblem& H);
   void alloc_prec32();
   void equilibrate();
 };

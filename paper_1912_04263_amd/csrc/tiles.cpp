@@ -78,10 +78,13 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
   TilePlan plan;
   plan.rowslot.assign((size_t)std::max(nrows, 0) + 1, 0);
   if (nrows <= 0) return plan;
-  const int32_t wcap = tp.wcap;
   // smaller tiles on small matrices, so that the launch still has ~kMinTiles of them
   const int64_t nnz_all = (int64_t)rowptr[nrows] - rowptr[0];
   const int32_t tile_nnz = (int32_t)std::max<int64_t>(kMinTileNnz, std::min<int64_t>(tp.tile_nnz, nnz_all / kMinTiles));
+  // window capacity: at most half a windowed tile's entries, so that staging a full window costs
+  // at most one column per two entries streamed (a power of two, at least 1024 columns)
+  int32_t wcap = tp.wcap;
+  while (wcap > 1024 && wcap > tile_nnz / 2) wcap >>= 1;
   const int32_t plain_nnz = (int32_t)std::max<int64_t>(kMinTileNnz, std::min<int64_t>(tp.plain_nnz, nnz_all / kMinTiles));
   // segment length: short segments on small matrices, so that a lane's serial chain stays short
   int32_t seg_max = kSegMax;
@@ -113,10 +116,18 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
   // `lanes`, the array offsets from running counts); the entries are written afterwards, chunk
   // by chunk in parallel.
   std::vector<Seg> lanes;  // 64 per chunk; len −1 for an empty lane
+  std::vector<Seg> sorted;
   int64_t n_src = 0, n_c16 = 0, n_c32 = 0;
-  auto add_tile = [&](std::vector<Seg>& segs, int32_t wlo, int32_t wlen) {
-    if (segs.empty()) return;
-    std::stable_sort(segs.begin(), segs.end(), [](const Seg& a, const Seg& b) { return a.len > b.len; });
+  auto add_tile = [&](std::vector<Seg>& segs, int32_t wlo, int32_t wlen, bool keep_empty = false) {
+    if (segs.empty() && !keep_empty) return;
+    {  // stable counting sort by length, longest first (lengths are 0..seg_max)
+      std::vector<int32_t> pos((size_t)seg_max + 2, 0);
+      for (const Seg& g : segs) pos[(size_t)(seg_max - g.len) + 1]++;
+      for (size_t b = 1; b < pos.size(); ++b) pos[b] += pos[b - 1];
+      sorted.resize(segs.size());
+      for (const Seg& g : segs) sorted[(size_t)pos[(size_t)(seg_max - g.len)]++] = g;
+      segs.swap(sorted);
+    }
     const bool win = wlen > 0;
     Tile t{};
     t.chunk0 = (int32_t)plan.chunks.size();
@@ -162,11 +173,14 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
   struct Block {
     int32_t b0, b1;
     std::vector<int32_t> wlo, wlen;
+    bool grid = false;  // asked for: one segment (possibly empty) per row and range
+    bool grid_ok = false;  // granted: every row's entries lie in the windows, ≤ seg_max per range
   };
   // bounds of every row of a block (3K + 1 entry positions per row, binary searches) and the
   // number of segments each row is cut into; reads the matrix only
-  auto bounds = [&](const Block& bl, int32_t K, int32_t* bnd, int32_t* np, const std::vector<int64_t>& cut) {
+  auto bounds = [&](Block& bl, int32_t K, int32_t* bnd, int32_t* np, const std::vector<int64_t>& cut) {
     const int32_t stride = 3 * K + 1;
+    bool grid_ok = bl.grid;
     for (int32_t i = 0; i < bl.b1 - bl.b0; ++i) {
       const int32_t r = bl.b0 + i;
       int32_t* B = bnd + (size_t)i * stride;
@@ -181,17 +195,41 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
         B[3 * j + 2] = ie;
         B[3 * j + 3] = e;
         c += pieces(a, ia) + pieces(ia, ie) + pieces(ie, e);
+        if (grid_ok && (a != ia || ie != e || bl.wlen[j] == 0 || ie - ia > seg_max)) grid_ok = false;
       }
       np[i] = c;
     }
+    bl.grid_ok = grid_ok;
+    if (grid_ok)
+      for (int32_t i = 0; i < bl.b1 - bl.b0; ++i) np[i] = K;
   };
   // slots, segments and tiles of a block from its bounds, in row order
   std::vector<std::vector<Seg>> wsegs;
+  std::vector<int32_t> tile_b0;  // per tile: the first row of its grid block, or −1
+  struct GridBlock {
+    int32_t b0, b1, K, t0;
+  };
+  std::vector<GridBlock> grids;
   auto emit = [&](const Block& bl, int32_t K, const int32_t* bnd, const int32_t* np,
                   std::vector<std::vector<Seg>>* by_range) {
     const int32_t stride = 3 * K + 1, Rb = bl.b1 - bl.b0;
     for (int32_t i = 0; i < Rb; ++i) plan.rowslot[bl.b0 + i + 1] = plan.rowslot[bl.b0 + i] + np[i];
     wsegs.assign(K, {});
+    if (bl.grid_ok) {
+      for (int32_t i = 0; i < Rb; ++i) {
+        const int32_t* B = bnd + (size_t)i * stride;
+        int32_t next = plan.rowslot[bl.b0 + i];
+        for (int32_t j = 0; j < K; ++j) wsegs[j].push_back({B[3 * j + 1], B[3 * j + 2] - B[3 * j + 1], next++});
+      }
+      const int32_t t0 = (int32_t)plan.tiles.size();
+      for (int32_t j = 0; j < K; ++j) {
+        add_tile(wsegs[j], bl.wlo[j], bl.wlen[j], true);
+        tile_b0.resize(plan.tiles.size(), -1);
+        tile_b0.back() = bl.b0;
+      }
+      grids.push_back({bl.b0, bl.b1, K, t0});
+      return;
+    }
     for (int32_t i = 0; i < Rb; ++i) {
       const int32_t* B = bnd + (size_t)i * stride;
       int32_t next = plan.rowslot[bl.b0 + i];
@@ -289,6 +327,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
         covS += cnt[w];
       }
     std::sort(S.begin(), S.end());
+
     // densest wcap-wide window on the fine grid
     std::sort(touched_f.begin(), touched_f.end());
     int64_t best = 0, best_lo = 0, best_hi = 0;
@@ -313,6 +352,26 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
         best_hi = std::min<int64_t>((touched_f[bh] + 1) << fsh, ncols);
       }
     }
+    // grid windows (sparse rows spread over all columns): the run's column span, in fine bins,
+    // cut into K ≤ wcap wide windows of near-equal width (window j: bins ⌊j·nf/K⌋ to
+    // ⌊(j+1)·nf/K⌋), each holding kGridMinSeg entries per row or more
+    std::vector<int64_t> gcut, cntG;
+    bool grid_run = false;
+    if (tp.grid && !touched_f.empty()) {
+      const int64_t fb = int64_t(1) << fsh, f0 = touched_f.front(), f1 = touched_f.back() + 1;
+      const int64_t nf = f1 - f0, K = (nf * fb + wcap - 1) / wcap;
+      if (K >= 2 && (nf + K - 1) / K * fb <= wcap) {
+        for (int64_t j = 0; j <= K; ++j) gcut.push_back(std::min<int64_t>((f0 + j * nf / K) * fb, ncols));
+        cntG.assign((size_t)K, 0);
+        size_t j = 0;
+        for (int64_t f : touched_f) {
+          while ((f0 + (int64_t)(j + 1) * nf / K) <= f) ++j;
+          cntG[j] += fine[f];
+        }
+        grid_run = true;
+        for (int64_t c : cntG) grid_run = grid_run && c >= (int64_t)kGridMinSeg * rows_g;
+      }
+    }
     std::vector<int64_t> cntS(S.size());
     for (size_t j = 0; j < S.size(); ++j) cntS[j] = cnt[S[j]];
     for (int64_t w : touched_w) cnt[w] = 0;
@@ -320,7 +379,38 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     touched_w.clear();
     touched_f.clear();
 
-    if (S.size() >= 2 && 2 * covS >= nnz_g) {
+    if (!(S.size() >= 2 && 2 * covS >= nnz_g) && grid_run) {
+      // ---- grid blocks: ranges are the windows, one segment per row and window (empty ones
+      // included, so that row r's slot in the block's tile j is that tile's first slot + r − b0);
+      // a block whose rows do not all fit falls back to the multi-range emission
+      const int32_t K = (int32_t)cntG.size();
+      std::vector<int64_t> cut(gcut);
+      cut[K] = ncols;
+      const double aseg = (double)nnz_g / (double)(rows_g * K);
+      // blocks of equal size (whole chunks): about tile_nnz entries per tile, but no more tiles than
+      // one round of two workgroups per compute unit when that keeps blocks within kGridMaxRows
+      const int64_t Rmax = std::max<int64_t>(
+          kLanes, std::min<int64_t>(kGridMaxRows, (int64_t)(tile_nnz / std::max(aseg, 1.0)) / kLanes * kLanes));
+      int64_t nb = (rows_g + Rmax - 1) / Rmax;
+      const int64_t nb_round = std::max<int64_t>(1, kGridRound / K);
+      if (nb * K > kGridRound && (rows_g + nb_round - 1) / nb_round <= kGridMaxRows) nb = nb_round;
+      const int32_t R = (int32_t)(((rows_g + nb - 1) / nb + kLanes - 1) / kLanes * kLanes);
+      std::vector<Block> blocks;
+      for (int32_t b0 = g0; b0 < g1; b0 += R) {
+        const int32_t b1 = std::min(g1, b0 + R), Rb = b1 - b0;
+        Block bl{b0, b1, std::vector<int32_t>(K, 0), std::vector<int32_t>(K, 0), true};
+        for (int32_t j = 0; j < K; ++j) {
+          const int32_t w0 = (int32_t)gcut[j];
+          const int32_t wl = (int32_t)(gcut[j + 1] - gcut[j]);
+          if (cntG[j] * Rb / rows_g * 16 >= wl) {
+            bl.wlo[j] = w0;
+            bl.wlen[j] = wl;
+          }
+        }
+        blocks.push_back(std::move(bl));
+      }
+      run_blocks(blocks, cut, nullptr, keep);
+    } else if (S.size() >= 2 && 2 * covS >= nnz_g) {
       // ---- multi-range blocks
       const int32_t K = (int32_t)S.size();
       std::vector<int64_t> cut(K + 1);
@@ -476,6 +566,11 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
           }
       }
     });
+    // grid tiles: row r of the block has its slot at first + (r − b0)
+    tile_b0.resize(nt, -1);
+    plan.tbase.assign(std::max<size_t>(nt, 1), 0);
+    for (size_t ti = 0; ti < nt; ++ti)
+      if (tile_b0[ti] >= 0) plan.tbase[ti] = (int32_t)(first[ti] - tile_b0[ti]);
   }
   // combine work: lanes per row ≈ a quarter of the row's slots (1..64), the largest over the
   // rows of one workgroup; a workgroup of kBlock threads takes one pass of consecutive rows
@@ -486,9 +581,17 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     return lg;
   };
   int32_t r = 0;
+  size_t gi = 0;  // next grid block (in row order)
   while (r < nrows) {
+    if (gi < grids.size() && grids[gi].b0 == r) {
+      const GridBlock& gb = grids[gi++];
+      for (int32_t a = gb.b0; a < gb.b1; a += kBlock) plan.comb.push_back({a, std::min(gb.b1, a + kBlock), -gb.K, gb.t0});
+      r = gb.b1;
+      continue;
+    }
+    const int32_t stop = gi < grids.size() ? grids[gi].b0 : nrows;
     int32_t lg = lg_of(r), r1 = r + 1;
-    while (r1 < nrows) {
+    while (r1 < stop) {
       const int32_t l2 = std::max(lg, lg_of(r1));
       if (r1 + 1 - r > (kBlock >> l2)) break;
       lg = l2;

@@ -53,7 +53,7 @@ int main(int argc, char** argv) {
     if (p.col16.size() + p.col32.size() != p.src.size()) FAIL("column arrays");
     std::vector<int> covered(nnz, 0), slotset(std::max<int64_t>(p.nslot, 1), 0);
     std::vector<double> part1(std::max<int64_t>(p.nslot, 1), 0.0), part2(part1);
-    long windowed = 0, padding = 0, in_win = 0;
+    long windowed = 0, padding = 0, in_win = 0, empty_segs = 0;
     for (const Tile& t : p.tiles) {
       if (t.chunk0 < 0 || t.nchunk < 1 || (size_t)t.chunk0 + t.nchunk > p.chunks.size()) FAIL("tile chunks");
       const bool win = t.wlen > 0;
@@ -63,7 +63,7 @@ int main(int argc, char** argv) {
       windowed += win;
       for (int ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci) {
         const Chunk& ch = p.chunks[ci];
-        if (ch.steps < 1 || ch.steps > kSegMax) FAIL("chunk steps %d", ch.steps);
+        if (ch.steps < 0 || ch.steps > kSegMax) FAIL("chunk steps %d", ch.steps);
         if (ch.base < 0 || (size_t)ch.base + 64 * (size_t)ch.steps > p.src.size()) FAIL("chunk values");
         const size_t csz = win ? p.col16.size() : p.col32.size();
         if (ch.cbase < 0 || (size_t)ch.cbase + 64 * (size_t)ch.steps > csz) FAIL("chunk columns");
@@ -91,7 +91,7 @@ int main(int argc, char** argv) {
           }
           if (slot >= 0) {
             if (slot >= p.nslot || slotset[slot]++) FAIL("slot %d", slot);
-            if (!any) FAIL("segment without entries");
+            if (!any) ++empty_segs;  // grid blocks keep one (possibly empty) segment per window
             part1[slot] = s1;
             part2[slot] = s2;
           }
@@ -121,8 +121,20 @@ int main(int argc, char** argv) {
       if (cnt && hi - lo + 1 != cnt) FAIL("tile slots not contiguous");
     }
     std::vector<int> combined(nrows, 0);
+    long grid_rows = 0;
     for (const CombItem& c : p.comb) {
-      if (c.lg < 0 || c.lg > 6 || c.r0 < 0 || c.r1 > nrows || c.r0 >= c.r1) FAIL("combine item");
+      if (c.lg > 6 || c.r0 < 0 || c.r1 > nrows || c.r0 >= c.r1) FAIL("combine item");
+      if (c.lg < 0) {
+        // grid item: K slots per row at tbase[t0 + j] + row, the row's slots in column order
+        const int K = -c.lg;
+        if (c.r1 - c.r0 > 256 || c.t0 < 0 || (size_t)c.t0 + K > p.tiles.size()) FAIL("grid item");
+        for (int r = c.r0; r < c.r1; ++r) {
+          if (p.rowslot[r + 1] - p.rowslot[r] != K) FAIL("grid row %d has %d slots", r, p.rowslot[r + 1] - p.rowslot[r]);
+          for (int j = 0; j < K; ++j)
+            if ((long)p.tbase[c.t0 + j] + r != p.slotidx[p.rowslot[r] + j]) FAIL("grid slot of row %d", r);
+        }
+        grid_rows += c.r1 - c.r0;
+      }
       for (int r = c.r0; r < c.r1; ++r) combined[r]++;
     }
     for (int r = 0; r < nrows; ++r)
@@ -138,9 +150,9 @@ int main(int argc, char** argv) {
       scale = std::max(scale, std::fabs(ref1[r]) + std::fabs(ref2[r]));
     }
     if (err > 1e-12 * std::max(scale, 1.0)) FAIL("row sums off by %g", err);
-    std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d\n", wcap,
+    std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d grid_rows %ld empty %ld\n", wcap,
                 p.tiles.size(), windowed, p.chunks.size(), 100.0 * padding / std::max<size_t>(p.src.size(), 1),
-                100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen);
+                100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen, grid_rows, empty_segs);
   }
   return 0;
 }

@@ -52,13 +52,32 @@ int main(int argc, char** argv) {
   const int rc = prepare(&P, q.data(), &A, m ? l.data() : nullptr, m ? u.data() : nullptr, &s, &H, &msg);
   std::printf("rc %d\n%s\n", rc, msg.c_str());
   if (rc) return 0;
+  // the values as the device places them (qpg_solver::place_raw): Ā's through the CSR → CSC
+  // index map, B's rows from the full P's rows and A's columns
+  std::vector<double> a_val(H.a_src.size()), b_val(H.b_col.size());
+  for (size_t k = 0; k < a_val.size(); ++k) {
+    if (H.a_src[k] < 0 || H.a_src[k] >= A.nnz) {
+      std::printf("a_src out of range\n");
+      return 1;
+    }
+    a_val[k] = H.a_csc_val[H.a_src[k]];
+  }
+  for (int i = 0; i < n; ++i) {
+    const int32_t o = H.b_ptr[i], sp = H.b_split[i];
+    if (sp - o != H.p_ptr[i + 1] - H.p_ptr[i] || H.b_ptr[i + 1] - sp != H.a_colptr[i + 1] - H.a_colptr[i]) {
+      std::printf("B row %d: part lengths\n", i);
+      return 1;
+    }
+    for (int32_t k = 0; k < sp - o; ++k) b_val[o + k] = H.p_val[H.p_ptr[i] + k];
+    for (int32_t k = 0; k < H.b_ptr[i + 1] - sp; ++k) b_val[sp + k] = H.a_csc_val[H.a_colptr[i] + k];
+  }
   write_all(d + "/out_a_ptr.bin", H.a_ptr);
   write_all(d + "/out_a_col.bin", H.a_col);
-  write_all(d + "/out_a_val.bin", H.a_val);
+  write_all(d + "/out_a_val.bin", a_val);
   write_all(d + "/out_b_ptr.bin", H.b_ptr);
   write_all(d + "/out_b_split.bin", H.b_split);
   write_all(d + "/out_b_col.bin", H.b_col);
-  write_all(d + "/out_b_val.bin", H.b_val);
+  write_all(d + "/out_b_val.bin", b_val);
   write_all(d + "/out_lb.bin", H.lb);
   write_all(d + "/out_ub.bin", H.ub);
   write_all(d + "/out_eqrow.bin", H.eqrow);

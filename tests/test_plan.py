@@ -140,3 +140,25 @@ def test_sparse_wide_rows_take_the_l2_range_layout(exe, tmp_path):
     M = sp.random(3000, 400000, density=100 / 400000, random_state=rng, format="csr")
     st = stats(run(exe, tmp_path, M, nsplit=50000))
     assert st["windowed"] == 0 and st["slots"] >= 3 * 3000
+
+
+def test_random_rows_take_the_grid_layout(exe, tmp_path):
+    # 20 entries per row spread uniformly over 4000 columns: ≈ 5 per 1024-column window, too few
+    # for the multi-range layout but enough for the grid (one segment per row and window)
+    rng = np.random.default_rng(5)
+    M = sp.random(50000, 4000, density=20 / 4000, random_state=rng, format="csr")
+    st = stats(run(exe, tmp_path, M, nsplit=1500, wcap=1024))
+    # runs of rows of similar length decide the layout; the few rows far from 20 entries form
+    # short runs of their own, which may take another layout
+    assert st["grid_rows"] >= 0.9 * 50000 and st["in-window"] > 95
+    # a few entries outside every qualifying window: those rows' blocks fall back, the rest stay
+    M = M.tolil()
+    M[7, 3999] = 1.0
+    st = stats(run(exe, tmp_path, M.tocsr(), nsplit=1500, wcap=1024))
+    assert st["grid_rows"] > 0
+
+
+def test_grid_layout_under_sanitizers(exe_sanitized, tmp_path):
+    rng = np.random.default_rng(6)
+    M = sp.random(20000, 3000, density=8 / 3000, random_state=rng, format="csr")
+    run(exe_sanitized, tmp_path, M, nsplit=1000, wcap=1024)
