@@ -48,11 +48,11 @@ struct DevState {
   int32_t abort_reason;  // 1 PCG not finished within the launched iterations, 2 breakdown, 3 capped
   int32_t pcg_sum;       // PCG iterations of the completed speculative ADMM iterations
   int32_t pcg_max;       // and their largest count
-  double norms[24];   // residual-check outputs (OpRPrim / OpRDual: 0..13, OpInfeasA/B: 16..22)
+  double norms[24];   // residual-check outputs (OpUpdate<CHECK> or OpRPrim / OpRDual: 0..13, OpInfeasA/B: 16..22)
 };
 
 struct RedBuf {
-  double* partials;   // [workgroups][kMaxSlots], read by the following k_finalize or vector kernel
+  double* partials;   // [slot][workgroups] (kMaxSlots × grid), read by the next k_finalize or vector kernel
   double* vpartials;  // the same for k_pcg_update, which reads `partials` of the B pass meanwhile
 };
 
@@ -103,14 +103,56 @@ __device__ __forceinline__ void block_reduce(double (&v)[NS], double* lds) {
 // Publish this workgroup's partials (thread 0 after block_reduce). They are combined by
 // k_finalize, launched next on the same stream: no cross-workgroup synchronisation inside a
 // kernel, and the combination order is fixed (workgroup order), so results are reproducible.
+// Slot-major layout, partials[s · grid + workgroup]: the readers take consecutive workgroups
+// in consecutive lanes, so each wavefront load touches a few cache lines instead of 64.
 template <int NS, unsigned MAXMASK>
 __device__ __forceinline__ void publish(double (&v)[NS], double* partials) {
   __shared__ double lds[kMaxSlots * 4];
   block_reduce<NS, MAXMASK>(v, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) partials[(size_t)blockIdx.x * kMaxSlots + s] = v[s];
+    for (int s = 0; s < NS; ++s) partials[(size_t)s * gridDim.x + blockIdx.x] = v[s];
   }
+}
+
+// Thread t of a BLOCK-thread workgroup folds partials t, t + BLOCK, t + 2·BLOCK, … into acc, in
+// that order. The loads of U consecutive steps are issued before any of them is folded (clamped
+// to a valid index instead of branched around, so nothing serialises them): the partials were
+// just written by other XCDs and each round trip costs a full memory latency.
+template <int NS, unsigned MAXMASK, int BLOCK, int U>
+__device__ __forceinline__ void gather_rounds(const double* __restrict__ partials, int count,
+                                              double (&acc)[NS]) {
+  for (int b0 = threadIdx.x; b0 < count; b0 += U * BLOCK) {
+    double v[U][NS];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = min(b0 + u * BLOCK, count - 1);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) v[u][s] = partials[(size_t)s * count + b];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (b0 + u * BLOCK < count) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = comb<MAXMASK>(s, acc[s], v[u][s]);
+      }
+  }
+}
+
+// U = the steps per thread (1, 2, 4), else the largest that keeps v within 48 doubles.
+template <int NS, unsigned MAXMASK, int BLOCK>
+__device__ __forceinline__ void gather_partials(const double* __restrict__ partials, int count,
+                                                double (&acc)[NS]) {
+  constexpr int kMaxU = 48 / NS < 8 ? (48 / NS > 4 ? 48 / NS : 4) : 8;
+  if (count <= 0) return;
+  if (count <= BLOCK)
+    gather_rounds<NS, MAXMASK, BLOCK, 1>(partials, count, acc);
+  else if (count <= 2 * BLOCK)
+    gather_rounds<NS, MAXMASK, BLOCK, 2>(partials, count, acc);
+  else if (count <= 4 * BLOCK)
+    gather_rounds<NS, MAXMASK, BLOCK, 4>(partials, count, acc);
+  else
+    gather_rounds<NS, MAXMASK, BLOCK, kMaxU>(partials, count, acc);
 }
 
 // One 1024-thread workgroup: combine `count` partials in a fixed order (thread t takes
@@ -131,11 +173,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(const double* __restrict
   double acc[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) acc[s] = 0.0;
-#pragma unroll 4
-  for (int b = threadIdx.x; b < count; b += kFinBlock) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = comb<MAXMASK>(s, acc[s], partials[(size_t)b * kMaxSlots + s]);
-  }
+  gather_partials<NS, MAXMASK, kFinBlock>(partials, count, acc);
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
     double x = acc[s];
@@ -577,7 +615,7 @@ struct OpUpdate {
   T* z;
   T* y;
   T* zt;
-  T* ax;
+  double* ax;  // null, or Āx̄ tracked by its recurrence (FP64 in both precisions)
   T* g;  // plane 0 of the right-hand-side vectors (n + m), read by the next OpRhsRec / OpRhsR0
   const T* lb;
   const T* ub;
@@ -603,10 +641,11 @@ struct OpUpdate {
     zt[i] = s1;
     g[n + i] = ri * (s1 - zn) + yn;
     if (ax) {
-      const T a = alpha * s1 + (T(1) - alpha) * ax[i];
-      ax[i] = a;
+      const double al = (double)alpha;
+      const double ad = al * (double)s1 + (1.0 - al) * ax[i];
+      ax[i] = ad;
       if constexpr (CHECK) {
-        const double e = einv[i], ad = (double)a, zd = (double)zn;
+        const double e = einv[i], zd = (double)zn;
         const double rp = ad - zd;
         red[0] = nmax(red[0], fabs(rp));
         red[1] = nmax(red[1], fabs(rp * e));
@@ -767,10 +806,7 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ parti
   double v[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) v[s] = 0.0;
-  for (int b = threadIdx.x; b < count; b += kBlock) {
-#pragma unroll
-    for (int s = 0; s < NS; ++s) v[s] = comb<MAXMASK>(s, v[s], partials[(size_t)b * kMaxSlots + s]);
-  }
+  gather_partials<NS, MAXMASK, kBlock>(partials, count, v);
   block_reduce<NS, MAXMASK>(v, lds);
   if (threadIdx.x == 0) {
 #pragma unroll

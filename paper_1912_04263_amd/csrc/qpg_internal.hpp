@@ -115,6 +115,7 @@ constexpr int kMinSeg = 16;    // entries per row and range that make a multi-ra
 constexpr int kGridMinSeg = 2; // entries per row and window that make a grid layout (see tiles.cpp)
 constexpr int kGridMaxRows = 16384;  // rows of a grid block at most
 constexpr int kGridRound = 512;      // grid tiles that run at once (two 1024-thread workgroups per CU)
+constexpr int kRunMinRows = 64;      // single-segment rows with consecutive slots that make a K = 1 combine item
 
 struct Chunk {
   int32_t base;   // first value (SELL order)
@@ -130,7 +131,8 @@ struct Tile {
 
 // k_combine work: rows [r0, r1), 2^lg lanes per row (rows with many slots share them out); or,
 // with lg = −K < 0, rows of a grid block: one lane per row, whose K slots are tbase[t0 + j] + row
-// (j = 0..K−1, column order), t0 = the block's first tile.
+// (j = 0..K−1, column order), t0 = the block's first tile; or (K = 1) a run of single-segment
+// rows whose slots are tbase[t0] + row, t0 past the tiles' entries.
 struct CombItem {
   int32_t r0, r1, lg, t0;
 };
@@ -142,7 +144,9 @@ struct TilePlan {
   std::vector<int32_t> segslot;  // per segment (64 per chunk, −1 for an empty lane): output slot
   std::vector<int32_t> rowslot;  // nrows + 1: row r has the segments [rowslot[r], rowslot[r + 1])
   std::vector<int32_t> slotidx;  // per segment in row order (column order within a row): its slot
-  std::vector<int32_t> tbase;    // per tile of a grid block: its first slot minus the block's first row
+  // per tile of a grid block: its first slot minus the block's first row; then one entry per run
+  // of single-segment rows with consecutive slots (slot − row)
+  std::vector<int32_t> tbase;
   hvec<int32_t> src;             // per SELL value position: CSR index, −1 for padding
   hvec<uint16_t> col16;          // column offsets of windowed tiles (SELL order)
   hvec<int32_t> col32;           // columns of the other tiles (SELL order)

@@ -263,8 +263,10 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // tracked (FP64) the primal residual of a check iteration comes out of the same pass. Between
   // checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a vector pass; a
   // check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
+  // Āx̄ is tracked in FP64 in both precisions (p64.ax): a check then takes the primal residual
+  // from the update pass instead of an Ā pass of its own.
   auto launch_update = [&](bool check, T* dxy) {
-    T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
+    double* ax = p64.ax;
     OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.g, V.lb, V.ub, escale,
                            (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
     if (check && ax) {
@@ -376,26 +378,42 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       if (after_pcg(k, it)) return finish(k);
     }
     T* dxy = (check && infeas && armed) ? V.dxy : nullptr;  // δx̄, δȳ of this step (Section 3.1)
-    T* ax = std::is_same<T, double>::value ? V.ax : nullptr;
     launch_update(check, dxy);
     if (!check) {
       ++k;
       continue;
     }
-    // (a9) residuals and termination every check_every iterations
+    // (a9) residuals and termination every check_every iterations. The update pass gave the
+    // primal residual from the tracked Āx̄. In FP32 that recurrence also carries the rounding
+    // drift of z̃ through the PCG iterations, so a solve that took more than kTrackedPcg PCG
+    // iterations recomputes Āx̄ by an Ā pass, and a check that would stop the solve confirms the
+    // primal residual by that pass first: drift can neither fake nor delay convergence there.
     {
-      if (!ax) {
+      constexpr int kTrackedPcg = 4;
+      const bool fp32 = std::is_same<T, float>::value;
+      bool exact = !fp32;
+      auto exact_prim = [&](bool mirror) {
         OpRPrim<T> rp{V.x, V.z, escale, st};
-        finalize(rp, spmv_A<T>(rp));
-      }
+        finalize(rp, spmv_A<T>(rp), nullptr, mirror);
+        exact = true;
+      };
+      if (!exact && it > kTrackedPcg) exact_prim(false);
       OpRDual<T> rd{V.x, V.y, V.qb, dscale, n, st};
       finalize(rd, spmv_B<T>(rd), nullptr, true);
       sync_state();
       const double* nm = st_host->norms;
-      const double prim = nm[1], nAx = nm[3], nz = nm[5];
+      double prim = nm[1], nAx = nm[3], nz = nm[5];
       const double dual = nm[7] / c, nPx = nm[9] / c, nAty = nm[11] / c;
-      const double eps_p = s.eps_abs + s.eps_rel * std::max(nAx, nz);
+      double eps_p = s.eps_abs + s.eps_rel * std::max(nAx, nz);
       const double eps_d = s.eps_abs + s.eps_rel * std::max(std::max(nPx, nAty), q_norm);
+      if (!exact && prim <= eps_p && dual <= eps_d) {
+        exact_prim(true);
+        sync_state();
+        prim = nm[1];
+        nAx = nm[3];
+        nz = nm[5];
+        eps_p = s.eps_abs + s.eps_rel * std::max(nAx, nz);
+      }
       info.prim_res = prim;
       info.dual_res = dual;
       info.obj_val = (0.5 * nm[12] + nm[13]) / c;
@@ -517,6 +535,7 @@ int qpg_solver::solve() {
     fill(V.z, m, 0.f);
     fill(V.y, m, 0.f);
     fill(V.zt, m, 0.f);
+    fill(p64.ax, m, 0.0);
     pairs<float>(rho);
     int fb = 0;
     k_end = admm<float>(1, rho, eps_pcg, status, fb);

@@ -65,7 +65,7 @@ struct Prec {
   T* bk = nullptr;  // right-hand side b of the ADMM iteration's PCG solve (n)
   T* w = nullptr;   // ρ̄Āp (m) = pw + n
   T* zt = nullptr;  // z̃ = Āx̃ of the last update pass (m)
-  T* ax = nullptr;  // Āx tracked by its recurrence (m), FP64 only
+  T* ax = nullptr;  // Āx tracked by its recurrence (m), in the FP64 set only (both precisions use it)
   // vectors gathered by the right-hand-side pass, two planes of n + m: x̃ then ρ̄(z̃ − z) + y;
   // 0 then ρ̄z − y (plane 1 only for OpRhsR0, written by k_pairs)
   T* g = nullptr;

@@ -580,6 +580,15 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     while (lg < 6 && (4 << lg) < ns) ++lg;
     return lg;
   };
+  // Runs of rows with one segment each whose slots are consecutive (slot = D + row, as within
+  // one tile of single-segment rows) are combined like a grid block with K = 1: the item reads
+  // D from tbase (entries appended after the tiles') and each lane its slot D + row, without
+  // the rowslot and slotidx lookups. run[r] = length of such a run starting at row r.
+  std::vector<int32_t> run((size_t)nrows + 1, 0);
+  auto delta = [&](int32_t q) { return (int64_t)plan.slotidx[plan.rowslot[q]] - q; };
+  for (int32_t q = nrows - 1; q >= 0; --q)
+    if (plan.rowslot[q + 1] - plan.rowslot[q] == 1)
+      run[q] = (run[q + 1] > 0 && delta(q + 1) == delta(q)) ? run[q + 1] + 1 : 1;
   int32_t r = 0;
   size_t gi = 0;  // next grid block (in row order)
   while (r < nrows) {
@@ -590,8 +599,16 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       continue;
     }
     const int32_t stop = gi < grids.size() ? grids[gi].b0 : nrows;
+    if (run[r] >= kRunMinRows) {
+      const int32_t e = std::min(stop, r + run[r]);
+      const int32_t t0 = (int32_t)plan.tbase.size();
+      plan.tbase.push_back((int32_t)delta(r));
+      for (int32_t a = r; a < e; a += kBlock) plan.comb.push_back({a, std::min(e, a + kBlock), -1, t0});
+      r = e;
+      continue;
+    }
     int32_t lg = lg_of(r), r1 = r + 1;
-    while (r1 < stop) {
+    while (r1 < stop && run[r1] < kRunMinRows) {
       const int32_t l2 = std::max(lg, lg_of(r1));
       if (r1 + 1 - r > (kBlock >> l2)) break;
       lg = l2;

@@ -121,13 +121,14 @@ int main(int argc, char** argv) {
       if (cnt && hi - lo + 1 != cnt) FAIL("tile slots not contiguous");
     }
     std::vector<int> combined(nrows, 0);
-    long grid_rows = 0;
+    long grid_rows = 0, run_rows = 0;
     for (const CombItem& c : p.comb) {
       if (c.lg > 6 || c.r0 < 0 || c.r1 > nrows || c.r0 >= c.r1) FAIL("combine item");
       if (c.lg < 0) {
         // grid item: K slots per row at tbase[t0 + j] + row, the row's slots in column order
         const int K = -c.lg;
-        if (c.r1 - c.r0 > 256 || c.t0 < 0 || (size_t)c.t0 + K > p.tiles.size()) FAIL("grid item");
+        if (c.r1 - c.r0 > 256 || c.t0 < 0 || (size_t)c.t0 + K > p.tbase.size()) FAIL("grid item");
+        if ((size_t)c.t0 >= p.tiles.size()) run_rows += c.r1 - c.r0;  // a run of single-segment rows
         for (int r = c.r0; r < c.r1; ++r) {
           if (p.rowslot[r + 1] - p.rowslot[r] != K) FAIL("grid row %d has %d slots", r, p.rowslot[r + 1] - p.rowslot[r]);
           for (int j = 0; j < K; ++j)
@@ -150,9 +151,9 @@ int main(int argc, char** argv) {
       scale = std::max(scale, std::fabs(ref1[r]) + std::fabs(ref2[r]));
     }
     if (err > 1e-12 * std::max(scale, 1.0)) FAIL("row sums off by %g", err);
-    std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d grid_rows %ld empty %ld\n", wcap,
+    std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d grid_rows %ld empty %ld run_rows %ld\n", wcap,
                 p.tiles.size(), windowed, p.chunks.size(), 100.0 * padding / std::max<size_t>(p.src.size(), 1),
-                100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen, grid_rows, empty_segs);
+                100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen, grid_rows, empty_segs, run_rows);
   }
   return 0;
 }
