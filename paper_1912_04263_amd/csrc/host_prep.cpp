@@ -102,14 +102,18 @@ int check_csc(const qpg_csc* M, int32_t nrows, int32_t ncols, bool upper, const 
 
 // Builds a CSR matrix (nrows rows) from entries produced column by column: emit(j, put) calls
 // put(row, column, payload) for the entries of column j in order (the payload is the entry's value,
-// or its index in the source arrays). Rows come out in the order a
-// serial pass over the columns would produce. The columns are cut into parts of about equal work
-// (work[j] = number of entries column j emits, as a prefix array); each part counts its entries
-// per row, the counts give each part its own write position in every row, and a second pass
-// writes them. The result does not depend on the number of parts.
+// or its index in the source arrays). Rows come out in the order a serial pass over the columns
+// would produce. The columns are cut into parts of about equal work (work[j] = number of entries
+// column j emits, as a prefix array). A direct scatter into the rows would write every entry to
+// a random place in the output; instead the entries are first distributed into buckets of 4096
+// consecutive rows (sequential appends: one write stream per bucket and part), bucket by bucket
+// and, within a bucket, part by part, so that each bucket holds its entries in serial column
+// order; then every bucket places its entries into its own rows, a range that stays in cache.
+// The result does not depend on the number of parts.
 template <class Emit, typename V>
 void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& work, Emit emit,
                      std::vector<int32_t>& ptr, hvec<int32_t>& col, hvec<V>& val) {
+  constexpr int kBucketShift = 12;
   const int64_t total = work[ncols];
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
   const int T = total < (1 << 18) ? 1 : std::min(16, hw);
@@ -118,43 +122,58 @@ void columns_to_rows(int32_t ncols, int32_t nrows, const std::vector<int64_t>& w
     cut[t] = (int32_t)(std::lower_bound(work.begin(), work.end(), total * t / T) - work.begin());
   cut[0] = 0;
   cut[T] = ncols;
-  std::vector<std::vector<int32_t>> pos(T);
+  const int64_t nb = ((int64_t)nrows >> kBucketShift) + 1;
+  // entries per (part, bucket), then each (part, bucket)'s first position: bucket-major, parts in
+  // order within a bucket
+  std::vector<std::vector<int64_t>> pos(T);
   parallel_chunks(T, 1, [&](int64_t t, int64_t, int64_t) {
     auto& c = pos[t];
-    c.assign(nrows, 0);
-    for (int32_t j = cut[t]; j < cut[t + 1]; ++j) emit(j, [&](int32_t r, int32_t, V) { c[r]++; });
+    c.assign((size_t)nb, 0);
+    for (int32_t j = cut[t]; j < cut[t + 1]; ++j) emit(j, [&](int32_t r, int32_t, V) { c[r >> kBucketShift]++; });
   });
-  ptr.assign((size_t)nrows + 1, 0);
-  parallel_chunks(nrows, 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi; ++i) {
-      int32_t s = 0;
-      for (int t = 0; t < T; ++t) s += pos[t][i];
-      ptr[i + 1] = s;
+  std::vector<int64_t> bstart((size_t)nb + 1, 0);
+  int64_t o = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    bstart[b] = o;
+    for (int t = 0; t < T; ++t) {
+      const int64_t c = pos[t][b];
+      pos[t][b] = o;
+      o += c;
     }
-  });
-  for (int32_t i = 0; i < nrows; ++i) ptr[i + 1] += ptr[i];
-  parallel_chunks(nrows, 1 << 16, [&](int64_t, int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi; ++i) {
-      int32_t o = ptr[i];
-      for (int t = 0; t < T; ++t) {
-        const int32_t c = pos[t][i];
-        pos[t][i] = o;
-        o += c;
-      }
-    }
-  });
-  col.resize(ptr[nrows]);
-  val.resize(ptr[nrows]);
+  }
+  bstart[nb] = o;
+  hvec<int32_t> trow((size_t)o), tcol((size_t)o);
+  hvec<V> tval((size_t)o);
   parallel_chunks(T, 1, [&](int64_t t, int64_t, int64_t) {
-    auto& o = pos[t];
+    auto& q = pos[t];
     for (int32_t j = cut[t]; j < cut[t + 1]; ++j)
       emit(j, [&](int32_t r, int32_t c, V v) {
-        col[o[r]] = c;
-        val[o[r]++] = v;
+        const int64_t d = q[r >> kBucketShift]++;
+        trow[d] = r;
+        tcol[d] = c;
+        tval[d] = v;
       });
   });
+  // each bucket: its rows' lengths (hence ptr: a bucket's rows start where its entries start),
+  // then its entries into their rows in bucket order
+  ptr.assign((size_t)nrows + 1, 0);
+  col.resize((size_t)o);
+  val.resize((size_t)o);
+  parallel_chunks(nb, 1, [&](int64_t b, int64_t, int64_t) {
+    const int32_t r0 = (int32_t)(b << kBucketShift);
+    const int32_t r1 = (int32_t)std::min<int64_t>(nrows, (b + 1) << kBucketShift);
+    if (r0 >= r1) return;
+    std::vector<int64_t> at((size_t)(r1 - r0) + 1, 0);
+    for (int64_t d = bstart[b]; d < bstart[b + 1]; ++d) at[(size_t)(trow[d] - r0) + 1]++;
+    for (int32_t i = 0; i < r1 - r0; ++i) at[i + 1] += at[i];
+    for (int32_t i = 0; i < r1 - r0; ++i) ptr[(size_t)r0 + i + 1] = (int32_t)(bstart[b] + at[i + 1]);
+    for (int64_t d = bstart[b]; d < bstart[b + 1]; ++d) {
+      const int64_t e = bstart[b] + at[(size_t)(trow[d] - r0)]++;
+      col[e] = tcol[d];
+      val[e] = tval[d];
+    }
+  });
 }
-
 
 }  // namespace
 
@@ -226,8 +245,22 @@ Plan make_plan(const std::vector<int32_t>& rowptr, int32_t nrows, int32_t cap) {
   return p;
 }
 
+void prepare_a(const qpg_csc* A, HostProblem* out) {
+  // A in CSR: the pattern, and each entry's index in the CSC arrays (visiting the CSC columns in
+  // order keeps each row's columns sorted); the values follow on the device
+  HostProblem& H = *out;
+  std::vector<int64_t> a_work((size_t)H.n + 1);
+  for (int32_t j = 0; j <= H.n; ++j) a_work[j] = A->colptr[j];
+  columns_to_rows(
+      H.n, H.m, a_work,
+      [&](int32_t j, auto&& put) {
+        for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k) put(A->rowidx[k], j, (int32_t)k);
+      },
+      H.a_ptr, H.a_col, H.a_src);
+}
+
 int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* l,
-            const double* u, const qpg_settings* s, HostProblem* out, std::string* msg) {
+            const double* u, const qpg_settings* s, HostProblem* out, std::string* msg, bool with_a) {
   int rc = validate_settings(s, msg);
   if (rc) return rc;
   if (!Pt || !A) {
@@ -265,7 +298,7 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
     }
   }
   // full P has at most 2·nnz(triu) entries; B holds full P and Aᵀ
-  std::vector<int64_t> p_work((size_t)n + 1, 0), a_work((size_t)n + 1);
+  std::vector<int64_t> p_work((size_t)n + 1, 0);
   parallel_chunks(n, 1 << 14, [&](int64_t, int64_t lo, int64_t hi) {
     for (int64_t j = lo; j < hi; ++j) {
       int64_t e = 0;
@@ -274,7 +307,6 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
     }
   });
   for (int32_t j = 0; j < n; ++j) p_work[j + 1] += p_work[j];
-  for (int32_t j = 0; j <= n; ++j) a_work[j] = A->colptr[j];
   if (p_work[n] + (int64_t)A->nnz > std::numeric_limits<int32_t>::max()) {
     *msg = "nnz(P) + nnz(A) overflows int32";
     return QPG_ERR_SIZE;
@@ -299,14 +331,6 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
         }
       },
       H.p_ptr, p_col, H.p_val);
-  // ---- A in CSR: the pattern, and each entry's index in the CSC arrays (visiting the CSC columns
-  // in order keeps each row's columns sorted); the values follow on the device
-  columns_to_rows(
-      n, m, a_work,
-      [&](int32_t j, auto&& put) {
-        for (int32_t k = A->colptr[j]; k < A->colptr[j + 1]; ++k) put(A->rowidx[k], j, (int32_t)k);
-      },
-      H.a_ptr, H.a_col, H.a_src);
   H.a_csc_val = A->val;
   H.a_colptr = A->colptr;
   // ---- B = [P | Aᵀ]: row i is row i of the full P, then column i of A (CSC of A = CSR of Aᵀ)
@@ -342,6 +366,7 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
   double qn = 0.0;
   for (int32_t i = 0; i < n; ++i) qn = std::max(qn, std::fabs(q[i]));
   H.q_norm_unscaled = qn;
+  if (with_a) prepare_a(A, out);
   return QPG_OK;
 }
 

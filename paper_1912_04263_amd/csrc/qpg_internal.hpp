@@ -199,8 +199,13 @@ struct HostProblem {
 };
 
 // Validate the inputs (returns QPG_OK or an error code with a message) and build HostProblem.
+// With with_a false, A's CSR pattern (a_ptr, a_col, a_src) is left to prepare_a, so that the
+// caller can start on B's work list first.
 int prepare(const qpg_csc* P_triu, const double* q, const qpg_csc* A, const double* l,
-            const double* u, const qpg_settings* s, HostProblem* out, std::string* msg);
+            const double* u, const qpg_settings* s, HostProblem* out, std::string* msg,
+            bool with_a = true);
+// A in CSR (after a successful prepare with with_a false).
+void prepare_a(const qpg_csc* A, HostProblem* out);
 
 int validate_settings(const qpg_settings* s, std::string* msg);
 

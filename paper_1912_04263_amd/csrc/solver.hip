@@ -908,7 +908,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
   std::string msg;
   int rc;
   try {
-    rc = prepare(P_triu, q, A, l, u, settings, &H, &msg);
+    rc = prepare(P_triu, q, A, l, u, settings, &H, &msg, false);
   } catch (const std::bad_alloc&) {
     rc = QPG_ERR_OOM;
     msg = "host allocation failed";
@@ -917,7 +917,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     g_setup_error = msg;
     return rc;
   }
-  mark("host checks, CSC->CSR, B = [P | A^T]", nullptr);
+  mark("host checks, full P, B = [P | A^T]", nullptr);
   qpg_solver* h = new (std::nothrow) qpg_solver();
   if (!h) {
     g_setup_error = "host allocation failed";
@@ -933,7 +933,8 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     HIPCHK(resolve_noalloc_scratch(h->device));
     // SpMV work lists: the window capacity is capped so that a window of doubles fits in one
     // workgroup's LDS. They depend on the sparsity pattern only, so two host threads (Ā, B)
-    // build them while the device equilibrates the values.
+    // build them while the device equilibrates the values; B's starts while A is converted to
+    // CSR.
     int lds_max = 0;
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
     h->win_cols = settings->spmv_window_cols > 0 ? settings->spmv_window_cols : kWinCols;
@@ -941,20 +942,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
       h->win_cols >>= 1;
     TilePlan ta, tb;
     std::exception_ptr plan_err_a, plan_err_b;
-    std::thread planner_a([&]() {
-      try {
-        ta = h->plan_tiles(H.a_ptr, H.a_col.data(), H.m, H.n);
-      } catch (...) {
-        plan_err_a = std::current_exception();
-      }
-    });
-    std::thread planner_b([&]() {
-      try {
-        tb = h->plan_tiles(H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
-      } catch (...) {
-        plan_err_b = std::current_exception();
-      }
-    });
+    std::thread planner_a, planner_b;
     struct Join {  // the planners read H: they are joined on every way out of this block
       std::thread& a;
       std::thread& b;
@@ -963,6 +951,22 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
         if (b.joinable()) b.join();
       }
     } join{planner_a, planner_b};
+    planner_b = std::thread([&]() {
+      try {
+        tb = h->plan_tiles(H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
+      } catch (...) {
+        plan_err_b = std::current_exception();
+      }
+    });
+    prepare_a(A, &H);
+    mark("A in CSR (host)", nullptr);
+    planner_a = std::thread([&]() {
+      try {
+        ta = h->plan_tiles(H.a_ptr, H.a_col.data(), H.m, H.n);
+      } catch (...) {
+        plan_err_a = std::current_exception();
+      }
+    });
     Plan pa = make_plan(H.a_ptr, H.m);
     Plan pb = make_plan(H.b_ptr, H.n);
     for (Plan* pl : {&pa, &pb})

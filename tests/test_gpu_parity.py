@@ -337,7 +337,7 @@ def test_verbose_reports_setup_phases_and_checks(capfd):
     with qpg.Solver.from_qp(p, verbose=1, max_iter=5) as s:
         s.solve()
     err = capfd.readouterr().err
-    for phase in ("host checks", "index uploads", "value uploads", "equilibration (device)", "work lists",
+    for phase in ("host checks", "A in CSR (host)", "index uploads", "value uploads", "equilibration (device)", "work lists",
                   "work-list uploads", "values into SELL order", "vectors, preconditioner"):
         assert f"qpg setup  {phase}" in err, phase
     assert "qpg     5  prim" in err
