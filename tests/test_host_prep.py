@@ -90,8 +90,10 @@ def random_problem(seed, n, m, dens):
     return sp.triu(P).tocsc(), P, q, A, l, u
 
 
+# the last two: more than 2^18 entries, so the conversion splits the columns into parts, and rows
+# spanning several 4096-row buckets (8192 rows: the last bucket is empty)
 @pytest.mark.parametrize("seed, n, m, dens, rv", [(0, 40, 60, 0.1, 0), (1, 300, 200, 0.05, 1),
-                                                  (2, 3000, 5000, 0.03, 0)])
+                                                  (2, 3000, 5000, 0.03, 0), (4, 2000, 8192, 0.02, 0)])
 def test_conversion_matches_scipy(exe, tmp_path, seed, n, m, dens, rv):
     Pt, P, q, A, l, u = random_problem(seed, n, m, dens)
     rc, msg, o = run(exe, str(tmp_path), Pt, q, A, l, u, rho_vector=rv)

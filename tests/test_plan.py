@@ -99,6 +99,18 @@ def test_edge_matrices_under_sanitizers(exe_sanitized, tmp_path):
     run(exe_sanitized, tmp_path, M, nsplit=30000, tile_nnz=1024, plain_nnz=1024, wcap=2048)
 
 
+def test_single_segment_rows_with_consecutive_slots_take_run_items(exe, tmp_path):
+    # SVM's B: its t rows (one entry of Aᵀ each) are single-segment rows, numbered in row order
+    # within their tiles, so the combine takes them as K = 1 runs; the random QP has none
+    p = pr.make("svm_small")
+    _, B = reduced_pair(p)
+    st = stats(run(exe, tmp_path, B, nsplit=p.n))
+    assert st["run_rows"] >= p.meta["n_points"]
+    p = pr.make("random_small")
+    _, B = reduced_pair(p)
+    assert stats(run(exe, tmp_path, B, nsplit=p.n))["run_rows"] == 0
+
+
 def test_wide_rows_take_the_multi_range_layout(exe, tmp_path):
     rng = np.random.default_rng(1)
     M = sp.random(200, 100000, density=0.02, random_state=rng, format="csr")
