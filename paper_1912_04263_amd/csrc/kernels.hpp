@@ -861,15 +861,21 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt
 }
 
 // An SpMV operation's row epilogue and side task without the SpMV: the row values s1 are given
-// (used by the ADMM update when z̃ = Āx̃ is already known).
+// (used by the ADMM update when z̃ = Āx̃ is already known). Reductions, if any, are published per
+// workgroup like k_combine's.
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__ s1, Op op,
+                                                 double* __restrict__ partials,
                                                  const int32_t* __restrict__ gate) {
   if (gate && *gate) return;
-  double red[1] = {0.0};
+  constexpr int NS = Op::NS > 0 ? Op::NS : 1;
+  double red[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) red[s] = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < rows; i += gridDim.x * kBlock)
     op.epilogue(i, s1[i], T(0), red);
   op.side();
+  if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }
 
 // PCG direction (Algorithm 3), iteration `it`: β = r⁺ᵀy⁺ / rᵀy from k_pcg_update's partials;

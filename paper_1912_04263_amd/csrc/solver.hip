@@ -259,25 +259,35 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     }
     return false;
   };
-  // (a7)–(a8) z̃ = Āx̃ fused with relaxation, projection and dual update; x update; with Āx
-  // tracked (FP64) the primal residual of a check iteration comes out of the same pass. Between
-  // checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a vector pass; a
-  // check recomputes z̃ = Āx̃ with the SpMV, which also resets any drift.
-  // Āx̄ is tracked in FP64 in both precisions (p64.ax): a check then takes the primal residual
-  // from the update pass instead of an Ā pass of its own.
-  auto launch_update = [&](bool check, T* dxy) {
+  // (a7)–(a8) z̃ = Āx̃ fused with relaxation, projection and dual update; x update. Between
+  // checks z̃ = Āx̃ comes from the PCG iterations (z̃ += αĀp) and the update is a vector pass.
+  // Āx̄ is tracked in FP64 in both precisions (p64.ax), so a check takes the primal residual
+  // from the update as well. A check recomputes z̃ = Āx̃ by an Ā pass (which resets the rounding
+  // drift of its recurrence) every kZtReset-th time in FP32 and never in FP64, where the drift
+  // stays at rounding level; with R = diag(ρ_i), z̃ is not carried through PCG and every update
+  // is an Ā pass.
+  constexpr int kZtReset = std::is_same<T, float>::value ? 4 : 0;
+  auto launch_update = [&](bool check, T* dxy, int kk) {
     double* ax = p64.ax;
     OpUpdate<T, false> upd{V.xt, V.x, V.z, V.y, V.zt, ax, V.g, V.lb, V.ub, escale,
                            (T)alpha, (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
-    if (check && ax) {
+    const int g = grid_for(std::max(n, m));
+    if (check) {
       OpUpdate<T, true> up{V.xt, V.x, V.z, V.y, V.zt, ax, V.g, V.lb, V.ub, escale, (T)alpha,
                            (T)rho, (T)(1.0 / rho), n, st, dxy, eqrow};
-      finalize(up, spmv_A<T>(up, agate), agate);
-    } else if (check || eqrow) {  // with R = diag(ρ_i), z̃ is not carried through PCG
+      const bool reset = eqrow || (kZtReset > 0 && (kk / s.check_every) % kZtReset == 0);
+      if (reset) {
+        finalize(up, spmv_A<T>(up, agate), agate);
+      } else {
+        hipLaunchKernelGGL((k_rows<T, OpUpdate<T, true>>), dim3(g), dim3(kBlock), 0, stream, m,
+                           (const T*)V.zt, up, rb.partials, agate);
+        finalize(up, g, agate);
+      }
+    } else if (eqrow) {
       spmv_A<T>(upd, agate);
     } else {
-      hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(grid_for(std::max(n, m))), dim3(kBlock), 0,
-                         stream, m, (const T*)V.zt, upd, agate);
+      hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(g), dim3(kBlock), 0, stream, m,
+                         (const T*)V.zt, upd, (double*)nullptr, agate);
     }
   };
   // after a host read that shows an abort: finish iteration j = abort_k (its PCG, then its
@@ -289,7 +299,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     const int it = reason == 1 ? pcg_loop<T>(rho, s.pcg_max_iter, true, st_host->iter) : st_host->iter;
     pending = false;
     if (after_pcg(j, it)) return -1;
-    launch_update(false, nullptr);
+    launch_update(false, nullptr, j);
     return j + 1;
   };
   // (a1)+(a2) right-hand side, ‖b‖∞ and the warm-started PCG residual: in one pass over B from
@@ -378,7 +388,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       if (after_pcg(k, it)) return finish(k);
     }
     T* dxy = (check && infeas && armed) ? V.dxy : nullptr;  // δx̄, δȳ of this step (Section 3.1)
-    launch_update(check, dxy);
+    launch_update(check, dxy, k);
     if (!check) {
       ++k;
       continue;
