@@ -326,6 +326,81 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(const Tile* __restrict__ ti
   op.side();
 }
 
+// Two gathered vectors at once (an operation with NV = 2 and gather2(c) returning both values):
+// one read of the matrix gives the segment sums of both products, written to slot planes 0–1
+// (first vector: columns < nsplit, ≥ nsplit) and 2–3 (second vector). The window holds pairs,
+// so it needs twice the LDS of k_spmv's.
+template <typename T>
+struct Pair {
+  T a, b;
+};
+
+template <typename T, class Op>
+__global__ __launch_bounds__(kSpmvBlock) void k_spmv2(const Tile* __restrict__ tiles,
+                                                  const Chunk* __restrict__ chunks,
+                                                  const int32_t* __restrict__ segslot,
+                                                  const uint16_t* __restrict__ col16,
+                                                  const int32_t* __restrict__ col32,
+                                                  const T* __restrict__ val, int nsplit, Op op,
+                                                  T* __restrict__ slots, int64_t pstride,
+                                                  const int32_t* __restrict__ gate) {
+  if (gate && *gate) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Pair<T>* win = reinterpret_cast<Pair<T>*>(smem);
+  const Tile t = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (t.wlen > 0) {
+#pragma unroll 8
+    for (int i = threadIdx.x; i < t.wlen; i += kSpmvBlock) win[i] = op.gather2(t.wlo + i);
+    __syncthreads();
+  }
+  for (int ci = t.chunk0 + wave; ci < t.chunk0 + t.nchunk; ci += kSpmvBlock / 64) {
+    const Chunk ch = chunks[ci];
+    const int slot = segslot[ch.seg0 + lane];
+    const T* vp = val + ch.base + lane;
+    T s1 = T(0), s2 = T(0), u1 = T(0), u2 = T(0);
+    if (t.wlen > 0) {
+      const uint16_t* cp = col16 + ch.cbase + lane;
+      const int lim = nsplit - t.wlo;
+#pragma unroll kSpmvUnroll
+      for (int s = 0; s < ch.steps; ++s) {
+        const int o = cp[64 * s];
+        const Pair<T> x = win[o];
+        const T v = vp[64 * s];
+        accumulate(v, x.a, o < lim, s1, s2);
+        accumulate(v, x.b, o < lim, u1, u2);
+      }
+    } else {
+      const int32_t* cp = col32 + ch.cbase + lane;
+#pragma unroll kSpmvUnroll
+      for (int s = 0; s < ch.steps; ++s) {
+        const int c = cp[64 * s];
+        const Pair<T> x = op.gather2(c);
+        const T v = vp[64 * s];
+        accumulate(v, x.a, c < nsplit, s1, s2);
+        accumulate(v, x.b, c < nsplit, u1, u2);
+      }
+    }
+    if (slot >= 0) {
+      slots[slot] = s1;
+      slots[pstride + slot] = s2;
+      slots[2 * pstride + slot] = u1;
+      slots[3 * pstride + slot] = u2;
+    }
+  }
+  op.side();
+}
+
+// Gathered vectors of an operation: 1, or NV when it declares it (2: k_spmv2, epilogue2).
+template <class Op, class = void>
+struct NumVec {
+  static constexpr int v = 1;
+};
+template <class Op>
+struct NumVec<Op, std::void_t<decltype(Op::NV)>> {
+  static constexpr int v = Op::NV;
+};
+
 // Row sums from the slots, then the epilogue. 2^lg lanes per row: lane l adds the row's slots
 // l, l + L, … (in column order, through slotidx) in order, then a fixed shuffle tree combines the
 // lanes (deterministic). A grid item (lg < 0) gives each row one lane, which adds the row's K
@@ -341,6 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
                                                     const int32_t* __restrict__ gate) {
   if (gate && *gate) return;
   constexpr int NS = Op::NS > 0 ? Op::NS : 1;
+  constexpr int NV = NumVec<Op>::v;  // 2: planes 2–3 hold the second vector's sums
   double red[NS];
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
@@ -348,15 +424,22 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
   if (c.lg < 0) {
     const int r = c.r0 + threadIdx.x;
     if (r < c.r1) {
-      T s1 = T(0), s2 = T(0);
+      T s1 = T(0), s2 = T(0), u1 = T(0), u2 = T(0);
       const int32_t* tb = tbase + c.t0;
 #pragma unroll 8
       for (int j = 0; j < -c.lg; ++j) {
         const int64_t q = (int64_t)tb[j] + r;
         s1 += slots[q];
         if (planes > 1) s2 += slots[pstride + q];
+        if constexpr (NV == 2) {
+          u1 += slots[2 * pstride + q];
+          u2 += slots[3 * pstride + q];
+        }
       }
-      op.epilogue(r, s1, s2, red);
+      if constexpr (NV == 2)
+        op.epilogue2(r, s1, s2, u1, u2, red);
+      else
+        op.epilogue(r, s1, s2, red);
     }
     if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
     return;
@@ -364,19 +447,32 @@ __global__ __launch_bounds__(kBlock) void k_combine(const CombItem* __restrict__
   const int lg = c.lg, L = 1 << lg, groups = kBlock >> lg;
   const int g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
   for (int r = c.r0 + g; r < c.r1; r += groups) {
-    T s1 = T(0), s2 = T(0);
+    T s1 = T(0), s2 = T(0), u1 = T(0), u2 = T(0);
     const int q1 = rowslot[r + 1];
 #pragma unroll 4
     for (int q = rowslot[r] + lane; q < q1; q += L) {
       const int sq = slotidx[q];
       s1 += slots[sq];
       if (planes > 1) s2 += slots[pstride + sq];
+      if constexpr (NV == 2) {
+        u1 += slots[2 * pstride + sq];
+        u2 += slots[3 * pstride + sq];
+      }
     }
     if (L > 1) {
       s1 = wave_sum(s1, L);
       if (planes > 1) s2 = wave_sum(s2, L);
+      if constexpr (NV == 2) {
+        u1 = wave_sum(u1, L);
+        u2 = wave_sum(u2, L);
+      }
     }
-    if (lane == 0) op.epilogue(r, s1, s2, red);
+    if (lane == 0) {
+      if constexpr (NV == 2)
+        op.epilogue2(r, s1, s2, u1, u2, red);
+      else
+        op.epilogue(r, s1, s2, red);
+    }
   }
   if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }
@@ -728,6 +824,46 @@ struct OpRDual {
   }
 };
 
+// The dual residual check and, from the same read of B, the product B·g that the next ADMM
+// iteration's right-hand side needs (g = plane 0 of the right-hand-side vectors, as written by
+// this iteration's update): bg = [P̄x̃; Āᵀ(ρ̄(z̃ − z) + y); Āᵀy] (n each), for k_rows with
+// OpRhsRec, or with OpRhsRescaled when ρ̄ has changed at this check.
+template <typename T>
+struct OpRDualRhs {
+  QPG_NO_SIDE
+  static constexpr int NV = 2;
+  static constexpr int NS = OpRDual<T>::NS;
+  static constexpr unsigned MAXMASK = OpRDual<T>::MAXMASK;
+  OpRDual<T> rd;
+  const T* g;
+  T* bg;
+  __device__ Pair<T> gather2(int c) const { return Pair<T>{rd.gather(c), g[c]}; }
+  __device__ void epilogue2(int i, T s1, T s2, T u1, T u2, double* red) const {
+    rd.epilogue(i, s1, s2, red);
+    bg[i] = u1;
+    bg[rd.n + i] = u2;
+    bg[2 * rd.n + i] = s2;
+  }
+  __device__ void operator()(const double* t) const { rd(t); }
+};
+
+// OpRhsRec from a B·g formed with ρ̄_g before a ρ̄ update: g's second part scales with ρ̄
+// (ρ_i = c_i·ρ̄ on every row), so Āᵀ(ρ̄(z̃ − z) + y) = Āᵀy + (ρ̄/ρ̄_g)·(Āᵀg_m − Āᵀy).
+template <typename T>
+struct OpRhsRescaled {
+  QPG_NO_SIDE
+  static constexpr int NS = OpRhsRec<T>::NS;
+  static constexpr unsigned MAXMASK = OpRhsRec<T>::MAXMASK;
+  OpRhsRec<T> rc;
+  const T* aty;  // Āᵀy (n)
+  T ratio;       // ρ̄ / ρ̄_g
+  __device__ void epilogue(int i, T s1, T s2, double* red) const {
+    const T a = aty[i];
+    rc.epilogue(i, s1, a + ratio * (s2 - a), red);
+  }
+  __device__ void operator()(const double* t) const { rc(t); }
+};
+
 // Infeasibility tests (Section 3.1) on the differences δx̄, δȳ of the last ADMM step, in two
 // passes. Bounds with |l_i|, |u_i| ≥ kInf/2 (unscaled) are infinite.
 // Pass 1 over the rows of Ā, gathering δx̄: with v = E⁻¹(Āδx̄) = Aδx,
@@ -860,11 +996,13 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(int n, T* __restrict__ xt
   publish<2, 2u>(red, partials);
 }
 
-// An SpMV operation's row epilogue and side task without the SpMV: the row values s1 are given
-// (used by the ADMM update when z̃ = Āx̃ is already known). Reductions, if any, are published per
-// workgroup like k_combine's.
+// An SpMV operation's row epilogue and side task without the SpMV: the row values s1 (and s2, or
+// zeros) are given (the ADMM update when z̃ = Āx̃ is already known; the right-hand side from B's
+// product computed by the dual-residual pass). Reductions, if any, are published per workgroup
+// like k_combine's.
 template <typename T, class Op>
-__global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__ s1, Op op,
+__global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__ s1,
+                                                 const T* __restrict__ s2, Op op,
                                                  double* __restrict__ partials,
                                                  const int32_t* __restrict__ gate) {
   if (gate && *gate) return;
@@ -873,7 +1011,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(int rows, const T* __restrict__
 #pragma unroll
   for (int s = 0; s < NS; ++s) red[s] = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < rows; i += gridDim.x * kBlock)
-    op.epilogue(i, s1[i], T(0), red);
+    op.epilogue(i, s1[i], s2 ? s2[i] : T(0), red);
   op.side();
   if constexpr (Op::NS > 0) publish<Op::NS, Op::MAXMASK>(red, partials);
 }

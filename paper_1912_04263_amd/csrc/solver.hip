@@ -147,6 +147,7 @@ void qpg_solver::alloc_prec32() {
   V.bk = alloc<float>(n);
   V.g = alloc<float>(2 * ((size_t)n + m));
   V.dxy = alloc<float>((size_t)n + m);
+  V.bg = alloc<float>(3 * (size_t)n);
   V.ready = true;
 }
 
@@ -280,14 +281,14 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
         finalize(up, spmv_A<T>(up, agate), agate);
       } else {
         hipLaunchKernelGGL((k_rows<T, OpUpdate<T, true>>), dim3(g), dim3(kBlock), 0, stream, m,
-                           (const T*)V.zt, up, rb.partials, agate);
+                           (const T*)V.zt, (const T*)nullptr, up, rb.partials, agate);
         finalize(up, g, agate);
       }
     } else if (eqrow) {
       spmv_A<T>(upd, agate);
     } else {
       hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(g), dim3(kBlock), 0, stream, m,
-                         (const T*)V.zt, upd, (double*)nullptr, agate);
+                         (const T*)V.zt, (const T*)nullptr, upd, (double*)nullptr, agate);
     }
   };
   // after a host read that shows an abort: finish iteration j = abort_k (its PCG, then its
@@ -310,11 +311,30 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // stays at rounding level, in FP32 the refresh bounds it.
   constexpr int kRhsRefresh = 50;
   double rho_b = 0.0;  // ρ̄ of the PCG solve whose x̃, r and bk are in place; 0: none
+  // A check's dual-residual pass also forms B·g for the next iteration (FP32, when the window
+  // of pairs fits in LDS and the check's PCG solve took at most kTrackedPcg steps): that
+  // iteration's recurrence then runs as a vector pass.
+  int bg_for = -1;     // the ADMM iteration whose B·g is in V.bg
+  double bg_rho = 0.0;  // ρ̄ of that g
   auto rhs = [&](const int32_t* gate, int kk) {
     if (rho_b > 0.0 && kk % kRhsRefresh != 0) {
       OpRhsRec<T> rc{V.x, V.xt, V.qb, V.g, V.dinv, V.r, V.p, V.bk, (T)sigma, (T)(rho / rho_b),
                      s.pcg_max_iter, s.pcg_rel_test, eps_pcg, st};
-      finalize(rc, spmv_B<T>(rc, gate), gate);
+      if (bg_for == kk) {
+        const int gn = grid_for(n);
+        if (rho == bg_rho) {
+          hipLaunchKernelGGL((k_rows<T, OpRhsRec<T>>), dim3(gn), dim3(kBlock), 0, stream, n,
+                             (const T*)V.bg, (const T*)V.bg + n, rc, rb.partials, gate);
+          finalize(rc, gn, gate);
+        } else {
+          OpRhsRescaled<T> rs{rc, (const T*)V.bg + 2 * (size_t)n, (T)(rho / bg_rho)};
+          hipLaunchKernelGGL((k_rows<T, OpRhsRescaled<T>>), dim3(gn), dim3(kBlock), 0, stream, n,
+                             (const T*)V.bg, (const T*)V.bg + n, rs, rb.partials, gate);
+          finalize(rs, gn, gate);
+        }
+      } else {
+        finalize(rc, spmv_B<T>(rc, gate), gate);
+      }
     } else {
       pairs<T>(rho);
       spmv_B<T>(OpRhsAt<T>{V.g + (size_t)n + m, V.bk}, gate);
@@ -409,7 +429,18 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       };
       if (!exact && it > kTrackedPcg) exact_prim(false);
       OpRDual<T> rd{V.x, V.y, V.qb, dscale, n, st};
-      finalize(rd, spmv_B<T>(rd), nullptr, true);
+      if constexpr (std::is_same<T, float>::value) {
+        // with many PCG steps per ADMM step the saved B pass is a small share of the work
+        if (pair_fits() && k < s.max_iter && it <= kTrackedPcg) {
+          finalize(rd, spmv_B_pair(OpRDualRhs<float>{rd, V.g, V.bg}), nullptr, true);
+          bg_for = k + 1;
+          bg_rho = rho;
+        } else {
+          finalize(rd, spmv_B<T>(rd), nullptr, true);
+        }
+      } else {
+        finalize(rd, spmv_B<T>(rd), nullptr, true);
+      }
       sync_state();
       const double* nm = st_host->norms;
       double prim = nm[1], nAx = nm[3], nz = nm[5];
@@ -503,7 +534,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
                 learned_dinv<T>(rho);
               else
                 jacobi<T>(rho);
-              pairs<T>(rho);
+              pairs<T>(rho);  // g with the new ρ̄ (the check's B·g is rescaled to it)
             }
           }
         }
@@ -947,6 +978,7 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     // CSR.
     int lds_max = 0;
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    h->lds_max = lds_max;
     h->win_cols = settings->spmv_window_cols > 0 ? settings->spmv_window_cols : kWinCols;
     while (h->win_cols > 1024 && (size_t)h->win_cols * sizeof(double) + 1024 > (size_t)lds_max)
       h->win_cols >>= 1;

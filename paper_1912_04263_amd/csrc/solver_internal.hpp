@@ -70,11 +70,12 @@ struct Prec {
   // 0 then ρ̄z − y (plane 1 only for OpRhsR0, written by k_pairs)
   T* g = nullptr;
   T* dxy = nullptr;         // δx̄ (n), then δȳ (m): differences of the last checked ADMM step
+  T* bg = nullptr;          // B·g from a check's dual-residual pass (P̄ part n, Āᵀ part n)
   bool ready = false;
 };
 
 // Device copy of a SpMV work list (TilePlan): the work list, the matrix in SELL order (values
-// in both precisions), and the slots (up to 3 planes).
+// in both precisions), and the slots (two planes of doubles, or four of floats).
 struct DevPlan {
   Tile* tiles = nullptr;
   int32_t ntiles = 0;
@@ -89,7 +90,7 @@ struct DevPlan {
   int32_t* col32 = nullptr;
   double* val64 = nullptr;
   float* val32 = nullptr;
-  void* slots = nullptr;  // double-sized: 3 planes of nslot values
+  void* slots = nullptr;  // 16 bytes per slot: planes of nslot values (k_spmv2 uses four of floats)
   int64_t nslot = 0;
   int32_t nrows = 0;
   int32_t max_wlen = 0;  // largest staged window, in columns
@@ -117,6 +118,7 @@ struct qpg_solver {
   int32_t na_items = 0, nb_items = 0;
   DevPlan plan_a, plan_b;  // SpMV work lists of Ā and B
   int32_t win_cols = 8192;  // LDS gather window capacity (columns)
+  int lds_max = 0;          // dynamic LDS per workgroup on the device (bytes)
   int32_t nnzA = 0, nnzB = 0;
   double *diagP = nullptr, *colsq = nullptr, *dscale = nullptr, *escale = nullptr;  // D⁻¹, E⁻¹
   uint8_t* eqrow = nullptr;     // equality-row flags when R = diag(ρ_i) (eq. rho_vec), else null
@@ -238,6 +240,35 @@ struct qpg_solver {
   template <typename T, class Op>
   int spmv_B(const Op& op, const int32_t* gate = nullptr) {
     return spmv<T>(plan_b, n, 2, op, gate);
+  }
+  // One read of B for two gathered vectors (k_spmv2, then k_combine over four slot planes), FP32
+  // only (the slots hold four planes of floats); false when its window of pairs would not fit in
+  // a workgroup's LDS.
+  bool pair_fits() const {
+    return (size_t)plan_b.max_wlen * 2 * sizeof(float) <= (size_t)lds_max;
+  }
+  template <class Op>
+  int spmv_B_pair(const Op& op, const int32_t* gate = nullptr) {
+    const DevPlan& pl = plan_b;
+    float* sl = static_cast<float*>(pl.slots);
+    const size_t shmem = (size_t)pl.max_wlen * sizeof(Pair<float>);
+    static std::atomic<size_t> lds_allowed[64];
+    const bool tab = device >= 0 && device < 64;
+    if (!tab || shmem > lds_allowed[device].load(std::memory_order_relaxed)) {
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv2<float, Op>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+      if (tab) {
+        size_t cur = lds_allowed[device].load(std::memory_order_relaxed);
+        while (cur < shmem && !lds_allowed[device].compare_exchange_weak(cur, shmem)) {
+        }
+      }
+    }
+    hipLaunchKernelGGL((k_spmv2<float, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles,
+                       pl.chunks, pl.segslot, pl.col16, pl.col32, (const float*)pl.val32, n, op, sl, pl.nslot,
+                       gate);
+    hipLaunchKernelGGL((k_combine<float, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
+                       pl.slotidx, pl.tbase, (const float*)sl, pl.nslot, 2, op, rb.partials, gate);
+    return pl.ncomb;
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
   template <class Op>
