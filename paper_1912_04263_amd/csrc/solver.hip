@@ -34,6 +34,7 @@ void qpg_solver::alloc_prec64(const HostProblem& H) {
   V.bk = alloc<double>(n);
   V.g = alloc<double>(2 * ((size_t)n + m));
   V.dxy = alloc<double>((size_t)n + m);
+  V.bg = alloc<double>(3 * (size_t)n);
   V.ready = true;
 }
 
@@ -311,8 +312,8 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // stays at rounding level, in FP32 the refresh bounds it.
   constexpr int kRhsRefresh = 50;
   double rho_b = 0.0;  // ρ̄ of the PCG solve whose x̃, r and bk are in place; 0: none
-  // A check's dual-residual pass also forms B·g for the next iteration (FP32, when the window
-  // of pairs fits in LDS and the check's PCG solve took at most kTrackedPcg steps): that
+  // A check's dual-residual pass also forms B·g for the next iteration (when the window of
+  // pairs fits in LDS and the check's PCG solve took at most kTrackedPcg steps): that
   // iteration's recurrence then runs as a vector pass.
   int bg_for = -1;     // the ADMM iteration whose B·g is in V.bg
   double bg_rho = 0.0;  // ρ̄ of that g
@@ -429,15 +430,11 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       };
       if (!exact && it > kTrackedPcg) exact_prim(false);
       OpRDual<T> rd{V.x, V.y, V.qb, dscale, n, st};
-      if constexpr (std::is_same<T, float>::value) {
-        // with many PCG steps per ADMM step the saved B pass is a small share of the work
-        if (pair_fits() && k < s.max_iter && it <= kTrackedPcg) {
-          finalize(rd, spmv_B_pair(OpRDualRhs<float>{rd, V.g, V.bg}), nullptr, true);
-          bg_for = k + 1;
-          bg_rho = rho;
-        } else {
-          finalize(rd, spmv_B<T>(rd), nullptr, true);
-        }
+      // with many PCG steps per ADMM step the saved B pass is a small share of the work
+      if (pair_fits<T>() && k < s.max_iter && it <= kTrackedPcg) {
+        finalize(rd, spmv_B_pair<T>(OpRDualRhs<T>{rd, V.g, V.bg}), nullptr, true);
+        bg_for = k + 1;
+        bg_rho = rho;
       } else {
         finalize(rd, spmv_B<T>(rd), nullptr, true);
       }
@@ -793,7 +790,8 @@ void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t
   pl.col32 = upload(t.col32);
   pl.nslot = t.nslot;
   pl.nrows = nrows;
-  pl.slots = alloc<double>(2 * (size_t)std::max<int64_t>(t.nslot, 1));
+  // B's slots hold four planes (the two-vector pass of the checks), Ā's two
+  pl.slots = alloc<double>((&pl == &plan_b ? 4 : 2) * (size_t)std::max<int64_t>(t.nslot, 1));
   pl.max_wlen = t.max_wlen;
   int64_t staged = 0, wtiles = 0;
   for (const Tile& x : t.tiles) {

@@ -75,7 +75,7 @@ struct Prec {
 };
 
 // Device copy of a SpMV work list (TilePlan): the work list, the matrix in SELL order (values
-// in both precisions), and the slots (two planes of doubles, or four of floats).
+// in both precisions), and the slots.
 struct DevPlan {
   Tile* tiles = nullptr;
   int32_t ntiles = 0;
@@ -90,7 +90,7 @@ struct DevPlan {
   int32_t* col32 = nullptr;
   double* val64 = nullptr;
   float* val32 = nullptr;
-  void* slots = nullptr;  // 16 bytes per slot: planes of nslot values (k_spmv2 uses four of floats)
+  void* slots = nullptr;  // planes of nslot values: two of doubles (Ā), four of doubles (B, k_spmv2)
   int64_t nslot = 0;
   int32_t nrows = 0;
   int32_t max_wlen = 0;  // largest staged window, in columns
@@ -241,21 +241,21 @@ struct qpg_solver {
   int spmv_B(const Op& op, const int32_t* gate = nullptr) {
     return spmv<T>(plan_b, n, 2, op, gate);
   }
-  // One read of B for two gathered vectors (k_spmv2, then k_combine over four slot planes), FP32
-  // only (the slots hold four planes of floats); false when its window of pairs would not fit in
-  // a workgroup's LDS.
+  // One read of B for two gathered vectors (k_spmv2, then k_combine over four slot planes of
+  // B's slots); false when its window of pairs would not fit in a workgroup's LDS.
+  template <typename T>
   bool pair_fits() const {
-    return (size_t)plan_b.max_wlen * 2 * sizeof(float) <= (size_t)lds_max;
+    return (size_t)plan_b.max_wlen * sizeof(Pair<T>) <= (size_t)lds_max;
   }
-  template <class Op>
+  template <typename T, class Op>
   int spmv_B_pair(const Op& op, const int32_t* gate = nullptr) {
     const DevPlan& pl = plan_b;
-    float* sl = static_cast<float*>(pl.slots);
-    const size_t shmem = (size_t)pl.max_wlen * sizeof(Pair<float>);
+    T* sl = static_cast<T*>(pl.slots);
+    const size_t shmem = (size_t)pl.max_wlen * sizeof(Pair<T>);
     static std::atomic<size_t> lds_allowed[64];
     const bool tab = device >= 0 && device < 64;
     if (!tab || shmem > lds_allowed[device].load(std::memory_order_relaxed)) {
-      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv2<float, Op>),
+      HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv2<T, Op>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
       if (tab) {
         size_t cur = lds_allowed[device].load(std::memory_order_relaxed);
@@ -263,11 +263,11 @@ struct qpg_solver {
         }
       }
     }
-    hipLaunchKernelGGL((k_spmv2<float, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles,
-                       pl.chunks, pl.segslot, pl.col16, pl.col32, (const float*)pl.val32, n, op, sl, pl.nslot,
-                       gate);
-    hipLaunchKernelGGL((k_combine<float, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
-                       pl.slotidx, pl.tbase, (const float*)sl, pl.nslot, 2, op, rb.partials, gate);
+    const T* val = std::is_same<T, double>::value ? (const T*)pl.val64 : (const T*)pl.val32;
+    hipLaunchKernelGGL((k_spmv2<T, Op>), dim3(pl.ntiles), dim3(kSpmvBlock), shmem, stream, pl.tiles, pl.chunks,
+                       pl.segslot, pl.col16, pl.col32, val, n, op, sl, pl.nslot, gate);
+    hipLaunchKernelGGL((k_combine<T, Op>), dim3(pl.ncomb), dim3(kBlock), 0, stream, pl.comb, pl.rowslot,
+                       pl.slotidx, pl.tbase, (const T*)sl, pl.nslot, 2, op, rb.partials, gate);
     return pl.ncomb;
   }
   // Combine the partials of the previous launch (count workgroups) and run op's finalisation.
