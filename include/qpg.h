@@ -166,7 +166,9 @@ int qpg_default_settings(qpg_settings* s);
  * convention of Section 6.2; A in CSC), expand P to full CSR and store A and Aᵀ in CSR
  * (Section 6.2), equilibrate (Algorithm 2), move everything to device memory and build the
  * SpMV work schedules. On success *out owns all device memory of the problem. Validation
- * failures return before any device call. */
+ * failures return before any device call. Large uploads pass through 128 MiB of pinned host
+ * memory per device (16 buffers of 8 MiB), allocated by the first qpg_setup on that device and
+ * kept until the process ends; setups on one device upload one at a time. */
 int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qpg_csc* A,
               const double* l, const double* u, const qpg_settings* settings);
 

@@ -166,15 +166,11 @@ struct qpg_solver {
     copy_h2d(d, h.data(), h.size() * sizeof(T));
     return d;
   }
-  // Host → device copy on the stream. Large copies go through two pinned staging buffers (the
-  // next piece is copied into one by several host threads while the DMA engine reads the other);
-  // the source may be released on return. Small ones are queued directly from the source, which
-  // must then stay valid until the stream has reached them.
+  // Host → device copy on the stream. Large copies go through the device's pinned staging
+  // buffers (host threads copy pieces into them while the DMA engine reads the others); the source
+  // may be released on return. Small ones are queued directly from the source, which must then
+  // stay valid until the stream has reached them.
   void copy_h2d(void* dst, const void* src, size_t bytes);
-  void release_staging();
-  void* staging[2] = {nullptr, nullptr};
-  hipEvent_t staging_done[2] = {nullptr, nullptr};
-  int staging_next = 0;
   template <typename T, typename S, class A>
   T* upload_as(const std::vector<S, A>& h) {
     qpg::hvec<T> t(h.size());
@@ -198,7 +194,6 @@ struct qpg_solver {
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
     if (out_host) (void)hipHostFree(out_host);
-    release_staging();
   }
 
   // ----------------------------------------------------------------- launches
