@@ -710,7 +710,7 @@ struct OpUpdate {
   T* x;
   T* z;
   T* y;
-  T* zt;
+  T* zt;       // z̃ = s1 is stored here (null: not stored)
   double* ax;  // null, or Āx̄ tracked by its recurrence (FP64 in both precisions)
   T* g;  // plane 0 of the right-hand-side vectors (n + m), read by the next OpRhsRec / OpRhsR0
   const T* lb;
@@ -734,7 +734,7 @@ struct OpUpdate {
     if (dxy) dxy[n + i] = yn - yi;
     y[i] = yn;
     z[i] = zn;
-    zt[i] = s1;
+    if (zt) zt[i] = s1;  // null where s1 was read from z̃ itself (k_rows)
     g[n + i] = ri * (s1 - zn) + yn;
     if (ax) {
       const double al = (double)alpha;

@@ -305,6 +305,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       if (reset) {
         finalize(up, spmv_A<T>(up, agate), agate);
       } else {
+        up.zt = nullptr;  // s1 is z̃ itself
         hipLaunchKernelGGL((k_rows<T, OpUpdate<T, true>>), dim3(g), dim3(kBlock), 0, stream, m,
                            (const T*)V.zt, (const T*)nullptr, up, rb.partials, agate);
         finalize(up, g, agate);
@@ -312,6 +313,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
     } else if (eqrow) {
       spmv_A<T>(upd, agate);
     } else {
+      upd.zt = nullptr;
       hipLaunchKernelGGL((k_rows<T, OpUpdate<T, false>>), dim3(g), dim3(kBlock), 0, stream, m,
                          (const T*)V.zt, (const T*)nullptr, upd, (double*)nullptr, agate);
     }
