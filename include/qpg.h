@@ -122,8 +122,9 @@ typedef struct {
                              without waiting for their PCG solves; the first PCG solve that is not
                              done after the predicted number of iterations (or breaks down, or hits
                              the cap) raises a device flag that skips the rest, and the host resumes
-                             there at the next read. 0: the host waits for every PCG solve (the
-                             synchronous loop of Section 6.3.3). Both give bitwise the same iterates. */
+                             there at the next read; only while the last PCG solve took at most 8
+                             iterations. 0: the host waits for every PCG solve (the synchronous
+                             loop of Section 6.3.3). Both give bitwise the same iterates. */
   int32_t spmv_window_cols; /* SpMV work lists: capacity in columns of a gather window staged in LDS
                              (a power of two from 1024 to 65536; halved until a window of doubles fits
                              the device's LDS, and on each matrix until it is at most half the entries

@@ -249,6 +249,7 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
   // iteration that set it, whose state is exactly what its PCG iterations left. So the host
   // waits once per check instead of once per ADMM iteration.
   const int32_t* agate = &st->abort;
+  constexpr int kSpecMaxPcg = 8;
   hipLaunchKernelGGL(k_spec_reset<DevState>, dim3(1), dim3(64), 0, stream, st);
   bool pending = false;  // speculative iterations launched since the last host read
   int last_cap_k = -2;
@@ -416,8 +417,10 @@ int qpg_solver::admm(int k_start, double& rho, double& eps_pcg, int& status,
       info.pcg_iter_total += it_l;
       trial = false;
       if (after_pcg(k, it)) return finish(k);
-    } else if (!check && s.speculate) {
-      // speculative: PCG with the predicted iteration count, no host read
+    } else if (!check && s.speculate && last_pcg <= kSpecMaxPcg) {
+      // speculative: PCG with the predicted iteration count, no host read (only where PCG takes
+      // few steps: there a host read is a large share of the iteration, and the predicted count
+      // is rarely short; with tens of steps an abort costs more than the reads it saves)
       rhs(agate, k);
       const int b = std::max(1, std::min(last_pcg, s.pcg_max_iter));
       for (int i = 0; i < b; ++i) pcg_iteration<T>(rho, true, false, i, i == b - 1 ? k : -1);

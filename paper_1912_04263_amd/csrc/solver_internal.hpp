@@ -315,12 +315,14 @@ struct qpg_solver {
 
   // Run PCG iterations after the initialisation kernel until st->done. The first batch is one
   // shorter than the previous PCG solve took, so that iterations launched after convergence
-  // (which exit at once) stay rare; then one iteration per host check. Returns the count.
+  // (which exit at once) stay rare; then batches of 2, 4 and 8 iterations per host check (fewer
+  // round trips when the count has grown, at most 7 gated iterations wasted). Returns the count.
   // `start` iterations of this solve have run already (a solve resumed after a speculation).
   template <typename T>
   int pcg_loop(double rho, int maxit, bool track_zt = false, int start = 0) {
     int issued = start;
     int batch = std::max(1, std::min(last_pcg - 1, maxit));
+    int more = 1;  // iterations per host read once the predicted count is spent: 2, 4, 8, 8, …
     for (;;) {
       int k = std::max(0, std::min(batch, maxit - issued));
       for (int i = 0; i < k; ++i)
@@ -329,7 +331,8 @@ struct qpg_solver {
       issued += k;
       sync_state();
       if (st_host->done || issued >= maxit) break;
-      batch = 1;
+      more = std::min(2 * more, 8);
+      batch = more;
     }
     last_pcg = std::max(1, st_host->iter);
     return st_host->iter;
