@@ -44,8 +44,9 @@ struct Seg {
   int32_t start, len, slot;
 };
 
-// Column counts over windows (w), eighth-windows (f) and 2^kL2Shift ranges (l2), with the lists
-// of the bins that are non-zero (so that clearing costs what was touched).
+// Column counts over eighth-windows (f), counted entry by entry, and from them over windows (w)
+// and 2^kL2Shift ranges (l2), with the lists of the bins that are non-zero (so that clearing costs
+// what was touched).
 struct Hist {
   std::vector<int64_t> w, f, l2, tw, tf, t2;
   Hist(int64_t nw, int64_t nf, int64_t n2) : w(nw, 0), f(nf, 0), l2(n2, 0) {}
@@ -53,19 +54,19 @@ struct Hist {
     if (cnt[b] == 0) touched.push_back(b);
     cnt[b] += by;
   }
-  void add(int32_t c, int32_t sh, int32_t fsh) {
-    bump(w, tw, c >> sh, 1);
-    bump(f, tf, c >> fsh, 1);
-    bump(l2, t2, c >> kL2Shift, 1);
-  }
-  // adds o's counts and clears o
+  void add(int32_t c, int32_t fsh) { bump(f, tf, c >> fsh, 1); }
+  // adds o's fine counts and clears o
   void merge(Hist& o) {
-    for (int64_t b : o.tw) bump(w, tw, b, o.w[b]), o.w[b] = 0;
     for (int64_t b : o.tf) bump(f, tf, b, o.f[b]), o.f[b] = 0;
-    for (int64_t b : o.t2) bump(l2, t2, b, o.l2[b]), o.l2[b] = 0;
-    o.tw.clear();
     o.tf.clear();
-    o.t2.clear();
+  }
+  // w and l2 from f: a window is 2^(sh − fsh) fine bins, an L2 range 2^(kL2Shift − fsh)
+  // (fsh ≤ sh ≤ 16 < kL2Shift)
+  void derive(int32_t sh, int32_t fsh) {
+    for (int64_t b : tf) {
+      bump(w, tw, b >> (sh - fsh), f[b]);
+      bump(l2, t2, b >> (kL2Shift - fsh), f[b]);
+    }
   }
 };
 constexpr int64_t kParHist = 1 << 20;  // runs with more entries are counted in parallel
@@ -110,44 +111,39 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     const int32_t* last = col + rowptr[r + 1];
     return (int32_t)(std::lower_bound(first, last, (int32_t)std::min<int64_t>(c, INT32_MAX)) - col);
   };
+  // the same, by an exponential search outward from entry position h of the row (cheap when the
+  // answer is near h, as for a row's bounds taken in column order)
+  auto seek_near = [&](int32_t r, int64_t c, int32_t h) {
+    const int32_t cc = (int32_t)std::min<int64_t>(c, INT32_MAX);
+    int32_t lo = rowptr[r], hi = rowptr[r + 1];  // the answer lies in [lo, hi]
+    h = std::min(std::max(h, lo), hi);
+    int32_t step = 1;
+    if (h < hi && col[h] < cc) {  // in (h, hi]: step right while col[p + step] < cc
+      int32_t p = h;
+      while (p + step < hi && col[p + step] < cc) p += step, step <<= 1;
+      lo = p + 1;
+      hi = (int32_t)std::min<int64_t>(hi, (int64_t)p + step);
+    } else {  // in [lo, h]: step left while col[p − step] ≥ cc
+      int32_t p = h;
+      while (p - step >= lo && col[p - step] >= cc) p -= step, step <<= 1;
+      lo = std::max(lo, p - step + 1);
+      hi = p;
+    }
+    return (int32_t)(std::lower_bound(col + lo, col + hi, cc) - col);
+  };
 
-  // One tile: segments sorted by length (longest first; ties in slot order), packed into chunks
-  // of 64 lanes in SELL order. Only the chunk structure is built here (the lanes' segments in
-  // `lanes`, the array offsets from running counts); the entries are written afterwards, chunk
-  // by chunk in parallel.
-  std::vector<Seg> lanes;  // 64 per chunk; len −1 for an empty lane
-  std::vector<Seg> sorted;
-  int64_t n_src = 0, n_c16 = 0, n_c32 = 0;
-  auto add_tile = [&](std::vector<Seg>& segs, int32_t wlo, int32_t wlen, bool keep_empty = false) {
-    if (segs.empty() && !keep_empty) return;
-    {  // stable counting sort by length, longest first (lengths are 0..seg_max)
-      std::vector<int32_t> pos((size_t)seg_max + 2, 0);
-      for (const Seg& g : segs) pos[(size_t)(seg_max - g.len) + 1]++;
-      for (size_t b = 1; b < pos.size(); ++b) pos[b] += pos[b - 1];
-      sorted.resize(segs.size());
-      for (const Seg& g : segs) sorted[(size_t)pos[(size_t)(seg_max - g.len)]++] = g;
-      segs.swap(sorted);
-    }
-    const bool win = wlen > 0;
-    Tile t{};
-    t.chunk0 = (int32_t)plan.chunks.size();
-    t.wlo = wlo;
-    t.wlen = wlen;
-    for (size_t c0 = 0; c0 < segs.size(); c0 += kLanes) {
-      const int32_t nseg = (int32_t)std::min<size_t>(kLanes, segs.size() - c0);
-      Chunk ch{};
-      ch.base = (int32_t)n_src;
-      ch.cbase = (int32_t)(win ? n_c16 : n_c32);
-      ch.steps = segs[c0].len;
-      ch.seg0 = (int32_t)lanes.size();
-      for (int32_t j = 0; j < kLanes; ++j) lanes.push_back(j < nseg ? segs[c0 + j] : Seg{0, -1, -1});
-      n_src += (int64_t)ch.steps * kLanes;
-      (win ? n_c16 : n_c32) += (int64_t)ch.steps * kLanes;
-      plan.chunks.push_back(ch);
-    }
-    t.nchunk = (int32_t)plan.chunks.size() - t.chunk0;
-    plan.tiles.push_back(t);
-    if (win) plan.max_wlen = std::max(plan.max_wlen, wlen);
+  // Tiles are listed first, in their final order, each with its segments in row order (grid
+  // tiles with the first row of their block, b0 ≥ 0, and kept even when empty); they are built
+  // afterwards, tile by tile in parallel: segments sorted by length, chunks of 64 lanes, entries.
+  struct Pending {
+    std::vector<Seg> segs;
+    int32_t wlo, wlen, b0;
+  };
+  std::vector<Pending> pend;
+  auto add_tile = [&](std::vector<Seg>&& segs, int32_t wlo, int32_t wlen, int32_t b0 = -1) {
+    if (segs.empty() && b0 < 0) return;
+    pend.push_back({std::move(segs), wlo, wlen, b0});
+    if (wlen > 0) plan.max_wlen = std::max(plan.max_wlen, wlen);
   };
 
   std::vector<Seg> plain;  // segments waiting for a tile without a window
@@ -158,7 +154,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     const size_t take = all ? plain.size() : plain.size() / kLanes * kLanes;
     std::vector<Seg> t(plain.begin(), plain.begin() + take);
     plain.erase(plain.begin(), plain.begin() + take);
-    add_tile(t, 0, 0);
+    add_tile(std::move(t), 0, 0);
     plain_entries = 0;
     for (const Seg& g : plain) plain_entries += g.len;
   };
@@ -176,7 +172,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     bool grid = false;  // asked for: one segment (possibly empty) per row and range
     bool grid_ok = false;  // granted: every row's entries lie in the windows, ≤ seg_max per range
   };
-  // bounds of every row of a block (3K + 1 entry positions per row, binary searches) and the
+  // bounds of every row of a block (3K + 1 entry positions per row, searched in column order) and the
   // number of segments each row is cut into; reads the matrix only
   auto bounds = [&](Block& bl, int32_t K, int32_t* bnd, int32_t* np, const std::vector<int64_t>& cut) {
     const int32_t stride = 3 * K + 1;
@@ -185,17 +181,27 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
       const int32_t r = bl.b0 + i;
       int32_t* B = bnd + (size_t)i * stride;
       int32_t c = 0;
+      int32_t a = rowptr[r];  // range j starts where range j − 1 ends
       for (int32_t j = 0; j < K; ++j) {
-        const int32_t a = j == 0 ? rowptr[r] : seek(r, cut[j]);
-        const int32_t e = j == K - 1 ? rowptr[r + 1] : seek(r, cut[j + 1]);
-        const int32_t ia = bl.wlen[j] > 0 ? std::max(a, seek(r, bl.wlo[j])) : e;
-        const int32_t ie = bl.wlen[j] > 0 ? std::min(e, seek(r, (int64_t)bl.wlo[j] + bl.wlen[j])) : e;
+        int32_t ia = a, ie = a;  // window bounds, clamped to the range below
+        if (bl.wlen[j] > 0) {
+          ia = seek_near(r, bl.wlo[j], a);
+          ie = seek_near(r, (int64_t)bl.wlo[j] + bl.wlen[j], ia);
+        }
+        const int32_t e = j == K - 1 ? rowptr[r + 1] : seek_near(r, cut[j + 1], ie);
+        if (bl.wlen[j] > 0) {
+          ia = std::max(a, ia);
+          ie = std::min(e, ie);
+        } else {
+          ia = ie = e;
+        }
         B[3 * j] = a;
         B[3 * j + 1] = ia;
         B[3 * j + 2] = ie;
         B[3 * j + 3] = e;
         c += pieces(a, ia) + pieces(ia, ie) + pieces(ie, e);
         if (grid_ok && (a != ia || ie != e || bl.wlen[j] == 0 || ie - ia > seg_max)) grid_ok = false;
+        a = e;
       }
       np[i] = c;
     }
@@ -203,53 +209,63 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
     if (grid_ok)
       for (int32_t i = 0; i < bl.b1 - bl.b0; ++i) np[i] = K;
   };
-  // slots, segments and tiles of a block from its bounds, in row order
-  std::vector<std::vector<Seg>> wsegs;
-  std::vector<int32_t> tile_b0;  // per tile: the first row of its grid block, or −1
-  struct GridBlock {
-    int32_t b0, b1, K, t0;
+  // segments of a block from its bounds, in row order, numbered from rowslot: per range, those
+  // inside its window and those outside (one list, or one per range for by-range tiles)
+  struct BlockSegs {
+    std::vector<std::vector<Seg>> win, out;
   };
-  std::vector<GridBlock> grids;
-  auto emit = [&](const Block& bl, int32_t K, const int32_t* bnd, const int32_t* np,
-                  std::vector<std::vector<Seg>>* by_range) {
+  auto cut_block = [&](const Block& bl, int32_t K, const int32_t* bnd, bool per_range, BlockSegs& o) {
     const int32_t stride = 3 * K + 1, Rb = bl.b1 - bl.b0;
-    for (int32_t i = 0; i < Rb; ++i) plan.rowslot[bl.b0 + i + 1] = plan.rowslot[bl.b0 + i] + np[i];
-    wsegs.assign(K, {});
+    o.win.assign(K, {});
+    o.out.assign(per_range ? K : 1, {});
     if (bl.grid_ok) {
+      for (int32_t j = 0; j < K; ++j) o.win[j].reserve((size_t)Rb);
       for (int32_t i = 0; i < Rb; ++i) {
         const int32_t* B = bnd + (size_t)i * stride;
         int32_t next = plan.rowslot[bl.b0 + i];
-        for (int32_t j = 0; j < K; ++j) wsegs[j].push_back({B[3 * j + 1], B[3 * j + 2] - B[3 * j + 1], next++});
+        for (int32_t j = 0; j < K; ++j) o.win[j].push_back({B[3 * j + 1], B[3 * j + 2] - B[3 * j + 1], next++});
       }
-      const int32_t t0 = (int32_t)plan.tiles.size();
-      for (int32_t j = 0; j < K; ++j) {
-        add_tile(wsegs[j], bl.wlo[j], bl.wlen[j], true);
-        tile_b0.resize(plan.tiles.size(), -1);
-        tile_b0.back() = bl.b0;
-      }
-      grids.push_back({bl.b0, bl.b1, K, t0});
       return;
     }
     for (int32_t i = 0; i < Rb; ++i) {
       const int32_t* B = bnd + (size_t)i * stride;
       int32_t next = plan.rowslot[bl.b0 + i];
       for (int32_t j = 0; j < K; ++j) {
-        std::vector<Seg>& out = by_range ? (*by_range)[j] : plain;
-        const size_t before = out.size();
+        std::vector<Seg>& out = o.out[per_range ? j : 0];
         cut_segs(out, B[3 * j], B[3 * j + 1], &next);
-        cut_segs(wsegs[j], B[3 * j + 1], B[3 * j + 2], &next);
+        cut_segs(o.win[j], B[3 * j + 1], B[3 * j + 2], &next);
         cut_segs(out, B[3 * j + 2], B[3 * j + 3], &next);
-        if (!by_range)
-          for (size_t q = before; q < plain.size(); ++q) plain_entries += plain[q].len;
       }
     }
-    for (int32_t j = 0; j < K; ++j) add_tile(wsegs[j], bl.wlo[j], bl.wlen[j]);
+  };
+  // the tiles of a block, in block order: its windowed tiles, then (single list) a tile of the
+  // segments outside windows once enough of them have gathered
+  struct GridBlock {
+    int32_t b0, b1, K, t0;
+  };
+  std::vector<GridBlock> grids;
+  auto emit = [&](const Block& bl, int32_t K, BlockSegs& o, std::vector<std::vector<Seg>>* by_range) {
+    if (bl.grid_ok) {
+      const int32_t t0 = (int32_t)pend.size();
+      for (int32_t j = 0; j < K; ++j) add_tile(std::move(o.win[j]), bl.wlo[j], bl.wlen[j], bl.b0);
+      grids.push_back({bl.b0, bl.b1, K, t0});
+      return;
+    }
+    if (by_range) {
+      for (int32_t j = 0; j < K; ++j) (*by_range)[j].insert((*by_range)[j].end(), o.out[j].begin(), o.out[j].end());
+    } else {
+      for (const Seg& g : o.out[0]) plain_entries += g.len;
+      plain.insert(plain.end(), o.out[0].begin(), o.out[0].end());
+    }
+    for (int32_t j = 0; j < K; ++j) add_tile(std::move(o.win[j]), bl.wlo[j], bl.wlen[j]);
     flush_plain(false);
   };
-  // The blocks of one run, in batches of bounded size: the window decision (`decide`) and the
-  // bounds of the blocks of a batch are computed in parallel, then the blocks are emitted in
+  // The blocks of one run, in batches of bounded size: the window decision (`decide`), the bounds
+  // and the segments of the blocks of a batch are computed in parallel (the slot numbers of a
+  // block's rows from the counts, in order, in between), then the blocks' tiles are listed in
   // order, so the work list does not depend on the number of threads.
   std::vector<int32_t> bbuf, npbuf;
+  std::vector<BlockSegs> bsegs;
   auto run_blocks = [&](std::vector<Block>& blocks, const std::vector<int64_t>& cut,
                         std::vector<std::vector<Seg>>* by_range, const auto& decide) {
     const int32_t K = (int32_t)cut.size() - 1, stride = 3 * K + 1;
@@ -272,8 +288,16 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
         decide(bl);
         bounds(bl, K, bbuf.data() + off[q], npbuf.data() + roff[q], cut);
       });
-      for (size_t q = 0; q < j1 - j0; ++q)
-        emit(blocks[j0 + q], K, bbuf.data() + off[q], npbuf.data() + roff[q], by_range);
+      for (size_t q = 0; q < j1 - j0; ++q) {
+        const Block& bl = blocks[j0 + q];
+        const int32_t* np = npbuf.data() + roff[q];
+        for (int32_t i = 0; i < bl.b1 - bl.b0; ++i) plan.rowslot[bl.b0 + i + 1] = plan.rowslot[bl.b0 + i] + np[i];
+      }
+      bsegs.resize(j1 - j0);
+      parallel_chunks((int64_t)(j1 - j0), 1, [&](int64_t q, int64_t, int64_t) {
+        cut_block(blocks[j0 + q], K, bbuf.data() + off[q], by_range != nullptr, bsegs[q]);
+      });
+      for (size_t q = 0; q < j1 - j0; ++q) emit(blocks[j0 + q], K, bsegs[q], by_range);
       j0 = j1;
     }
   };
@@ -300,15 +324,16 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
 
     // ---- column histogram of the run (a long run in parts, counted in parallel and merged)
     if (nnz_g < kParHist) {
-      for (int64_t k = rowptr[g0]; k < rowptr[g1]; ++k) hist.add(col[k], sh, fsh);
+      for (int64_t k = rowptr[g0]; k < rowptr[g1]; ++k) hist.add(col[k], fsh);
     } else {
-      if (part.empty()) part.assign(kHistParts, Hist(cnt.size(), fine.size(), cnt2.size()));
+      if (part.empty()) part.assign(kHistParts, Hist(0, fine.size(), 0));
       parallel_chunks(kHistParts, 1, [&](int64_t t, int64_t, int64_t) {
         const int64_t k0 = rowptr[g0] + nnz_g * t / kHistParts, k1 = rowptr[g0] + nnz_g * (t + 1) / kHistParts;
-        for (int64_t k = k0; k < k1; ++k) part[t].add(col[k], sh, fsh);
+        for (int64_t k = k0; k < k1; ++k) part[t].add(col[k], fsh);
       });
       for (Hist& h : part) hist.merge(h);
     }
+    hist.derive(sh, fsh);
     std::vector<int64_t> S2;  // L2-sized column ranges holding min_seg entries per row
     int64_t covS2 = 0;
     for (int64_t w : touched_2)
@@ -456,8 +481,7 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
           size_t e = i;
           int64_t ent = 0;
           while (e < v.size() && (ent < plain_nnz || (e - i) % kLanes != 0)) ent += v[e++].len;
-          std::vector<Seg> t(v.begin() + i, v.begin() + e);
-          add_tile(t, 0, 0);
+          add_tile(std::vector<Seg>(v.begin() + i, v.begin() + e), 0, 0);
           i = e;
         }
       }
@@ -504,74 +528,94 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
   }
   flush_plain(true);
   plan.nslot = plan.rowslot[nrows];
-  // ---- the entries in SELL order. Padding repeats the lane's last column with a zero value.
-  plan.segslot.resize(lanes.size());
+  // ---- the tiles. Pass 1, per tile: the slots (a tile's segments get consecutive slots in the
+  // order they were listed, which is row order, and slotidx maps a segment's row-order id to its
+  // slot), then the segments sorted by length, longest first (a stable counting sort, so ties stay
+  // in row order), and the tile's count of entries in SELL order.
+  const size_t nt = pend.size();
+  std::vector<int64_t> first(nt + 1, 0), nent(nt, 0);
+  for (size_t ti = 0; ti < nt; ++ti) first[ti + 1] = first[ti] + (int64_t)pend[ti].segs.size();
+  plan.slotidx.assign((size_t)plan.nslot, -1);
+  parallel_chunks((int64_t)nt, 8, [&](int64_t, int64_t t0, int64_t t1) {
+    std::vector<int32_t> pos;
+    std::vector<Seg> sorted;
+    for (int64_t ti = t0; ti < t1; ++ti) {
+      std::vector<Seg>& segs = pend[ti].segs;
+      for (size_t k = 0; k < segs.size(); ++k) plan.slotidx[segs[k].slot] = (int32_t)(first[ti] + (int64_t)k);
+      pos.assign((size_t)seg_max + 2, 0);  // lengths are 0..seg_max
+      for (const Seg& g : segs) pos[(size_t)(seg_max - g.len) + 1]++;
+      for (size_t b = 1; b < pos.size(); ++b) pos[b] += pos[b - 1];
+      sorted.resize(segs.size());
+      for (const Seg& g : segs) sorted[(size_t)pos[(size_t)(seg_max - g.len)]++] = g;
+      segs.swap(sorted);
+      int64_t e = 0;
+      for (size_t c0 = 0; c0 < segs.size(); c0 += kLanes) e += (int64_t)segs[c0].len * kLanes;
+      nent[ti] = e;
+    }
+  });
+  // offsets, in tile order: chunks, entries, and column indices (16-bit for windowed tiles)
+  plan.tiles.resize(nt);
+  std::vector<int64_t> sbase(nt), cbase(nt);
+  int64_t n_chunk = 0, n_src = 0, n_c16 = 0, n_c32 = 0;
+  for (size_t ti = 0; ti < nt; ++ti) {
+    const Pending& pt = pend[ti];
+    const int32_t nch = (int32_t)((pt.segs.size() + kLanes - 1) / kLanes);
+    plan.tiles[ti] = Tile{(int32_t)n_chunk, nch, pt.wlo, pt.wlen};
+    int64_t& nc = pt.wlen > 0 ? n_c16 : n_c32;
+    sbase[ti] = n_src;
+    cbase[ti] = nc;
+    n_chunk += nch;
+    n_src += nent[ti];
+    nc += nent[ti];
+  }
+  // ---- pass 2, per tile: chunks of 64 lanes in SELL order (a chunk takes as many steps as its
+  // longest segment), each lane's slot, and the entries. Padding repeats the lane's last column
+  // with a zero value.
+  plan.chunks.resize((size_t)n_chunk);
+  plan.segslot.resize((size_t)n_chunk * kLanes);
   plan.src.resize((size_t)n_src);
   plan.col16.resize((size_t)n_c16);
   plan.col32.resize((size_t)n_c32);
-  parallel_chunks((int64_t)plan.tiles.size(), 8, [&](int64_t, int64_t t0, int64_t t1) {
+  parallel_chunks((int64_t)nt, 8, [&](int64_t, int64_t t0, int64_t t1) {
+    Seg g[kLanes];
     for (int64_t ti = t0; ti < t1; ++ti) {
       const Tile& t = plan.tiles[ti];
+      const std::vector<Seg>& segs = pend[ti].segs;
       const bool win = t.wlen > 0;
-      for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci) {
-        const Chunk& ch = plan.chunks[ci];
-        const Seg* g = &lanes[ch.seg0];
-        int32_t* src = &plan.src[ch.base];
-        for (int32_t j = 0; j < kLanes; ++j) plan.segslot[ch.seg0 + j] = g[j].slot;
+      int64_t base = sbase[ti], cb = cbase[ti];
+      for (int32_t c = 0; c < t.nchunk; ++c) {
+        const size_t c0 = (size_t)c * kLanes;
+        const size_t nseg = std::min<size_t>(kLanes, segs.size() - c0);
+        for (size_t j = 0; j < (size_t)kLanes; ++j) g[j] = j < nseg ? segs[c0 + j] : Seg{0, -1, -1};
+        Chunk& ch = plan.chunks[(size_t)t.chunk0 + c];
+        ch.base = (int32_t)base;
+        ch.cbase = (int32_t)cb;
+        ch.steps = g[0].len;
+        ch.seg0 = (t.chunk0 + c) * kLanes;
+        for (int32_t j = 0; j < kLanes; ++j) plan.segslot[(size_t)ch.seg0 + j] = g[j].slot >= 0 ? plan.slotidx[g[j].slot] : -1;
+        int32_t* src = &plan.src[(size_t)base];
         for (int32_t q = 0; q < ch.steps; ++q) {
           for (int32_t j = 0; j < kLanes; ++j) {
             const int32_t len = g[j].len;
             const int32_t k = q < len ? g[j].start + q : -1;
-            const int32_t c = len > 0 ? col[q < len ? g[j].start + q : g[j].start + len - 1] : (win ? t.wlo : 0);
+            const int32_t c1 = len > 0 ? col[q < len ? g[j].start + q : g[j].start + len - 1] : (win ? t.wlo : 0);
             src[(size_t)q * kLanes + j] = k;
             if (win)
-              plan.col16[(size_t)ch.cbase + (size_t)q * kLanes + j] = (uint16_t)(c - t.wlo);
+              plan.col16[(size_t)cb + (size_t)q * kLanes + j] = (uint16_t)(c1 - t.wlo);
             else
-              plan.col32[(size_t)ch.cbase + (size_t)q * kLanes + j] = c;
+              plan.col32[(size_t)cb + (size_t)q * kLanes + j] = c1;
           }
         }
+        base += (int64_t)ch.steps * kLanes;
+        cb += (int64_t)ch.steps * kLanes;
       }
     }
   });
-  // ---- slot numbers tile by tile. Up to here a segment's id is its position in row order
-  // (rowslot); each tile's segments now get consecutive slots in that order, and slotidx maps
-  // the row-order id to the slot.
-  {
-    const size_t nt = plan.tiles.size();
-    std::vector<int64_t> first(nt + 1, 0);
-    for (size_t ti = 0; ti < nt; ++ti) {
-      const Tile& t = plan.tiles[ti];
-      int64_t c = 0;
-      for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
-        for (int32_t j = 0; j < kLanes; ++j) c += plan.segslot[(size_t)plan.chunks[ci].seg0 + j] >= 0;
-      first[ti + 1] = first[ti] + c;
-    }
-    plan.slotidx.assign((size_t)plan.nslot, -1);
-    parallel_chunks((int64_t)nt, 8, [&](int64_t, int64_t t0, int64_t t1) {
-      std::vector<int32_t> ids;
-      for (int64_t ti = t0; ti < t1; ++ti) {
-        const Tile& t = plan.tiles[ti];
-        ids.clear();
-        for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
-          for (int32_t j = 0; j < kLanes; ++j) {
-            const int32_t id = plan.segslot[(size_t)plan.chunks[ci].seg0 + j];
-            if (id >= 0) ids.push_back(id);
-          }
-        std::sort(ids.begin(), ids.end());
-        for (size_t k = 0; k < ids.size(); ++k) plan.slotidx[ids[k]] = (int32_t)(first[ti] + (int64_t)k);
-        for (int32_t ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci)
-          for (int32_t j = 0; j < kLanes; ++j) {
-            int32_t& sl = plan.segslot[(size_t)plan.chunks[ci].seg0 + j];
-            if (sl >= 0) sl = plan.slotidx[sl];
-          }
-      }
-    });
-    // grid tiles: row r of the block has its slot at first + (r − b0)
-    tile_b0.resize(nt, -1);
-    plan.tbase.assign(std::max<size_t>(nt, 1), 0);
-    for (size_t ti = 0; ti < nt; ++ti)
-      if (tile_b0[ti] >= 0) plan.tbase[ti] = (int32_t)(first[ti] - tile_b0[ti]);
-  }
+  // grid tiles: row r of the block has its slot at first + (r − b0)
+  plan.tbase.assign(std::max<size_t>(nt, 1), 0);
+  for (size_t ti = 0; ti < nt; ++ti)
+    if (pend[ti].b0 >= 0) plan.tbase[ti] = (int32_t)(first[ti] - pend[ti].b0);
+  std::vector<Pending>().swap(pend);
   // combine work: lanes per row ≈ a quarter of the row's slots (1..64), the largest over the
   // rows of one workgroup; a workgroup of kBlock threads takes one pass of consecutive rows
   auto lg_of = [&](int32_t q) {
