@@ -52,6 +52,29 @@ void atomic_min(std::atomic<int64_t>& a, int64_t v) {
 
 // Structural checks of a CSC matrix (columns checked in parallel; the first failing column is
 // reported, as a serial scan would).
+// [0, n) cut into `parts` ranges of about equal work, item i costing ptr[i + 1] − ptr[i] entries
+// plus one (ptr non-decreasing): a few long columns or rows then no longer fall to one thread
+template <typename I>
+std::vector<int64_t> work_cuts(const I* ptr, int64_t n, int64_t parts) {
+  std::vector<int64_t> cut((size_t)parts + 1, n);
+  const int64_t total = (int64_t)(ptr[n] - ptr[0]) + n;
+  cut[0] = 0;
+  for (int64_t t = 1; t < parts; ++t) {
+    const int64_t target = total * t / parts;
+    int64_t lo = cut[(size_t)t - 1], hi = n;  // first i with (ptr[i] − ptr[0]) + i ≥ target
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if ((int64_t)(ptr[mid] - ptr[0]) + mid < target)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    cut[(size_t)t] = lo;
+  }
+  return cut;
+}
+constexpr int64_t kWorkParts = 256;
+
 int check_csc(const qpg_csc* M, int32_t nrows, int32_t ncols, bool upper, const char* name,
               std::string* msg) {
   char buf[256];
@@ -76,9 +99,10 @@ int check_csc(const qpg_csc* M, int32_t nrows, int32_t ncols, bool upper, const 
       return QPG_ERR_ARG;
     }
   std::atomic<int64_t> bad{INT64_MAX};
-  parallel_chunks(ncols, 4096, [&](int64_t, int64_t lo, int64_t hi) {
+  const std::vector<int64_t> cols = work_cuts(M->colptr, ncols, kWorkParts);
+  parallel_chunks(kWorkParts, 1, [&](int64_t t, int64_t, int64_t) {
     std::string m2;
-    for (int64_t j = lo; j < hi; ++j)
+    for (int64_t j = cols[(size_t)t]; j < cols[(size_t)t + 1]; ++j)
       if (column_error(M, (int32_t)j, nrows, upper, name, &m2)) {
         atomic_min(bad, j);
         return;
@@ -334,14 +358,14 @@ int prepare(const qpg_csc* Pt, const double* q, const qpg_csc* A, const double* 
   H.a_csc_val = A->val;
   H.a_colptr = A->colptr;
   // ---- B = [P | Aᵀ]: row i is row i of the full P, then column i of A (CSC of A = CSR of Aᵀ)
-  constexpr int64_t kRows = 1 << 13;  // rows or columns per parallel chunk
   H.b_ptr.assign(n + 1, 0);
   H.b_split.resize(n);
   for (int32_t i = 0; i < n; ++i)
     H.b_ptr[i + 1] = H.b_ptr[i] + (H.p_ptr[i + 1] - H.p_ptr[i]) + (A->colptr[i + 1] - A->colptr[i]);
   H.b_col.resize(H.b_ptr[n]);
-  parallel_chunks(n, kRows, [&](int64_t, int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi; ++i) {
+  const std::vector<int64_t> rows = work_cuts(H.b_ptr.data(), n, kWorkParts);
+  parallel_chunks(kWorkParts, 1, [&](int64_t t, int64_t, int64_t) {
+    for (int64_t i = rows[(size_t)t]; i < rows[(size_t)t + 1]; ++i) {
       int32_t o = H.b_ptr[i];
       for (int32_t k = H.p_ptr[i]; k < H.p_ptr[i + 1]; ++k, ++o) H.b_col[o] = p_col[k];
       H.b_split[i] = o;
