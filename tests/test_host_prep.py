@@ -173,3 +173,49 @@ def test_malformed_inputs_are_rejected(exe, tmp_path, case):
                      raw=kw.get("raw"))
     assert rc == code, (case[0], rc, msg)
     assert msg
+
+
+def skewed_problem(seed, n_dense=12, n=700, m=3000):
+    """A few dense columns of A that hold most of its entries (as the feature columns of the SVM
+    QP do) beside many columns of one or two entries: the column checks and B's rows are cut into
+    parts of equal entry counts, so a part boundary falls inside the dense run and the long tail
+    of short columns spreads over many parts."""
+    rng = np.random.default_rng(seed)
+    dense = sp.random(m, n_dense, density=0.6, random_state=rng, format="csc")
+    rows = rng.integers(0, m, size=n - n_dense)
+    tail = sp.csc_matrix((rng.standard_normal(n - n_dense), (rows, np.arange(n - n_dense))), shape=(m, n - n_dense))
+    A = sp.hstack([dense, tail]).tocsc()
+    A.sort_indices()
+    Pt = sp.diags(1.0 + rng.random(n)).tocsc()
+    l = -rng.random(m)
+    u = rng.random(m)
+    return Pt, rng.standard_normal(n), A, l, u
+
+
+def test_conversion_of_skewed_columns(exe, tmp_path):
+    Pt, q, A, l, u = skewed_problem(5)
+    assert np.diff(A.indptr)[:12].sum() > 0.9 * A.nnz
+    rc, msg, o = run(exe, str(tmp_path), Pt, q, A, l, u)
+    assert rc == 0, msg
+    Ar = sp.csr_matrix(A)
+    Ar.sort_indices()
+    np.testing.assert_array_equal(o["a_ptr"], Ar.indptr)
+    np.testing.assert_array_equal(o["a_col"], Ar.indices)
+    np.testing.assert_array_equal(o["a_val"], Ar.data)
+    B = sp.hstack([sp.csr_matrix(Pt), sp.csr_matrix(A.T)]).tocsr()
+    B.sort_indices()
+    np.testing.assert_array_equal(o["b_ptr"], B.indptr)
+    np.testing.assert_array_equal(o["b_col"], B.indices)
+    np.testing.assert_array_equal(o["b_val"], B.data)
+
+
+@pytest.mark.parametrize("where", ["first dense column", "inside the dense run", "last column"])
+def test_skewed_columns_bad_index_is_found(exe, tmp_path, where):
+    """A row index out of range is reported wherever the parts of the column check cut."""
+    Pt, q, A, l, u = skewed_problem(6)
+    j = {"first dense column": 0, "inside the dense run": 7, "last column": A.shape[1] - 1}[where]
+    ri = A.indices.copy()
+    ri[A.indptr[j + 1] - 1] = A.shape[0]
+    rc, msg, _ = run(exe, str(tmp_path), Pt, q, A, l, u, raw={"ari": ri})
+    assert rc == ERR_ARG, (where, rc, msg)
+    assert "A" in msg
