@@ -147,9 +147,15 @@ struct TilePlan {
   // per tile of a grid block: its first slot minus the block's first row; then one entry per run
   // of single-segment rows with consecutive slots (slot − row)
   std::vector<int32_t> tbase;
+  // per lane (64 per chunk): the first CSR index of its segment and the segment's length (−1 for
+  // an empty lane). Lane j of a chunk, at step q < steps, holds the entry lstart + q (CSR index
+  // −1 and the lane's last column past the segment's end; the window's first column, or column 0
+  // without a window, for a lane with no entries).
+  hvec<int32_t> lstart, llen;
   hvec<int32_t> src;             // per SELL value position: CSR index, −1 for padding
   hvec<uint16_t> col16;          // column offsets of windowed tiles (SELL order)
   hvec<int32_t> col32;           // columns of the other tiles (SELL order)
+  int64_t n_src = 0, n_c16 = 0, n_c32 = 0;  // their sizes (also when only the lanes are written)
   int64_t nslot = 0;
   int32_t max_wlen = 0;          // largest staged window (columns)
 };
@@ -161,6 +167,9 @@ struct TileParams {
   int32_t max_rows;   // rows per block at most
   int32_t min_seg = kMinSeg;  // entries per row and range (on average) for a multi-range layout
   bool grid = true;           // the grid layout may be used (see tiles.cpp)
+  // write the entries in SELL order (src, col16, col32) on the host; without, only the lanes
+  // (lstart, llen), from which the device writes them
+  bool host_entries = true;
 };
 
 // nrows × ncols CSR matrix (row pointers rowptr[0..nrows], column indices col[rowptr[0] ..

@@ -274,6 +274,48 @@ __global__ __launch_bounds__(kBlock) void k_gather_values(int64_t count, const i
   }
 }
 
+// The entries of a work list in SELL order, from its lanes (see TilePlan): one workgroup per
+// tile, one wavefront per chunk, a lane per lane. At step q, lane j of a chunk holds the CSR index
+// start + q while q < len, else −1 (padding), and the column of that entry (of the segment's last
+// entry in the padding; the window's first column, or 0 without a window, for an empty lane),
+// stored as an offset from the window's first column in a windowed tile. The arguments are the
+// planner's own arrays, whose bounds it guarantees; the indices are checked again here so that a
+// malformed list cannot make this kernel read or write outside them.
+__global__ __launch_bounds__(kBlock) void k_sell_build(const Tile* __restrict__ tiles, int32_t ntiles,
+                                                       const Chunk* __restrict__ chunks, int64_t nchunk,
+                                                       const int32_t* __restrict__ lstart,
+                                                       const int32_t* __restrict__ llen,
+                                                       const int32_t* __restrict__ col, int64_t nnz,
+                                                       int32_t* __restrict__ src, int64_t n_src,
+                                                       uint16_t* __restrict__ col16, int64_t n_c16,
+                                                       int32_t* __restrict__ col32, int64_t n_c32) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = kBlock >> 6;
+  for (int32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile T = tiles[t];
+    const bool win = T.wlen > 0;
+    if (T.chunk0 < 0) continue;
+    for (int64_t ci = (int64_t)T.chunk0 + wave; ci < (int64_t)T.chunk0 + T.nchunk && ci < nchunk; ci += nwave) {
+      const Chunk ch = chunks[ci];
+      const int64_t steps = ch.steps, base = ch.base, cbase = ch.cbase;
+      if (base < 0 || cbase < 0 || steps < 0 || base + steps * 64 > n_src ||
+          cbase + steps * 64 > (win ? n_c16 : n_c32) || ch.seg0 < 0 || (int64_t)ch.seg0 + 64 > nchunk * 64)
+        continue;
+      const int32_t s0 = lstart[(int64_t)ch.seg0 + lane];
+      int32_t len = llen[(int64_t)ch.seg0 + lane];
+      if (s0 < 0 || (int64_t)s0 + len > nnz) len = -1;
+      for (int64_t q = 0; q < steps; ++q) {
+        const int32_t k = q < len ? s0 + (int32_t)q : -1;
+        const int32_t c = len > 0 ? col[q < len ? k : s0 + len - 1] : (win ? T.wlo : 0);
+        src[base + q * 64 + lane] = k;
+        if (win)
+          col16[cbase + q * 64 + lane] = (uint16_t)(c - T.wlo);
+        else
+          col32[cbase + q * 64 + lane] = c;
+      }
+    }
+  }
+}
+
 // Values of B = [P | Aᵀ] in CSR (unscaled): row i is row i of the full P (p_val from p_ptr[i]),
 // then column i of A (A's CSC values from a_colptr[i]), both contiguous; one wavefront per row.
 __global__ __launch_bounds__(kBlock) void k_assemble_b(int n, const int32_t* __restrict__ b_ptr,

@@ -799,11 +799,17 @@ TilePlan qpg_solver::plan_tiles(const std::vector<int32_t>& rowptr, const int32_
                 s.spmv_min_seg > 0 ? s.spmv_min_seg : kMinSeg,
                 // the grid layout stages windows of 16384 columns for short rows: it pays in float
                 // (64 KB of LDS per window), not in double (128 KB, one workgroup per CU)
-                s.precision == QPG_MIXED};
+                s.precision == QPG_MIXED,
+                // the entries in SELL order are written on the device (upload_plan)
+                false};
   return make_tiles(rowptr, col, nrows, ncols, tp);
 }
 
-void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows) {
+// The work list on the device. The entries in SELL order (CSR index and column of every
+// position) are written there from the lanes and the pattern's columns dcol, already on the
+// device, instead of being built on the host and uploaded.
+void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows,
+                             const int32_t* dcol) {
   if (t.tiles.empty()) t.tiles.push_back(Tile{0, 0, 0, 0});
   if (t.comb.empty()) t.comb.push_back(CombItem{0, 0, 0, 0});
   pl.ncomb = (int32_t)t.comb.size();
@@ -815,8 +821,18 @@ void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t
   pl.rowslot = upload(t.rowslot);
   pl.slotidx = upload(t.slotidx);
   pl.tbase = upload(t.tbase);
-  pl.col16 = upload(t.col16);
-  pl.col32 = upload(t.col32);
+  pl.nsrc = t.n_src;
+  pl.src = alloc<int32_t>((size_t)t.n_src);
+  pl.col16 = alloc<uint16_t>((size_t)t.n_c16);
+  pl.col32 = alloc<int32_t>((size_t)t.n_c32);
+  int32_t* lstart = upload(t.lstart);
+  int32_t* llen = upload(t.llen);
+  const int64_t nnz = (int64_t)rowptr[nrows] - rowptr[0];
+  const int g = std::max(1, std::min(pl.ntiles, 65536));
+  hipLaunchKernelGGL(k_sell_build, dim3(g), dim3(kBlock), 0, stream, (const Tile*)pl.tiles, pl.ntiles,
+                     (const Chunk*)pl.chunks, (int64_t)t.chunks.size(), (const int32_t*)lstart,
+                     (const int32_t*)llen, dcol, nnz, pl.src, t.n_src, pl.col16, t.n_c16, pl.col32, t.n_c32);
+  HIPCHK(hipGetLastError());
   pl.nslot = t.nslot;
   pl.nrows = nrows;
   // B's slots hold four planes (the two-vector pass of the checks), Ā's two
@@ -827,41 +843,34 @@ void qpg_solver::upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t
     staged += x.wlen;
     wtiles += x.wlen > 0;
   }
-  const int64_t layout[8] = {(int64_t)rowptr[nrows] - rowptr[0], (int64_t)t.col16.size(), (int64_t)t.col32.size(),
-                             (int64_t)t.tiles.size(), wtiles, staged, t.nslot, (int64_t)t.chunks.size()};
+  const int64_t layout[8] = {nnz, t.n_c16, t.n_c32, (int64_t)t.tiles.size(), wtiles, staged, t.nslot,
+                             (int64_t)t.chunks.size()};
   std::copy(layout, layout + 8, pl.layout);
   HIPCHK(hipStreamSynchronize(stream));  // t's host arrays go out of scope
-  pl.src = std::move(t.src);
+  free_tracked(lstart);
+  free_tracked(llen);
 }
 
 // Values in the plan's SELL order (zero in the padding), gathered on the device from the
 // equilibrated CSR values through the plan's CSR index of every SELL position; FP32 copies cast
 // from them.
 void qpg_solver::place_values(DevPlan& pl, const double* csr_val, bool fp32) {
-  const size_t count = pl.src.size();
-  int32_t* src = nullptr;
-  HIPCHK(hipMalloc((void**)&src, std::max<size_t>(count, 1) * sizeof(int32_t)));
-  try {
-    copy_h2d(src, pl.src.data(), count * sizeof(int32_t));
-    pl.val64 = alloc<double>(count);
-    if (count) {
-      const int g = (int)std::min<size_t>((count + kBlock - 1) / kBlock, 65536);
-      hipLaunchKernelGGL(k_gather_values, dim3(g), dim3(kBlock), 0, stream, (int64_t)count, (const int32_t*)src,
-                         csr_val, pl.val64);
-    }
-    if (fp32) {
-      pl.val32 = alloc<float>(count);
-      if (count)
-        hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for((int)count)), dim3(kBlock), 0, stream,
-                           (int)count, pl.val32, (const double*)pl.val64);
-    }
-    HIPCHK(hipStreamSynchronize(stream));
-  } catch (...) {
-    (void)hipFree(src);
-    throw;
+  const size_t count = (size_t)pl.nsrc;
+  pl.val64 = alloc<double>(count);
+  if (count) {
+    const int g = (int)std::min<size_t>((count + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(k_gather_values, dim3(g), dim3(kBlock), 0, stream, (int64_t)count, (const int32_t*)pl.src,
+                       csr_val, pl.val64);
   }
-  HIPCHK(hipFree(src));
-  hvec<int32_t>().swap(pl.src);
+  if (fp32) {
+    pl.val32 = alloc<float>(count);
+    if (count)
+      hipLaunchKernelGGL((k_cast<float, double>), dim3(grid_for((int)count)), dim3(kBlock), 0, stream,
+                         (int)count, pl.val32, (const double*)pl.val64);
+  }
+  HIPCHK(hipStreamSynchronize(stream));
+  free_tracked(pl.src);
+  pl.src = nullptr;
 }
 
 // Modified Ruiz equilibration (Algorithm 2) of the uploaded raw problem, on the device (see
@@ -1083,8 +1092,8 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
     if (plan_err_a) std::rethrow_exception(plan_err_a);
     if (plan_err_b) std::rethrow_exception(plan_err_b);
     mark("work lists (wait for the host thread)", nullptr);
-    h->upload_plan(h->plan_a, ta, H.a_ptr, H.m);
-    h->upload_plan(h->plan_b, tb, H.b_ptr, H.n);
+    h->upload_plan(h->plan_a, ta, H.a_ptr, H.m, h->a_col);
+    h->upload_plan(h->plan_b, tb, H.b_ptr, H.n, h->b_col);
     mark("work-list uploads", h->stream);
     if (std::max(h->plan_a.ncomb, h->plan_b.ncomb) > maxgrid) {
       maxgrid = std::max(h->plan_a.ncomb, h->plan_b.ncomb);

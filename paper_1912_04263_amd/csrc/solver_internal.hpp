@@ -95,7 +95,8 @@ struct DevPlan {
   int32_t nrows = 0;
   int32_t max_wlen = 0;  // largest staged window, in columns
   int64_t layout[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // see qpg_spmv_layout
-  qpg::hvec<int32_t> src;  // host copy of the SELL order (until the values are placed)
+  int32_t* src = nullptr;  // CSR index of every SELL position, on the device until the values are placed
+  int64_t nsrc = 0;
 };
 
 struct LearnedState;  // learned-preconditioner data of a solver (learned.hip)
@@ -159,6 +160,13 @@ struct qpg_solver {
     if (e != hipSuccess) throw HipError{e, "hipMalloc"};
     allocs.push_back(ptr);
     return static_cast<T*>(ptr);
+  }
+  // frees a block from alloc before the solver ends
+  void free_tracked(void* ptr) {
+    auto it = std::find(allocs.begin(), allocs.end(), ptr);
+    if (it == allocs.end()) return;
+    allocs.erase(it);
+    HIPCHK(hipFree(ptr));
   }
   template <typename T, class A>
   T* upload(const std::vector<T, A>& h) {
@@ -377,7 +385,8 @@ struct qpg_solver {
   int solve();
   TilePlan plan_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int32_t nrows,
                       int32_t ncols) const;
-  void upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows);
+  void upload_plan(DevPlan& pl, TilePlan& t, const std::vector<int32_t>& rowptr, int32_t nrows,
+                   const int32_t* dcol);
   void place_values(DevPlan& pl, const double* csr_val, bool fp32);
   void alloc_prec64(const HostProblem& H);
   void place_raw(const HostProblem& H);

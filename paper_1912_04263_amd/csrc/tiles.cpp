@@ -573,9 +573,16 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
   // with a zero value.
   plan.chunks.resize((size_t)n_chunk);
   plan.segslot.resize((size_t)n_chunk * kLanes);
-  plan.src.resize((size_t)n_src);
-  plan.col16.resize((size_t)n_c16);
-  plan.col32.resize((size_t)n_c32);
+  plan.lstart.resize((size_t)n_chunk * kLanes);
+  plan.llen.resize((size_t)n_chunk * kLanes);
+  plan.n_src = n_src;
+  plan.n_c16 = n_c16;
+  plan.n_c32 = n_c32;
+  if (tp.host_entries) {
+    plan.src.resize((size_t)n_src);
+    plan.col16.resize((size_t)n_c16);
+    plan.col32.resize((size_t)n_c32);
+  }
   parallel_chunks((int64_t)nt, 8, [&](int64_t, int64_t t0, int64_t t1) {
     Seg g[kLanes];
     for (int64_t ti = t0; ti < t1; ++ti) {
@@ -592,8 +599,15 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
         ch.cbase = (int32_t)cb;
         ch.steps = g[0].len;
         ch.seg0 = (t.chunk0 + c) * kLanes;
-        for (int32_t j = 0; j < kLanes; ++j) plan.segslot[(size_t)ch.seg0 + j] = g[j].slot >= 0 ? plan.slotidx[g[j].slot] : -1;
-        int32_t* src = &plan.src[(size_t)base];
+        for (int32_t j = 0; j < kLanes; ++j) {
+          plan.segslot[(size_t)ch.seg0 + j] = g[j].slot >= 0 ? plan.slotidx[g[j].slot] : -1;
+          plan.lstart[(size_t)ch.seg0 + j] = g[j].start;
+          plan.llen[(size_t)ch.seg0 + j] = g[j].len;
+        }
+        base += (int64_t)ch.steps * kLanes;
+        cb += (int64_t)ch.steps * kLanes;
+        if (!tp.host_entries) continue;
+        int32_t* src = &plan.src[(size_t)ch.base];
         for (int32_t q = 0; q < ch.steps; ++q) {
           for (int32_t j = 0; j < kLanes; ++j) {
             const int32_t len = g[j].len;
@@ -601,13 +615,11 @@ TilePlan make_tiles(const std::vector<int32_t>& rowptr, const int32_t* col, int3
             const int32_t c1 = len > 0 ? col[q < len ? g[j].start + q : g[j].start + len - 1] : (win ? t.wlo : 0);
             src[(size_t)q * kLanes + j] = k;
             if (win)
-              plan.col16[(size_t)cb + (size_t)q * kLanes + j] = (uint16_t)(c1 - t.wlo);
+              plan.col16[(size_t)ch.cbase + (size_t)q * kLanes + j] = (uint16_t)(c1 - t.wlo);
             else
-              plan.col32[(size_t)cb + (size_t)q * kLanes + j] = c1;
+              plan.col32[(size_t)ch.cbase + (size_t)q * kLanes + j] = c1;
           }
         }
-        base += (int64_t)ch.steps * kLanes;
-        cb += (int64_t)ch.steps * kLanes;
       }
     }
   });

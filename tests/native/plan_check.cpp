@@ -151,6 +151,30 @@ int main(int argc, char** argv) {
       scale = std::max(scale, std::fabs(ref1[r]) + std::fabs(ref2[r]));
     }
     if (err > 1e-12 * std::max(scale, 1.0)) FAIL("row sums off by %g", err);
+    // the lanes alone give the same entries (the device writes them from the lanes): lane j of a
+    // chunk at step q holds CSR index lstart + q while q < llen, else −1, and the column of that
+    // entry, or of the segment's last entry past its end, or the window's first column (0 without
+    // a window) for a lane with no entries
+    if (p.lstart.size() != p.segslot.size() || p.llen.size() != p.segslot.size() || (long)p.src.size() != p.n_src ||
+        (long)p.col16.size() != p.n_c16 || (long)p.col32.size() != p.n_c32)
+      FAIL("lane arrays");
+    for (const Tile& t : p.tiles) {
+      const bool win = t.wlen > 0;
+      for (int ci = t.chunk0; ci < t.chunk0 + t.nchunk; ++ci) {
+        const Chunk& ch = p.chunks[ci];
+        for (int j = 0; j < 64; ++j) {
+          const long s0 = p.lstart[ch.seg0 + j], len = p.llen[ch.seg0 + j];
+          if (len > ch.steps || (len > 0 && (s0 < 0 || s0 + len > nnz))) FAIL("lane %d of chunk %d", j, ci);
+          for (int q = 0; q < ch.steps; ++q) {
+            const long k = q < len ? s0 + q : -1;
+            const long c = len > 0 ? col[q < len ? k : s0 + len - 1] : (win ? t.wlo : 0);
+            const size_t o = (size_t)q * 64 + j;
+            const long c2 = win ? (long)t.wlo + p.col16[ch.cbase + o] : (long)p.col32[ch.cbase + o];
+            if (p.src[ch.base + o] != k || c2 != c) FAIL("lane %d of chunk %d at step %d", j, ci, q);
+          }
+        }
+      }
+    }
     std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d grid_rows %ld empty %ld run_rows %ld\n", wcap,
                 p.tiles.size(), windowed, p.chunks.size(), 100.0 * padding / std::max<size_t>(p.src.size(), 1),
                 100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen, grid_rows, empty_segs, run_rows);
