@@ -58,6 +58,32 @@ struct StagingSet {
   hipEvent_t done[kStageThreads][2] = {};
 };
 StagingSet g_staging[kStageDevices];
+
+// allocates the set's missing buffers and events (S.mu held); a new buffer is written once, so
+// that the first copy into it does not pay for the first touch of its pages
+void ensure_staging(StagingSet& S) {
+  for (int t = 0; t < kStageThreads; ++t)
+    for (int b = 0; b < 2; ++b) {
+      if (!S.done[t][b]) HIPCHK(hipEventCreateWithFlags(&S.done[t][b], hipEventDisableTiming));
+      if (!S.buf[t][b]) {
+        HIPCHK(hipHostMalloc(&S.buf[t][b], kStagePiece, hipHostMallocDefault));
+        std::memset(S.buf[t][b], 0, kStagePiece);
+      }
+    }
+}
+
+// the staging set of a device, made ready ahead of the first large copy (run on a thread of its
+// own during setup); a failure is left to the copy itself to report
+void warm_staging(int device) {
+  if (device < 0 || device >= kStageDevices) return;
+  try {
+    HIPCHK(hipSetDevice(device));
+    StagingSet& S = g_staging[device];
+    std::lock_guard<std::mutex> lock(S.mu);
+    ensure_staging(S);
+  } catch (...) {
+  }
+}
 }  // namespace
 
 void qpg_solver::copy_h2d(void* dst, const void* src, size_t bytes) {
@@ -69,12 +95,7 @@ void qpg_solver::copy_h2d(void* dst, const void* src, size_t bytes) {
   }
   StagingSet& S = g_staging[device];
   std::lock_guard<std::mutex> lock(S.mu);
-  for (int t = 0; t < kStageThreads; ++t)
-    for (int b = 0; b < 2; ++b)
-      if (!S.buf[t][b]) {
-        HIPCHK(hipEventCreateWithFlags(&S.done[t][b], hipEventDisableTiming));
-        HIPCHK(hipHostMalloc(&S.buf[t][b], kStagePiece, hipHostMallocDefault));
-      }
+  ensure_staging(S);
   const size_t npieces = (bytes + kStagePiece - 1) / kStagePiece;
   const int T = (int)std::min<size_t>(kStageThreads, npieces);
   const char* s = static_cast<const char*>(src);
@@ -1020,15 +1041,19 @@ int qpg_setup(qpg_solver** out, const qpg_csc* P_triu, const double* q, const qp
       h->win_cols >>= 1;
     TilePlan ta, tb;
     std::exception_ptr plan_err_a, plan_err_b;
-    std::thread planner_a, planner_b;
-    struct Join {  // the planners read H: they are joined on every way out of this block
+    std::thread planner_a, planner_b, stager;
+    struct Join {  // the planners read H: the threads are joined on every way out of this block
       std::thread& a;
       std::thread& b;
+      std::thread& s;
       ~Join() {
-        if (a.joinable()) a.join();
-        if (b.joinable()) b.join();
+        for (std::thread* t : {&a, &b, &s})
+          if (t->joinable()) t->join();
       }
-    } join{planner_a, planner_b};
+    } join{planner_a, planner_b, stager};
+    // the uploads' pinned staging buffers (once per device and process) are made ready beside
+    // the host's conversion of A
+    stager = std::thread(warm_staging, h->device);
     planner_b = std::thread([&]() {
       try {
         tb = h->plan_tiles(H.b_ptr, H.b_col.data(), H.n, H.n + H.m);
