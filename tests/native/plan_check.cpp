@@ -23,6 +23,14 @@ static std::vector<T> read_all(const std::string& f) {
   return v;
 }
 
+// FNV-1a over the bytes of an array (the work list's fingerprint, to compare builds)
+template <class V>
+static unsigned long long fnv(const V& v, unsigned long long x = 1469598103934665603ull) {
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(v.data());
+  for (size_t i = 0; i < v.size() * sizeof(v[0]); ++i) x = (x ^ p[i]) * 1099511628211ull;
+  return x;
+}
+
 #define FAIL(...)             \
   do {                        \
     std::printf("FAIL: ");    \
@@ -178,6 +186,19 @@ int main(int argc, char** argv) {
     std::printf("wcap %d tiles %zu windowed %ld chunks %zu padding %.1f%% in-window %.1f%% slots %ld maxwin %d grid_rows %ld empty %ld run_rows %ld\n", wcap,
                 p.tiles.size(), windowed, p.chunks.size(), 100.0 * padding / std::max<size_t>(p.src.size(), 1),
                 100.0 * in_win / std::max<long>(nnz, 1), (long)p.nslot, p.max_wlen, grid_rows, empty_segs, run_rows);
+    unsigned long long hsh = fnv(p.tiles);
+    hsh = fnv(p.chunks, hsh);
+    hsh = fnv(p.comb, hsh);
+    hsh = fnv(p.segslot, hsh);
+    hsh = fnv(p.rowslot, hsh);
+    hsh = fnv(p.slotidx, hsh);
+    hsh = fnv(p.tbase, hsh);
+    hsh = fnv(p.lstart, hsh);
+    hsh = fnv(p.llen, hsh);
+    hsh = fnv(p.src, hsh);
+    hsh = fnv(p.col16, hsh);
+    hsh = fnv(p.col32, hsh);
+    std::printf("fingerprint wcap %d %016llx\n", wcap, hsh);
   }
   return 0;
 }

@@ -23,11 +23,13 @@ SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefine
 
 
 @functools.lru_cache(maxsize=None)
-def checker(tmpdir, sanitize=False):
-    exe = os.path.join(tmpdir, "plan_check_asan" if sanitize else "plan_check")
+def checker(tmpdir, sanitize=False, shuffled=False):
+    exe = os.path.join(tmpdir, "plan_check_asan" if sanitize else "plan_check_shuffled" if shuffled else "plan_check")
     opt = SANITIZE if sanitize else ["-O2"]
+    par = (os.path.join(ROOT, "tests", "native", "parallel_shuffled.cpp") if shuffled
+           else os.path.join(CSRC, "host_parallel.cpp"))
     subprocess.run(["g++", *opt, "-std=c++17", "-I", CSRC, os.path.join(ROOT, "tests", "native", "plan_check.cpp"),
-                    os.path.join(CSRC, "tiles.cpp"), os.path.join(CSRC, "host_parallel.cpp"), "-lpthread", "-o", exe],
+                    os.path.join(CSRC, "tiles.cpp"), par, "-lpthread", "-o", exe],
                    check=True)
     return exe
 
@@ -45,13 +47,20 @@ def exe_sanitized(tmp_path_factory):
     return checker(str(tmp_path_factory.mktemp("plan_asan")), sanitize=True)
 
 
+@pytest.fixture(scope="module")
+def exe_shuffled(tmp_path_factory):
+    """The checker linked against a stand-in for the host thread pool whose thread count is set
+    by QPG_TEST_THREADS and which runs the chunks in a scrambled order."""
+    return checker(str(tmp_path_factory.mktemp("plan_shuffled")), shuffled=True)
+
+
 def stats(out):
     """Fields of the first output line (window size wcap) as a dict of ints/floats."""
     f = out.splitlines()[0].replace("%", "").split()
     return {f[i]: float(f[i + 1]) for i in range(0, len(f) - 1, 2)}
 
 
-def run(exe, tmp_path, M, nsplit=None, tile_nnz=32768, plain_nnz=8192, wcap=8192):
+def run(exe, tmp_path, M, nsplit=None, tile_nnz=32768, plain_nnz=8192, wcap=8192, env=None):
     M = sp.csr_matrix(M)
     M.sort_indices()
     pre = str(tmp_path / "m")
@@ -59,7 +68,8 @@ def run(exe, tmp_path, M, nsplit=None, tile_nnz=32768, plain_nnz=8192, wcap=8192
     M.indices.astype(np.int32).tofile(pre + "_col.bin")
     ncols = M.shape[1]
     out = subprocess.run([exe, pre, str(ncols), str(ncols if nsplit is None else nsplit), str(tile_nnz),
-                          str(plain_nnz), str(wcap)], capture_output=True, text=True)
+                          str(plain_nnz), str(wcap)], capture_output=True, text=True,
+                         env=None if env is None else dict(os.environ, **env))
     assert out.returncode == 0, out.stdout + out.stderr
     return out.stdout
 
@@ -174,3 +184,35 @@ def test_grid_layout_under_sanitizers(exe_sanitized, tmp_path):
     rng = np.random.default_rng(6)
     M = sp.random(20000, 3000, density=8 / 3000, random_state=rng, format="csr")
     run(exe_sanitized, tmp_path, M, nsplit=1000, wcap=1024)
+
+
+def fingerprints(out):
+    return [line.split()[-1] for line in out.splitlines() if line.startswith("fingerprint")]
+
+
+@pytest.mark.parametrize("case", ["svm_small B", "portfolio_small A", "lasso_small B", "grid", "skewed"])
+def test_work_lists_do_not_depend_on_the_host_threads(exe, exe_shuffled, tmp_path, case):
+    """The planner's parallel passes write disjoint parts and its lists are assembled in block
+    order, so every array of the work list is the same for any number of host threads and any
+    order in which the threads take the chunks (1, 3 and 8 threads, scrambled, against the
+    library's own pool)."""
+    rng = np.random.default_rng(11)
+    nsplit = None
+    if case == "grid":
+        M = sp.random(30000, 4000, density=20 / 4000, random_state=rng, format="csr")
+        wcap = 1024
+    elif case == "skewed":  # a few long rows among many short ones, wide and narrow
+        M = sp.vstack([sp.random(40, 50000, density=0.2, random_state=rng),
+                       sp.random(20000, 50000, density=3 / 50000, random_state=rng)]).tocsr()
+        wcap = 8192
+    else:
+        name, which = case.split()
+        p = pr.make(name)
+        A, B = reduced_pair(p)
+        M, nsplit, wcap = (A, None, 8192) if which == "A" else (B, p.n, 8192)
+    ref = fingerprints(run(exe, tmp_path, M, nsplit=nsplit, wcap=wcap))
+    assert len(ref) == 2
+    for threads in (1, 3, 8):
+        got = fingerprints(run(exe_shuffled, tmp_path, M, nsplit=nsplit, wcap=wcap,
+                               env={"QPG_TEST_THREADS": str(threads)}))
+        assert got == ref, (case, threads)
