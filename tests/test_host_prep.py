@@ -24,12 +24,13 @@ INF = 1e20
 
 
 @functools.lru_cache(maxsize=None)
-def harness(tmpdir):
-    exe = os.path.join(tmpdir, "prep_check")
+def harness(tmpdir, shuffled=False):
+    exe = os.path.join(tmpdir, "prep_check_shuffled" if shuffled else "prep_check")
+    par = (os.path.join(ROOT, "tests", "native", "parallel_shuffled.cpp") if shuffled
+           else os.path.join(CSRC, "host_parallel.cpp"))
     subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
                     "-fno-sanitize-recover=undefined", "-I", CSRC, os.path.join(ROOT, "tests", "native", "prep_check.cpp"),
-                    os.path.join(CSRC, "host_prep.cpp"), os.path.join(CSRC, "host_parallel.cpp"), "-lpthread",
-                    "-o", exe], check=True)
+                    os.path.join(CSRC, "host_prep.cpp"), par, "-lpthread", "-o", exe], check=True)
     return exe
 
 
@@ -38,7 +39,7 @@ def exe(tmp_path_factory):
     return harness(str(tmp_path_factory.mktemp("prep")))
 
 
-def run(exe, d, P_triu, q, A, l, u, rho_vector=0, raw=None):
+def run(exe, d, P_triu, q, A, l, u, rho_vector=0, raw=None, threads=None):
     """Write the problem, run prepare() under the sanitizers, return (rc, message, outputs)."""
     P_triu = sp.csc_matrix(P_triu)
     A = sp.csc_matrix(A)
@@ -51,6 +52,8 @@ def run(exe, d, P_triu, q, A, l, u, rho_vector=0, raw=None):
     for k, v in (("q", q), ("l", l), ("u", u)):
         np.asarray(v, dtype=np.float64).tofile(os.path.join(d, k + ".bin"))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    if threads is not None:
+        env["QPG_TEST_THREADS"] = str(threads)
     r = subprocess.run([exe, d, str(A.shape[1]), str(A.shape[0]), str(rho_vector)], capture_output=True, text=True,
                        env=env)
     assert r.returncode == 0, r.stdout + r.stderr
@@ -219,3 +222,28 @@ def test_skewed_columns_bad_index_is_found(exe, tmp_path, where):
     rc, msg, _ = run(exe, str(tmp_path), Pt, q, A, l, u, raw={"ari": ri})
     assert rc == ERR_ARG, (where, rc, msg)
     assert "A" in msg
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_conversion_does_not_depend_on_the_host_threads(tmp_path_factory, tmp_path, threads):
+    """The harness linked against a stand-in thread pool (tests/native/parallel_shuffled.cpp):
+    the given number of threads take the chunks of every parallel pass in a scrambled order, and
+    the converted arrays still match SciPy's, on the skewed matrix and on a random one."""
+    exe = harness(str(tmp_path_factory.mktemp("prep_shuffled")), shuffled=True)
+    Pt, q, A, l, u = skewed_problem(7)
+    rc, msg, o = run(exe, str(tmp_path), Pt, q, A, l, u, threads=threads)
+    assert rc == 0, msg
+    Ar = sp.csr_matrix(A)
+    Ar.sort_indices()
+    B = sp.hstack([sp.csr_matrix(Pt), sp.csr_matrix(A.T)]).tocsr()
+    B.sort_indices()
+    for k, ref in (("a_ptr", Ar.indptr), ("a_col", Ar.indices), ("a_val", Ar.data), ("b_ptr", B.indptr),
+                   ("b_col", B.indices), ("b_val", B.data)):
+        np.testing.assert_array_equal(o[k], ref, err_msg=k)
+    Pt, P, q, A, l, u = random_problem(2, 3000, 5000, 0.03)
+    rc, msg, o = run(exe, str(tmp_path), Pt, q, A, l, u, threads=threads)
+    assert rc == 0, msg
+    Ar = sp.csr_matrix(A)
+    Ar.sort_indices()
+    np.testing.assert_array_equal(o["a_col"], Ar.indices)
+    np.testing.assert_array_equal(o["a_val"], Ar.data)
